@@ -1,0 +1,171 @@
+/*
+ * tc.h - C ABI of the MI355X triangle-counting library (libtc.so).
+ *
+ * Method: exact triangle counting as matching of a triangle query Q against an
+ * undirected data graph G (Wang & Owens, "Fast BFS-Based Triangle Counting on
+ * GPUs", Sec. II-A problem definition, Def. 1-2; Sec. III-A, Alg. 1).
+ *
+ *   tc_build_csr         input cleaning: pairs -> symmetric, deduplicated,
+ *                        self-loop-free CSR with ascending rows (Sec. II-A: the
+ *                        graphs are undirected and unlabeled; Sec. III-B: CSR).
+ *   tc_orient            unique mapping order (Alg. 1 "Generate_UMO", Sec. III-A
+ *                        NEC ordering): keep each undirected edge once, from the
+ *                        lower-ranked to the higher-ranked endpoint.
+ *   tc_count             all-source advance over the oriented graph (Alg. 1
+ *                        "Advance", Sec. III-B) enumerating wedges u->v->w, the
+ *                        filter that keeps wedges closed by the stored non-tree
+ *                        edge (u,w) (Alg. 1 "Store_none_tree_connection"), and
+ *                        the reduction to |M|/|Q| (Alg. 1 return value).
+ *   tc_count_per_vertex  the same, plus t(v) = number of triangles containing v.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers on the current HIP device, owned
+ *    by the caller.  The library never allocates device memory: each entry
+ *    point that needs scratch memory takes a caller-owned workspace.
+ *  - Workspace protocol: call with ws == NULL to receive the required size in
+ *    *ws_bytes (TC_OK, nothing is launched).  Call again with ws pointing to at
+ *    least that many bytes (256-byte aligned) and *ws_bytes set to its size;
+ *    a smaller *ws_bytes returns TC_ERR_WORKSPACE.
+ *  - stream is a hipStream_t passed as void* (NULL = the default stream).  Work
+ *    is enqueued asynchronously; no entry point synchronises the host.
+ *  - Errors that can be seen from the host (bad sizes, null pointers, short
+ *    workspace) are returned immediately and nothing is launched.  Errors that
+ *    only the device can see (an out-of-range vertex id, an output capacity too
+ *    small) are reported through the device-side size output of the call
+ *    (nnz_out / m_out), which then holds -status; the CSR written in that case
+ *    is the empty graph (all offsets 0), so later calls stay memory-safe.
+ *  - Vertex ids are 0-based int32 in [0, n), n < 2^31.  Row offsets are int32
+ *    or int64 (offset_bytes = 4 or 8); column indices are int32.
+ *  - A CSR passed to tc_orient / tc_count must be well formed: row_ptr[0] = 0,
+ *    non-decreasing, every column id in [0, n), rows strictly ascending.  The
+ *    outputs of tc_build_csr and tc_orient are.  Malformed input is undefined
+ *    behaviour (it may read out of bounds).
+ *  - Counts are exact unsigned 64-bit integers.  Distinct streams may run calls
+ *    concurrently as long as they use distinct workspaces and outputs.
+ *  - tc_last_error() returns a thread-local message for the last non-OK status.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tc_status;
+
+#define TC_OK 0
+#define TC_ERR_INVALID_ARG 1      /* bad size, null pointer, unknown option */
+#define TC_ERR_ID_OUT_OF_RANGE 2  /* an input pair holds an id outside [0, n) */
+#define TC_ERR_CAPACITY 3         /* an output array is too small */
+#define TC_ERR_WORKSPACE 4        /* *ws_bytes is below the required size */
+#define TC_ERR_HIP 5              /* a HIP runtime call or kernel launch failed */
+#define TC_ERR_UNSUPPORTED 6      /* n >= 2^31, or int32 offsets too narrow */
+
+#define TC_ORDER_DEGREE 0 /* rank(v) = (deg(v), v) lexicographic: the default */
+#define TC_ORDER_ID 1     /* rank(v) = v: the paper's "destination id larger than source id" */
+
+/* Read-only view of a CSR graph in device memory. */
+typedef struct tc_csr {
+  int64_t n;            /* number of vertices; ids are in [0, n) */
+  int32_t offset_bytes; /* 4: row_ptr is int32_t[n+1]; 8: row_ptr is int64_t[n+1] */
+  const void* row_ptr;  /* device; row_ptr[n] is the number of stored entries */
+  const int32_t* col;   /* device; row_ptr[n] column ids, each row ascending */
+} tc_csr;
+
+/*
+ * tc_build_csr - clean an undirected edge list into a symmetric CSR.
+ *
+ * Follows the problem statement (Sec. II-A): G is undirected, so (u,v) and
+ * (v,u) are one edge; it has no labels or weights.  Self-loops cannot be part
+ * of a triangle match under an injective mapping (Def. 2) and are dropped.
+ *
+ *   n            vertices, 0 <= n < 2^31
+ *   num_pairs    number of input pairs (>= 0)
+ *   src, dst     device int32[num_pairs]; pair i is {src[i], dst[i]}.
+ *                Duplicates, both directions and self-loops are allowed.
+ *   offset_bytes 4 or 8: width of row_ptr.  4 requires 2*num_pairs < 2^31.
+ *   row_ptr      device, (n+1) offsets of width offset_bytes (written)
+ *   col          device int32[col_capacity] (written): for every vertex u its
+ *                distinct neighbours v != u in ascending order
+ *   col_capacity entries available in col; the result needs 2m entries
+ *                (m = distinct undirected non-loop edges <= num_pairs)
+ *   nnz_out      device int64[1] (written): 2m, or -TC_ERR_ID_OUT_OF_RANGE if
+ *                an id lies outside [0, n), or -TC_ERR_CAPACITY if 2m >
+ *                col_capacity; on either error row_ptr is all zeros.
+ *   ws, ws_bytes workspace (see protocol above); O(num_pairs + n) bytes.
+ */
+tc_status tc_build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst,
+                       int32_t offset_bytes, void* row_ptr, int32_t* col, int64_t col_capacity,
+                       int64_t* nnz_out, void* ws, size_t* ws_bytes, void* stream);
+
+/*
+ * tc_orient - keep each undirected edge once, oriented by a strict total order.
+ *
+ * The paper's unique mapping order (Alg. 1 "Generate_UMO"; Sec. III-A, NEC
+ * ordering u1 < u2 < u3) visits equivalent query nodes in increasing order so
+ * each triangle is matched once.  Any strict total order has that property;
+ * TC_ORDER_DEGREE ranks by (degree, id), which bounds every out-degree by
+ * O(sqrt(m)); TC_ORDER_ID is the paper's id order.
+ *
+ *   sym          symmetric CSR (as written by tc_build_csr)
+ *   order        TC_ORDER_DEGREE or TC_ORDER_ID
+ *   dag_row_ptr  device, (n+1) offsets of width sym->offset_bytes (written)
+ *   dag_col      device int32[dag_col_capacity] (written): for each u the v with
+ *                rank(u) < rank(v), ascending by id (a subsequence of u's row)
+ *   dag_col_capacity  entries available in dag_col; m = row_ptr[n]/2 are needed
+ *   m_out        device int64[1] (written): m, or -TC_ERR_CAPACITY (then
+ *                dag_row_ptr is all zeros)
+ *   ws, ws_bytes workspace; O(n) bytes.
+ */
+tc_status tc_orient(const tc_csr* sym, int32_t order, void* dag_row_ptr, int32_t* dag_col,
+                    int64_t dag_col_capacity, int64_t* m_out, void* ws, size_t* ws_bytes,
+                    void* stream);
+
+/*
+ * tc_count - number of triangles T of the oriented graph (Alg. 1 return value
+ * |M|/|Q|: each triangle is matched exactly once under the orientation).
+ *
+ * For every source u (all-source traversal, Sec. III), every v in N+(u) and
+ * every w in N+(v), the wedge u->v->w is a match iff w is in N+(u).  Sources
+ * with out-degree < 2 and middles with out-degree 0 cannot complete a match
+ * and are pruned (the 1- and 2-look-ahead of Sec. III-C).
+ *
+ *   dag      oriented CSR (as written by tc_orient; any DAG works)
+ *   total    device uint64[1] (written, not accumulated)
+ *   ws, ws_bytes  workspace; O(n) bytes.
+ */
+tc_status tc_count(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_bytes, void* stream);
+
+/*
+ * tc_count_per_vertex - per-vertex triangle counts t(v) and the total.
+ *
+ * t(v) is the number of triangles that contain v; sum_v t(v) = 3T.  The paper
+ * outputs the listing M of matched node sequences (Sec. II-A, Alg. 1); t(v) is
+ * the number of times v appears in M.
+ *
+ *   dag         oriented CSR
+ *   per_vertex  device uint64[dag->n] (written, not accumulated)
+ *   total       device uint64[1] or NULL (written when non-NULL)
+ *   ws, ws_bytes  workspace; O(n) bytes.
+ */
+tc_status tc_count_per_vertex(const tc_csr* dag, uint64_t* per_vertex, uint64_t* total, void* ws,
+                              size_t* ws_bytes, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* tc_status_string(tc_status status);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* tc_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t tc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

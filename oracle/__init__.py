@@ -1,0 +1,145 @@
+"""CPU oracle for exact triangle counting (ctypes wrapper over ``tc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The library's product
+path never calls it, and it imports nothing from the product package.
+
+Each function follows a definition of Wang & Owens, "Fast BFS-Based Triangle
+Counting on GPUs" (problem definition Sec. II-A, Def. 1-2; Alg. 1 unique mapping
+order and non-tree-edge check); the C source states which one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "tc_oracle.c"
+_LIB = _HERE / "liboracle.so"
+
+ORDER_DEGREE = 0
+ORDER_ID = 1
+ORDER_KEY = 2
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle with gcc (plain C99 + OpenMP, no target-specific flags)."""
+    if force or not _LIB.exists():
+        tmp = _LIB.with_suffix(".so.tmp")
+        subprocess.run(["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared", str(_SRC),
+                        "-o", str(tmp)], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not _LIB.exists():
+            build(force=True)
+        lib = ctypes.CDLL(str(_LIB))
+        i64, i32, p = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        lib.oracle_clean.restype = i64
+        lib.oracle_clean.argtypes = [i64, i64, p, p, p, p, i64]
+        lib.oracle_orient.restype = i64
+        lib.oracle_orient.argtypes = [i64, p, p, i32, p, p, p]
+        lib.oracle_count.restype = ctypes.c_uint64
+        lib.oracle_count.argtypes = [i64, p, p, p, i32]
+        lib.oracle_vertex_triangles.restype = i64
+        lib.oracle_vertex_triangles.argtypes = [i64, i64, p, p, i32]
+        lib.oracle_max_threads.restype = i32
+        lib.oracle_max_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+
+
+class OracleError(ValueError):
+    pass
+
+
+def clean(n: int, src, dst) -> tuple[np.ndarray, np.ndarray]:
+    """Raw pairs -> symmetric deduplicated self-loop-free CSR (row_ptr int64, col int32)."""
+    lib = _load()
+    src, dst = _i32(src), _i32(dst)
+    if src.shape != dst.shape:
+        raise OracleError("src and dst differ in length")
+    p = src.size
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(max(2 * p, 1), dtype=np.int32)
+    nnz = lib.oracle_clean(n, p, _ptr(src), _ptr(dst), _ptr(row_ptr), _ptr(col), col.size)
+    if nnz == -2:
+        raise OracleError("vertex id outside [0, n)")
+    if nnz < 0:
+        raise OracleError(f"oracle_clean failed ({nnz})")
+    return row_ptr, col[:nnz].copy()
+
+
+def orient(row_ptr: np.ndarray, col: np.ndarray, order: int = ORDER_DEGREE,
+           key: np.ndarray | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """Keep (u, v) iff rank(u) < rank(v); rank = (degree, id), id, or (key, id)."""
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = _i32(col)
+    n = row_ptr.size - 1
+    if order == ORDER_KEY:
+        if key is None or key.size != n:
+            raise OracleError("ORDER_KEY needs a key per vertex")
+        key = np.ascontiguousarray(key, dtype=np.int64)
+    else:
+        key = None
+    dag_ptr = np.zeros(n + 1, dtype=np.int64)
+    dag_col = np.zeros(max(col.size // 2, 1), dtype=np.int32)
+    m = lib.oracle_orient(n, _ptr(row_ptr), _ptr(col), order, _ptr(key), _ptr(dag_ptr),
+                          _ptr(dag_col))
+    return dag_ptr, dag_col[:m].copy()
+
+
+def count(dag_ptr: np.ndarray, dag_col: np.ndarray, *, per_vertex: bool = False,
+          threads: int = 0):
+    """Triangles of an oriented graph; with per_vertex, also t(v) as uint64[n]."""
+    lib = _load()
+    dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
+    dag_col = _i32(dag_col)
+    n = dag_ptr.size - 1
+    t = np.zeros(max(n, 1), dtype=np.uint64) if per_vertex else None
+    total = int(lib.oracle_count(n, _ptr(dag_ptr), _ptr(dag_col), _ptr(t), threads))
+    if per_vertex:
+        return total, t[:n].copy()
+    return total
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def vertex_triangles(n: int, src, dst, v: int) -> int:
+    """t(v) straight from the raw pairs: distinct edges among the neighbours of v."""
+    lib = _load()
+    src, dst = _i32(src), _i32(dst)
+    r = lib.oracle_vertex_triangles(n, src.size, _ptr(src), _ptr(dst), int(v))
+    if r < 0:
+        raise OracleError("oracle_vertex_triangles failed")
+    return int(r)
+
+
+def triangles(n: int, src, dst, *, per_vertex: bool = False, order: int = ORDER_DEGREE,
+              threads: int = 0):
+    """Whole pipeline from raw pairs: clean -> orient -> count."""
+    row_ptr, col = clean(n, src, dst)
+    dag_ptr, dag_col = orient(row_ptr, col, order)
+    return count(dag_ptr, dag_col, per_vertex=per_vertex, threads=threads)

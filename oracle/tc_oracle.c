@@ -1,0 +1,233 @@
+/*
+ * tc_oracle.c - CPU oracle for exact triangle counting.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library's product path may call,
+ * link or load this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code with the GPU path.
+ *
+ * It is deliberately plain and slow: every function follows a definition from
+ * Wang & Owens, "Fast BFS-Based Triangle Counting on GPUs", written out.
+ *
+ *  - oracle_clean: Sec. II-A (problem definition) says both graphs are
+ *    undirected with no labels or weights, so (u,v) and (v,u) are one edge.
+ *    Def. 2 maps query nodes injectively, so a self-loop can never be part of a
+ *    triangle match and is dropped.  The result is E = {{u,v} : u != v} as a
+ *    symmetric CSR with ascending rows (Sec. III-B stores graphs as CSR).
+ *  - oracle_orient: the unique mapping order of Alg. 1 ("Generate_UMO") and of
+ *    Sec. III-A (the triangle is one neighbourhood-equivalence class; visit its
+ *    nodes in increasing order u1 < u2 < u3).  Each undirected edge is kept
+ *    once, from the lower to the higher rank, for a strict total order "rank".
+ *  - oracle_count: the wedge u -> v -> w of the oriented graph is a match iff
+ *    the non-tree query edge (u1, u3) is present (Alg. 1
+ *    "Store_none_tree_connection"), i.e. w is also an out-neighbour of u.  With
+ *    rank(u) < rank(v) < rank(w) forced by the orientation, every triangle
+ *    {a,b,c} of G is found exactly once, so the count is |M|/|Q| of Alg. 1.
+ *    Found by merging the two sorted out-neighbour lists (node iterator).
+ *    Per-vertex counts t(x) = number of triangles containing x.
+ *  - oracle_vertex_triangles: t(v) by its definition straight from the raw
+ *    input pairs: the number of distinct edges among the neighbours of v.
+ *
+ * Every function is pinned by the CPU test suite against brute force over
+ * vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms and invariants.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/*
+ * Clean num_pairs raw pairs into a symmetric CSR.
+ * row_ptr: int64[n+1]; col: int32[cap].
+ * Returns 2m (number of stored entries), -2 if an id is outside [0, n),
+ * -3 if 2m > cap, -1 on allocation failure.
+ */
+int64_t oracle_clean(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst,
+                     int64_t* row_ptr, int32_t* col, int64_t cap) {
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return -2;
+  }
+  /* one key per unordered pair {a, b}, a < b; self-loops are not edges */
+  uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(num_pairs > 0 ? num_pairs : 1));
+  if (!keys) return -1;
+  int64_t k = 0;
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    int64_t a = src[i], b = dst[i];
+    if (a == b) continue;
+    if (a > b) { int64_t t = a; a = b; b = t; }
+    keys[k++] = ((uint64_t)a << 32) | (uint64_t)b;
+  }
+  qsort(keys, (size_t)k, sizeof(uint64_t), cmp_u64);
+  int64_t m = 0;
+  for (int64_t i = 0; i < k; ++i) {
+    if (i == 0 || keys[i] != keys[i - 1]) keys[m++] = keys[i];
+  }
+  if (2 * m > cap) { free(keys); return -3; }
+  /* degree of every vertex, then offsets */
+  for (int64_t v = 0; v <= n; ++v) row_ptr[v] = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    row_ptr[(keys[i] >> 32) + 1] += 1;
+    row_ptr[(keys[i] & 0xFFFFFFFFu) + 1] += 1;
+  }
+  for (int64_t v = 0; v < n; ++v) row_ptr[v + 1] += row_ptr[v];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!fill) { free(keys); return -1; }
+  for (int64_t v = 0; v < n; ++v) fill[v] = row_ptr[v];
+  for (int64_t i = 0; i < m; ++i) {
+    int32_t a = (int32_t)(keys[i] >> 32), b = (int32_t)(keys[i] & 0xFFFFFFFFu);
+    col[fill[a]++] = b;
+    col[fill[b]++] = a;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    qsort(col + row_ptr[v], (size_t)(row_ptr[v + 1] - row_ptr[v]), sizeof(int32_t), cmp_i32);
+  }
+  free(fill);
+  free(keys);
+  return 2 * m;
+}
+
+/*
+ * rank(u) < rank(v) for the strict total order selected by `order`:
+ *   0: (degree, id)   1: id   2: (key[v], id) for a caller-supplied key array.
+ */
+static int rank_less(int32_t order, const int64_t* row_ptr, const int64_t* key, int64_t u,
+                     int64_t v) {
+  int64_t ku = 0, kv = 0;
+  if (order == 0) {
+    ku = row_ptr[u + 1] - row_ptr[u];
+    kv = row_ptr[v + 1] - row_ptr[v];
+  } else if (order == 2) {
+    ku = key[u];
+    kv = key[v];
+  }
+  if (ku != kv) return ku < kv;
+  return u < v;
+}
+
+/*
+ * Orient a symmetric CSR: keep entry (u, v) iff rank(u) < rank(v).
+ * dag_ptr: int64[n+1]; dag_col: int32[row_ptr[n] / 2].  Rows stay ascending
+ * by id (a subsequence of the symmetric row).  Returns m, the kept entries.
+ */
+int64_t oracle_orient(int64_t n, const int64_t* row_ptr, const int32_t* col, int32_t order,
+                      const int64_t* key, int64_t* dag_ptr, int32_t* dag_col) {
+  int64_t m = 0;
+  dag_ptr[0] = 0;
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      if (rank_less(order, row_ptr, key, u, col[e])) dag_col[m++] = col[e];
+    }
+    dag_ptr[u + 1] = m;
+  }
+  return m;
+}
+
+/*
+ * Count triangles of an oriented graph (rows ascending by id).
+ * For each source u and each v in N+(u), every w common to N+(u) and N+(v)
+ * closes the wedge u -> v -> w: one triangle {u, v, w}.
+ * t (nullable): uint64[n], set to the per-vertex counts.
+ * threads <= 0 uses the OpenMP default.
+ */
+uint64_t oracle_count(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col, uint64_t* t,
+                      int32_t threads) {
+  uint64_t total = 0;
+  if (t) memset(t, 0, sizeof(uint64_t) * (size_t)n);
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#else
+  (void)threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total)
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
+      int64_t v = dag_col[e];
+      int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];
+      int64_t j = dag_ptr[v], jend = dag_ptr[v + 1];
+      uint64_t found = 0;
+      while (i < iend && j < jend) {
+        int32_t a = dag_col[i], b = dag_col[j];
+        if (a < b) {
+          ++i;
+        } else if (b < a) {
+          ++j;
+        } else {
+          ++found;
+          if (t) {
+#pragma omp atomic
+            t[a] += 1;
+          }
+          ++i;
+          ++j;
+        }
+      }
+      total += found;
+      if (t && found) {
+#pragma omp atomic
+        t[u] += found;
+#pragma omp atomic
+        t[v] += found;
+      }
+    }
+  }
+  return total;
+}
+
+/* Threads an OpenMP parallel region of oracle_count would use. */
+int32_t oracle_max_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/*
+ * t(v) from the raw pairs, by definition: the number of distinct edges {a, b}
+ * (a != b) with both a and b adjacent to v.  Returns -1 on a bad argument.
+ */
+int64_t oracle_vertex_triangles(int64_t n, int64_t num_pairs, const int32_t* src,
+                                const int32_t* dst, int32_t v) {
+  if (v < 0 || v >= n) return -1;
+  unsigned char* nbr = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!nbr) return -1;
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    if (src[i] == v && dst[i] != v) nbr[dst[i]] = 1;
+    if (dst[i] == v && src[i] != v) nbr[src[i]] = 1;
+  }
+  int64_t cap = 1024, k = 0;
+  uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)cap);
+  if (!keys) { free(nbr); return -1; }
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    int64_t a = src[i], b = dst[i];
+    if (a == b || !nbr[a] || !nbr[b]) continue;
+    if (a > b) { int64_t t = a; a = b; b = t; }
+    if (k == cap) {
+      cap *= 2;
+      uint64_t* grown = (uint64_t*)realloc(keys, sizeof(uint64_t) * (size_t)cap);
+      if (!grown) { free(keys); free(nbr); return -1; }
+      keys = grown;
+    }
+    keys[k++] = ((uint64_t)a << 32) | (uint64_t)b;
+  }
+  qsort(keys, (size_t)k, sizeof(uint64_t), cmp_u64);
+  int64_t distinct = 0;
+  for (int64_t i = 0; i < k; ++i) {
+    if (i == 0 || keys[i] != keys[i - 1]) ++distinct;
+  }
+  free(keys);
+  free(nbr);
+  return distinct;
+}

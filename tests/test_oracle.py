@@ -1,0 +1,202 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against results that do not come from itself:
+brute force over vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms of
+graph families, invariants of the definition, and the golden fixtures.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import goldens, pins
+
+
+def _run(n, s, d, order=oracle.ORDER_DEGREE):
+    return oracle.triangles(n, s, d, per_vertex=True, order=order)
+
+
+@pytest.mark.parametrize("case", pins.closed_form_cases(), ids=lambda c: c[0])
+def test_closed_forms(case):
+    name, (n, s, d), T, t = case
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        total, per = _run(n, s, d, order)
+        assert total == T, name
+        assert int(per.sum()) == 3 * T
+        if t is not None:
+            np.testing.assert_array_equal(per, t)
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_brute_force_random_tiny(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 33))
+    p = float(rng.choice([0.05, 0.15, 0.3, 0.5, 0.8, 1.0]))
+    n, s, d = pins.random_simple(n, p, seed)
+    bt, bper = pins.brute_force(n, s, d)
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        total, per = _run(n, s, d, order)
+        assert total == bt
+        np.testing.assert_array_equal(per, bper)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_brute_force_noisy_input(seed):
+    """Duplicates, reversed pairs and self-loops do not change the counts."""
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(2, 28))
+    n, s, d = pins.random_simple(n, float(rng.uniform(0.1, 0.9)), seed)
+    bt, bper = pins.brute_force(n, s, d)
+    n, s2, d2 = pins.noisy(n, s, d, seed)
+    total, per = _run(n, s2, d2)
+    assert total == bt
+    np.testing.assert_array_equal(per, bper)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_trace_a3_config1(seed):
+    """G(1024, 8192), the small configuration itself, against trace(A^3)/6."""
+    s, d, n = graphgen.erdos_renyi(1024, 8192, seed)
+    tt, tper = pins.trace_cube(n, s.numpy(), d.numpy())
+    total, per = _run(n, s.numpy(), d.numpy())
+    assert total == tt
+    np.testing.assert_array_equal(per, tper)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_trace_a3_small_rmat(seed):
+    """Skewed R-MAT graphs (hubs, duplicates, self-loops in the raw pairs)."""
+    s, d, n = graphgen.rmat(9, 8, 300 + seed)
+    tt, tper = pins.trace_cube(n, s.numpy(), d.numpy())
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        total, per = _run(n, s.numpy(), d.numpy(), order)
+        assert total == tt
+        np.testing.assert_array_equal(per, tper)
+
+
+def test_clean_matches_set_definition():
+    for seed in range(30):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(1, 40))
+        p = int(rng.integers(0, 120))
+        s = rng.integers(0, n, p)
+        d = rng.integers(0, n, p)
+        row_ptr, col = oracle.clean(n, s, d)
+        E = pins.edge_set(s, d)
+        want = [sorted({b for e in E if a in e for b in e if b != a}) for a in range(n)]
+        assert row_ptr[0] == 0 and row_ptr[-1] == 2 * len(E)
+        for a in range(n):
+            assert list(col[row_ptr[a]:row_ptr[a + 1]]) == want[a]
+
+
+def test_clean_rejects_out_of_range():
+    with pytest.raises(oracle.OracleError):
+        oracle.clean(4, [0, 1], [2, 4])
+    with pytest.raises(oracle.OracleError):
+        oracle.clean(4, [-1], [2])
+
+
+def test_orient_matches_definition():
+    for seed in range(20):
+        rng = np.random.default_rng(50 + seed)
+        n, s, d = pins.random_simple(int(rng.integers(2, 30)), 0.4, seed)
+        row_ptr, col = oracle.clean(n, s, d)
+        deg = np.diff(row_ptr)
+        key = rng.integers(0, 5, n)
+        for order, rank in [(oracle.ORDER_DEGREE, lambda v: (deg[v], v)),
+                            (oracle.ORDER_ID, lambda v: v),
+                            (oracle.ORDER_KEY, lambda v: (key[v], v))]:
+            dp, dc = oracle.orient(row_ptr, col, order, key)
+            assert dp[-1] == row_ptr[-1] // 2
+            for u in range(n):
+                nbrs = col[row_ptr[u]:row_ptr[u + 1]]
+                want = [v for v in nbrs if rank(u) < rank(v)]
+                assert list(dc[dp[u]:dp[u + 1]]) == want
+
+
+def test_orientation_order_invariance():
+    s, d, n = graphgen.rmat(11, 8, 5)
+    row_ptr, col = oracle.clean(n, s.numpy(), d.numpy())
+    results = []
+    rng = np.random.default_rng(3)
+    for order, key in [(oracle.ORDER_DEGREE, None), (oracle.ORDER_ID, None),
+                       (oracle.ORDER_KEY, rng.integers(0, 1 << 40, n))]:
+        dp, dc = oracle.orient(row_ptr, col, order, key)
+        results.append(oracle.count(dp, dc, per_vertex=True))
+    for total, per in results[1:]:
+        assert total == results[0][0]
+        np.testing.assert_array_equal(per, results[0][1])
+    assert int(results[0][1].sum()) == 3 * results[0][0]
+
+
+def test_relabel_invariance():
+    s, d, n = graphgen.rmat(10, 8, 9)
+    s, d = s.numpy(), d.numpy()
+    total, per = _run(n, s, d)
+    perm = np.random.default_rng(1).permutation(n)
+    total2, per2 = _run(n, perm[s], perm[d])
+    assert total2 == total
+    np.testing.assert_array_equal(per2[perm], per)
+
+
+def test_disjoint_union_additive():
+    parts = [pins.complete(7), pins.wheel(6), pins.petersen(), pins.friendship(4)]
+    s_all, d_all, off, T, pers = [], [], 0, 0, []
+    for n, s, d in parts:
+        s_all += [x + off for x in s]
+        d_all += [x + off for x in d]
+        off += n
+        t, p = _run(n, s, d)
+        T += t
+        pers.append(p)
+    total, per = _run(off, s_all, d_all)
+    assert total == T
+    np.testing.assert_array_equal(per, np.concatenate(pers))
+
+
+def test_vertex_triangles_definition():
+    for seed in range(15):
+        rng = np.random.default_rng(900 + seed)
+        n, s, d = pins.random_simple(int(rng.integers(3, 30)), 0.35, seed)
+        n, s, d = pins.noisy(n, s, d, seed)
+        _, bper = pins.brute_force(n, s, d)
+        for v in range(n):
+            assert oracle.vertex_triangles(n, s, d, v) == int(bper[v])
+
+
+def test_threads_do_not_change_counts():
+    s, d, n = graphgen.rmat(12, 16, 77)
+    rp, c = oracle.clean(n, s.numpy(), d.numpy())
+    dp, dc = oracle.orient(rp, c)
+    a = oracle.count(dp, dc, per_vertex=True, threads=1)
+    b = oracle.count(dp, dc, per_vertex=True, threads=4)
+    assert a[0] == b[0]
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("fx", goldens.all_fixtures(), ids=lambda f: f.name)
+def test_golden_fixtures(fx):
+    """Hand-checked graphs, each with the closed form or fact that fixes its counts."""
+    assert int(fx.per_vertex.sum()) == 3 * fx.triangles  # the fixture itself is consistent
+    bt, bper = pins.brute_force(fx.n, fx.src, fx.dst)
+    assert bt == fx.triangles
+    np.testing.assert_array_equal(bper, fx.per_vertex)
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        total, per = _run(fx.n, fx.src, fx.dst, order)
+        assert total == fx.triangles
+        np.testing.assert_array_equal(per, fx.per_vertex)
+
+
+def test_golden_config1_counts_pinned_by_trace():
+    """The stored G(1024, 8192) counts agree with trace(A^3)/6 recomputed here."""
+    import json
+    import os
+    with open(os.path.join(goldens.GOLDEN_DIR, "er1024_8192.json")) as f:
+        data = json.load(f)
+    for seed, g in data["graphs"].items():
+        s, d, n = graphgen.erdos_renyi(1024, 8192, int(seed))
+        tt, tper = pins.trace_cube(n, s.numpy(), d.numpy())
+        assert g["triangles"] == tt
+        np.testing.assert_array_equal(np.array(g["per_vertex"], dtype=np.uint64), tper)
