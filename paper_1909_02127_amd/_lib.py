@@ -1,0 +1,165 @@
+"""ctypes binding of libtc.so: the C ABI entry points under their own names.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Torch tensors supply device memory and torch's current stream supplies
+the HIP stream.  There is no fallback: if libtc.so is missing, importing this
+module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import torch
+
+_LIB_PATH = Path(__file__).resolve().parent / "libtc.so"
+
+TC_OK = 0
+TC_ERR_INVALID_ARG = 1
+TC_ERR_ID_OUT_OF_RANGE = 2
+TC_ERR_CAPACITY = 3
+TC_ERR_WORKSPACE = 4
+TC_ERR_HIP = 5
+TC_ERR_UNSUPPORTED = 6
+
+TC_ORDER_DEGREE = 0
+TC_ORDER_ID = 1
+
+
+class TcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+class tc_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("offset_bytes", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not _LIB_PATH.exists():
+        raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python -m paper_1909_02127_amd.build)")
+    lib = ctypes.CDLL(str(_LIB_PATH))
+    i64, i32, p, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)
+    csr = ctypes.POINTER(tc_csr)
+    lib.tc_build_csr.restype = i32
+    lib.tc_build_csr.argtypes = [i64, i64, p, p, i32, p, p, i64, p, p, sz, p]
+    lib.tc_orient.restype = i32
+    lib.tc_orient.argtypes = [csr, i32, p, p, i64, p, p, sz, p]
+    lib.tc_count.restype = i32
+    lib.tc_count.argtypes = [csr, p, p, sz, p]
+    lib.tc_count_per_vertex.restype = i32
+    lib.tc_count_per_vertex.argtypes = [csr, p, p, p, sz, p]
+    lib.tc_status_string.restype = ctypes.c_char_p
+    lib.tc_status_string.argtypes = [i32]
+    lib.tc_last_error.restype = ctypes.c_char_p
+    lib.tc_last_error.argtypes = []
+    lib.tc_version.restype = i32
+    lib.tc_version.argtypes = []
+    return lib
+
+
+LIB = _load()
+LIB_PATH = str(_LIB_PATH)
+
+
+def status_string(status: int) -> str:
+    return LIB.tc_status_string(status).decode()
+
+
+def _check(status: int) -> None:
+    if status != TC_OK:
+        raise TcError(status, LIB.tc_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libtc must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_csr(n: int, row_ptr: torch.Tensor, col: torch.Tensor) -> tc_csr:
+    if row_ptr.dtype not in (torch.int32, torch.int64) or col.dtype != torch.int32:
+        raise ValueError("row_ptr must be int32/int64 and col int32")
+    return tc_csr(n, row_ptr.element_size(), _ptr(row_ptr), _ptr(col))
+
+
+def _ws_query(fn, *args) -> int:
+    size = ctypes.c_size_t(0)
+    _check(fn(*args, None, ctypes.byref(size), None))
+    return int(size.value)
+
+
+def _ws_call(fn, ws: torch.Tensor, *args, stream=None) -> None:
+    size = ctypes.c_size_t(ws.numel() * ws.element_size())
+    _check(fn(*args, _ptr(ws), ctypes.byref(size), _stream(stream)))
+
+
+# ---- the C ABI, one function each ---------------------------------------------
+
+def tc_build_csr_workspace(n: int, num_pairs: int, offset_bytes: int = 4) -> int:
+    return _ws_query(LIB.tc_build_csr, n, num_pairs, None, None, offset_bytes, None, None, 0, None)
+
+
+def tc_build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, row_ptr: torch.Tensor,
+                 col: torch.Tensor, nnz_out: torch.Tensor, ws: torch.Tensor, *, stream=None) -> None:
+    if src.dtype != torch.int32 or dst.dtype != torch.int32 or src.numel() != dst.numel():
+        raise ValueError("src and dst must be int32 tensors of equal length")
+    if nnz_out.dtype != torch.int64 or row_ptr.numel() != n + 1:
+        raise ValueError("nnz_out must be int64[1] and row_ptr must hold n+1 offsets")
+    _ws_call(LIB.tc_build_csr, ws, n, src.numel(), _ptr(src), _ptr(dst), row_ptr.element_size(),
+             _ptr(row_ptr), _ptr(col), col.numel(), _ptr(nnz_out), stream=stream)
+
+
+def tc_orient_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_orient, ctypes.byref(csr), TC_ORDER_DEGREE, None, None, 0, None)
+
+
+def tc_orient(n: int, row_ptr: torch.Tensor, col: torch.Tensor, order: int,
+              dag_row_ptr: torch.Tensor, dag_col: torch.Tensor, m_out: torch.Tensor,
+              ws: torch.Tensor, *, stream=None) -> None:
+    if dag_row_ptr.dtype != row_ptr.dtype or dag_row_ptr.numel() != n + 1:
+        raise ValueError("dag_row_ptr must match row_ptr's dtype and hold n+1 offsets")
+    csr = make_csr(n, row_ptr, col)
+    _ws_call(LIB.tc_orient, ws, ctypes.byref(csr), order, _ptr(dag_row_ptr), _ptr(dag_col),
+             dag_col.numel(), _ptr(m_out), stream=stream)
+
+
+def tc_count_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_count, ctypes.byref(csr), None)
+
+
+def tc_count(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor, total: torch.Tensor,
+             ws: torch.Tensor, *, stream=None) -> None:
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count, ws, ctypes.byref(csr), _ptr(total), stream=stream)
+
+
+def tc_count_per_vertex_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_count_per_vertex, ctypes.byref(csr), None, None)
+
+
+def tc_count_per_vertex(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                        per_vertex: torch.Tensor, total: torch.Tensor | None, ws: torch.Tensor, *,
+                        stream=None) -> None:
+    if per_vertex.numel() != n:
+        raise ValueError("per_vertex must hold n counts")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count_per_vertex, ws, ctypes.byref(csr), _ptr(per_vertex), _ptr(total),
+             stream=stream)
+
+
+def tc_version() -> int:
+    return int(LIB.tc_version())

@@ -1,0 +1,311 @@
+// build_csr.hip - tc_build_csr: raw pairs -> symmetric, deduplicated, self-loop-free CSR.
+//
+// The problem statement (Sec. II-A) makes G undirected and unlabeled, so (u,v)
+// and (v,u) are one edge; Def. 2's injective mapping leaves self-loops out of
+// every match.  The graph is stored as CSR (Sec. III-B).
+//
+// Device pipeline (all on the caller's stream, no host synchronisation):
+//   1. make_keys: each pair {a,b}, a != b, emits the packed keys (a<<cb | b) and
+//      (b<<cb | a), cb = bits of an id; self-loops and bad pairs emit a sentinel
+//      that sorts last; an out-of-range id raises a device error flag.
+//   2. LSD radix sort of the 2*num_pairs keys over their 2*cb significant bits,
+//      8 bits per pass: per-tile digit histograms, one scan over the
+//      digit-major histogram table, and a stable scatter whose in-tile ranks
+//      come from 8 wave ballots per key.
+//   3. One scan over "first of its run" flags drops duplicates and sentinels,
+//      writes col, and records the first position of every non-empty row.
+//   4. A suffix-minimum scan turns the row starts into row_ptr (empty rows take
+//      the next row's start), in int32 or int64 offsets.
+//   5. A finalize step reports 2m, or -status with an all-zero row_ptr.
+#include "tc_device.h"
+#include "tc_host.h"
+#include "tc_scan.h"
+
+namespace tc {
+namespace {
+
+constexpr int kRadixBlock = 256;
+constexpr int kRadixItems = 16;
+constexpr int64_t kRadixTile = (int64_t)kRadixBlock * kRadixItems;
+constexpr uint64_t kSentinel = ~0ull;
+
+int id_bits(int64_t n) {
+  int b = 1;
+  while (b < 31 && ((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+__global__ __launch_bounds__(256) void make_keys_kernel(int64_t n, int64_t num_pairs,
+                                                        const int32_t* __restrict__ src,
+                                                        const int32_t* __restrict__ dst, int cb,
+                                                        uint64_t* __restrict__ keys,
+                                                        int32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < num_pairs; i += stride) {
+    int64_t a = src[i], b = dst[i];
+    uint64_t k0 = kSentinel, k1 = kSentinel;
+    if (a < 0 || a >= n || b < 0 || b >= n) {
+      bad = true;
+    } else if (a != b) {
+      k0 = ((uint64_t)a << cb) | (uint64_t)b;
+      k1 = ((uint64_t)b << cb) | (uint64_t)a;
+    }
+    keys[2 * i] = k0;
+    keys[2 * i + 1] = k1;
+  }
+  if (ballot(bad) != 0 && lane_id() == 0) atomicOr(err, 1);
+}
+
+__global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t* __restrict__ keys,
+                                                                 int64_t nk, int shift,
+                                                                 uint32_t mask,
+                                                                 uint32_t* __restrict__ hist,
+                                                                 int64_t num_tiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll 4
+  for (int r = 0; r < kRadixItems; ++r) {
+    int64_t i = base + (int64_t)r * kRadixBlock + threadIdx.x;
+    if (i < nk) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile: keys of equal digit keep their input order.
+__global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
+    const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int64_t nk, int shift, int bits,
+    const uint32_t* __restrict__ offsets, int64_t num_tiles) {
+  __shared__ uint32_t base_s[256];
+  __shared__ uint32_t wcnt[kRadixBlock / kWave][256];
+  const int t = threadIdx.x;
+  const int wave = t / kWave;
+  const uint32_t mask = (1u << bits) - 1u;
+  base_s[t] = offsets[(int64_t)t * num_tiles + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < kRadixBlock / kWave; ++w) wcnt[w][t] = 0;
+  __syncthreads();
+  const int64_t tile = (int64_t)blockIdx.x * kRadixTile;
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t i = tile + (int64_t)r * kRadixBlock + t;
+    const bool valid = i < nk;
+    const uint64_t k = valid ? in[i] : 0;
+    const uint32_t d = (uint32_t)(k >> shift) & mask;
+    uint64_t peers = ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = rank_below(peers);
+    if (valid && rank == 0) wcnt[wave][d] = popc(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base_s[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      out[pos] = k;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kRadixBlock / kWave; ++w) {
+      add += wcnt[w][t];
+      wcnt[w][t] = 0;
+    }
+    base_s[t] += add;
+    __syncthreads();
+  }
+}
+
+struct HistLoad {
+  const uint32_t* hist;
+  __device__ int64_t operator()(int64_t i) const { return hist[i]; }
+};
+struct HistStore {
+  uint32_t* hist;
+  __device__ void operator()(int64_t i, int64_t p) const { hist[i] = (uint32_t)p; }
+};
+
+struct RunFlag {
+  const uint64_t* keys;
+  __device__ __forceinline__ bool operator()(int64_t i) const {
+    const uint64_t k = keys[i];
+    return k != kSentinel && (i == 0 || keys[i - 1] != k);
+  }
+};
+struct DedupLoad {
+  RunFlag flag;
+  __device__ int64_t operator()(int64_t i) const { return flag(i) ? 1 : 0; }
+};
+struct DedupStore {
+  RunFlag flag;
+  int cb;
+  int32_t* col;
+  int64_t cap;
+  int64_t* start;
+  __device__ void operator()(int64_t i, int64_t pos) const {
+    if (!flag(i)) return;
+    const uint64_t k = flag.keys[i];
+    const uint64_t row = k >> cb;
+    if (pos < cap) col[pos] = (int32_t)(k & ((1ull << cb) - 1ull));
+    if (i == 0 || (flag.keys[i - 1] >> cb) != row) start[row] = pos;
+  }
+};
+
+__global__ void fill_i64_kernel(int64_t* p, int64_t len, int64_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = v;
+}
+
+__global__ void clear_i32_kernel(int32_t* p) { *p = 0; }
+
+// start[n] = number of distinct entries (total of the dedup scan).
+__global__ void set_total_kernel(int64_t* start, int64_t n, const int64_t* dedup_total) {
+  start[n] = *dedup_total;
+}
+
+// Row offsets: row_ptr[r] = min(start[r..n]) via an exclusive min-scan over reversed rows.
+struct SuffixLoad {
+  const int64_t* start;
+  int64_t n;
+  __device__ int64_t operator()(int64_t i) const { return start[n - i]; }
+};
+template <typename OffT>
+struct SuffixStore {
+  const int64_t* start;
+  int64_t n;
+  OffT* row_ptr;
+  __device__ void operator()(int64_t i, int64_t exc) const {
+    const int64_t s = start[n - i];
+    row_ptr[n - i] = (OffT)(s < exc ? s : exc);
+  }
+};
+
+__global__ void finalize_kernel(const int32_t* err, const int64_t* total, int64_t cap,
+                                int64_t* nnz_out) {
+  int64_t r = *total;
+  if (*err) r = -(int64_t)TC_ERR_ID_OUT_OF_RANGE;
+  else if (r > cap) r = -(int64_t)TC_ERR_CAPACITY;
+  *nnz_out = r;
+}
+
+template <typename OffT>
+__global__ void zero_on_error_kernel(OffT* row_ptr, int64_t len, const int64_t* nnz_out) {
+  if (*nnz_out >= 0) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+    row_ptr[i] = 0;
+}
+
+struct BuildLayout {
+  uint64_t* keys_a;
+  uint64_t* keys_b;
+  uint32_t* hist;
+  int64_t* partial_a;
+  int64_t* partial_b;
+  int64_t* start;
+  int32_t* err;
+  size_t bytes;
+};
+
+BuildLayout carve_build(void* ws, int64_t n, int64_t num_pairs) {
+  const int64_t nk = 2 * num_pairs;
+  const int64_t tiles = (nk + kRadixTile - 1) / kRadixTile;
+  int64_t pa = scan_partial_len(256 * tiles);
+  if (scan_partial_len(n + 1) > pa) pa = scan_partial_len(n + 1);
+  Carver c(ws);
+  BuildLayout L;
+  L.keys_a = c.take<uint64_t>(nk);
+  L.keys_b = c.take<uint64_t>(nk);
+  L.hist = c.take<uint32_t>(256 * tiles);
+  L.partial_a = c.take<int64_t>(pa);
+  L.partial_b = c.take<int64_t>(scan_partial_len(nk));
+  L.start = c.take<int64_t>(n + 1);
+  L.err = c.take<int32_t>(1);
+  L.bytes = c.used();
+  return L;
+}
+
+template <typename OffT>
+tc_status build_impl(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst,
+                     OffT* row_ptr, int32_t* col, int64_t cap, int64_t* nnz_out,
+                     const BuildLayout& L, hipStream_t s) {
+  const int64_t nk = 2 * num_pairs;
+  const int cb = id_bits(n);
+  const int key_bits = 2 * cb;
+  const int64_t tiles = (nk + kRadixTile - 1) / kRadixTile;
+
+  clear_i32_kernel<<<1, 1, 0, s>>>(L.err);
+  if (num_pairs > 0) {
+    make_keys_kernel<<<grid_for(num_pairs, 256, 8192), 256, 0, s>>>(n, num_pairs, src, dst, cb,
+                                                                     L.keys_a, L.err);
+  }
+  uint64_t* in = L.keys_a;
+  uint64_t* out = L.keys_b;
+  if (nk > 0) {
+    for (int shift = 0; shift < key_bits; shift += 8) {
+      const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
+      radix_hist_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(in, nk, shift, (1u << bits) - 1u,
+                                                               L.hist, tiles);
+      hipError_t e = scan_exclusive<OpSum>(256 * tiles, HistLoad{L.hist}, HistStore{L.hist},
+                                           L.partial_a, s);
+      if (e != hipSuccess) return check_hip(e, "radix digit scan");
+      radix_scatter_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(in, out, nk, shift, bits,
+                                                                  L.hist, tiles);
+      uint64_t* t = in;
+      in = out;
+      out = t;
+    }
+  }
+  fill_i64_kernel<<<grid_for(n + 1, 256, 4096), 256, 0, s>>>(L.start, n + 1, INT64_MAX);
+  RunFlag flag{in};
+  hipError_t e = scan_exclusive<OpSum>(nk, DedupLoad{flag}, DedupStore{flag, cb, col, cap, L.start},
+                                       L.partial_b, s);
+  if (e != hipSuccess) return check_hip(e, "dedup scan");
+  const int64_t* dedup_total = L.partial_b + scan_num_tiles(nk);
+  set_total_kernel<<<1, 1, 0, s>>>(L.start, n, dedup_total);
+  e = scan_exclusive<OpMin>(n + 1, SuffixLoad{L.start, n}, SuffixStore<OffT>{L.start, n, row_ptr},
+                            L.partial_a, s);
+  if (e != hipSuccess) return check_hip(e, "row offset scan");
+  finalize_kernel<<<1, 1, 0, s>>>(L.err, dedup_total, cap, nnz_out);
+  zero_on_error_kernel<OffT><<<grid_for(n + 1, 256, 4096), 256, 0, s>>>(row_ptr, n + 1, nnz_out);
+  return check_hip(hipGetLastError(), "tc_build_csr launch");
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_build_csr(int64_t n, int64_t num_pairs, const int32_t* src,
+                                  const int32_t* dst, int32_t offset_bytes, void* row_ptr,
+                                  int32_t* col, int64_t col_capacity, int64_t* nnz_out, void* ws,
+                                  size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  if (n < 0 || num_pairs < 0 || col_capacity < 0)
+    return fail(TC_ERR_INVALID_ARG, "negative size (n=%lld num_pairs=%lld capacity=%lld)",
+                (long long)n, (long long)num_pairs, (long long)col_capacity);
+  if (n > INT32_MAX) return fail(TC_ERR_UNSUPPORTED, "n=%lld needs ids beyond int32", (long long)n);
+  if (num_pairs > INT32_MAX)
+    return fail(TC_ERR_UNSUPPORTED, "num_pairs=%lld exceeds 2^31-1", (long long)num_pairs);
+  if (offset_bytes != 4 && offset_bytes != 8)
+    return fail(TC_ERR_INVALID_ARG, "offset_bytes must be 4 or 8, got %d", offset_bytes);
+  if (offset_bytes == 4 && 2 * num_pairs > INT32_MAX)
+    return fail(TC_ERR_UNSUPPORTED, "int32 offsets cannot hold 2*num_pairs=%lld entries",
+                (long long)(2 * num_pairs));
+  const BuildLayout need = carve_build(nullptr, n, num_pairs);
+  tc_status st;
+  if (workspace_query(ws, ws_bytes, need.bytes, &st)) return st;
+  if (!row_ptr || !nnz_out || (num_pairs > 0 && (!src || !dst)) || (col_capacity > 0 && !col))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const BuildLayout L = carve_build(ws, n, num_pairs);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (offset_bytes == 4)
+    st = build_impl<int32_t>(n, num_pairs, src, dst, static_cast<int32_t*>(row_ptr), col,
+                             col_capacity, nnz_out, L, s);
+  else
+    st = build_impl<int64_t>(n, num_pairs, src, dst, static_cast<int64_t*>(row_ptr), col,
+                             col_capacity, nnz_out, L, s);
+  return st == TC_OK ? ok() : st;
+}

@@ -1,0 +1,453 @@
+// count.hip - tc_count / tc_count_per_vertex: all-source wedge advance + closing-edge filter.
+//
+// Alg. 1 verifies the triangle query in |Q|-1 = 2 BFS iterations from every
+// candidate source: the first advance u -> v, the second v -> w, and a match
+// needs the stored non-tree query edge (u1,u3), i.e. w in N+(u)
+// ("Store_none_tree_connection").  Here the two iterations are fused into one
+// pass that never materialises partial results: for each source u the group
+// (one workgroup, or one wave for small sources) stages N+(u) in an LDS table,
+// then streams every N+(v), v in N+(u), with coalesced reads and probes each w.
+// The count is the number of hits, which equals |M|/|Q| of Alg. 1 because the
+// orientation (unique mapping order) makes every triangle appear once.
+//
+// Pruning (Sec. III-C k-look-ahead): a source with d+(u) < 2 cannot close a
+// wedge (2-look-ahead) and is never queued; a middle v with d+(v) = 0 adds no
+// work (1-look-ahead).
+//
+// Probe structure: two-choice cuckoo hashing in LDS (two independent
+// multiplicative hashes into two halves of the table, load <= 0.4), so a probe
+// is exactly two LDS reads with no data-dependent loop.  Keys that do not settle
+// within kMaxKicks evictions go to a small stash; if the stash overflows the
+// group falls back to binary search over the sorted N+(u) it also keeps in LDS.
+//
+// Load balance: sources are binned by d+(u); sources with d+(u) > kSmallMax are
+// handed out largest class first through a global cursor, one workgroup each
+// (its four waves take the v's round robin); the rest are handled one wave each.
+// N+(u) longer than kChunk is processed in kChunk-sized slices of the table.
+//
+// Per-vertex counts: t(u) += hits of source u, t(v) += hits of edge (u,v), and
+// t(w) += the hit counter of w's LDS slot, flushed once per source, so global
+// atomics are at most n + 2m rather than one per triangle.
+#include "tc_device.h"
+#include "tc_host.h"
+
+namespace tc {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kSmallMax = 64;    // d+(u) <= kSmallMax: one wave per source
+constexpr int kChunk = 1024;     // keys per LDS table slice (workgroup mode)
+constexpr int kSideMax = 2048;   // slots per cuckoo half for kChunk keys (load <= 0.4)
+constexpr int kSmallSide = 128;  // slots per cuckoo half for kSmallMax keys
+constexpr int kStash = 32;
+constexpr int kMaxKicks = 48;
+constexpr int32_t kEmpty = -1;
+constexpr int32_t kNoKey = -2;  // probe value of an inactive lane: never stored
+constexpr int kNumClasses = 8;  // 0..6: workgroup classes by size (largest first), 7: small
+
+constexpr uint32_t kHashA = 0x9E3779B1u;
+constexpr uint32_t kHashB = 0x7FEB352Du;
+
+__host__ __device__ constexpr int small_bytes_per_wave(bool pv) {
+  return (2 * kSmallSide) * 4 * (pv ? 2 : 1) + kSmallMax * 4 + kStash * 8 + 16;
+}
+__host__ __device__ constexpr int group_bytes(bool pv) {
+  return (2 * kSideMax) * 4 * (pv ? 2 : 1) + kChunk * 4 + kStash * 8 + 16;
+}
+__host__ __device__ constexpr int smem_bytes(bool pv) {
+  return group_bytes(pv) > kWavesPerBlock * small_bytes_per_wave(pv)
+             ? group_bytes(pv)
+             : kWavesPerBlock * small_bytes_per_wave(pv);
+}
+
+// Size class of a source by out-degree; -1 when it cannot close a wedge.
+__device__ __forceinline__ int source_class(int64_t d) {
+  if (d < 2) return -1;
+  if (d <= kSmallMax) return 7;
+  if (d <= 128) return 6;
+  if (d <= 256) return 5;
+  if (d <= 512) return 4;
+  if (d <= 1024) return 3;
+  if (d <= 2048) return 2;
+  if (d <= 4096) return 1;
+  return 0;
+}
+
+struct CountState {
+  int32_t class_count[kNumClasses];
+  int32_t class_cursor[kNumClasses];
+  int32_t large_cursor;
+  int32_t pad[7];
+};
+
+template <typename OffT>
+__global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* __restrict__ row_ptr,
+                                                        CountState* __restrict__ st) {
+  __shared__ int32_t h[kNumClasses];
+  if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    const int c = source_class((int64_t)(row_ptr[u + 1] - row_ptr[u]));
+    if (c >= 0) atomicAdd(&h[c], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumClasses && h[threadIdx.x]) atomicAdd(&st->class_count[threadIdx.x], h[threadIdx.x]);
+}
+
+constexpr int kBinItems = 16;
+
+template <typename OffT>
+__global__ __launch_bounds__(256) void bin_write_kernel(int64_t n, const OffT* __restrict__ row_ptr,
+                                                        CountState* __restrict__ st,
+                                                        int32_t* __restrict__ list) {
+  __shared__ int32_t lcnt[kNumClasses];
+  __shared__ int32_t gbase[kNumClasses];
+  if (threadIdx.x < kNumClasses) lcnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * (256 * kBinItems);
+  int cls[kBinItems];
+  int32_t lr[kBinItems];
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    const int64_t u = base + r * 256 + threadIdx.x;
+    cls[r] = u < n ? source_class((int64_t)(row_ptr[u + 1] - row_ptr[u])) : -1;
+    lr[r] = cls[r] >= 0 ? atomicAdd(&lcnt[cls[r]], 1) : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumClasses) {
+    int32_t off = 0;
+    for (int c = 0; c < (int)threadIdx.x; ++c) off += st->class_count[c];
+    gbase[threadIdx.x] = off + (lcnt[threadIdx.x] ? atomicAdd(&st->class_cursor[threadIdx.x],
+                                                              lcnt[threadIdx.x])
+                                                  : 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    if (cls[r] >= 0) list[gbase[cls[r]] + lr[r]] = (int32_t)(base + r * 256 + threadIdx.x);
+  }
+}
+
+__global__ void init_state_kernel(CountState* st, uint64_t* total) {
+  int32_t* p = reinterpret_cast<int32_t*>(st);
+  for (int i = threadIdx.x; i < (int)(sizeof(CountState) / 4); i += blockDim.x) p[i] = 0;
+  if (threadIdx.x == 0) *total = 0;
+}
+
+__global__ void zero_u64_kernel(uint64_t* p, int64_t len) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
+}
+
+// One LDS cuckoo table (plus stash and the sorted keys it was built from).
+struct Table {
+  int32_t* slot;       // [2 * side]; halves [0, side) and [side, 2 * side)
+  uint32_t* cnt;       // [2 * side] hit counters (per-vertex mode only)
+  int32_t* sorted;     // [keys] the keys in ascending order
+  int32_t* stash;      // [kStash]
+  uint32_t* stash_cnt; // [kStash]
+  int32_t* meta;       // [0] stash entries, [1] overflow flag, [2] broadcast slot
+};
+
+template <bool PV>
+__device__ __forceinline__ Table table_at(char* base, int side) {
+  Table t;
+  t.slot = reinterpret_cast<int32_t*>(base);
+  char* p = base + 2 * side * 4;
+  t.cnt = reinterpret_cast<uint32_t*>(p);
+  if (PV) p += 2 * side * 4;
+  t.sorted = reinterpret_cast<int32_t*>(p);
+  p += (side == kSideMax ? kChunk : kSmallMax) * 4;
+  t.stash = reinterpret_cast<int32_t*>(p);
+  p += kStash * 4;
+  t.stash_cnt = reinterpret_cast<uint32_t*>(p);
+  p += kStash * 4;
+  t.meta = reinterpret_cast<int32_t*>(p);
+  return t;
+}
+
+__device__ __forceinline__ uint32_t hash_a(int32_t k, int shift) {
+  return ((uint32_t)k * kHashA) >> shift;
+}
+__device__ __forceinline__ uint32_t hash_b(int32_t k, int shift) {
+  return ((uint32_t)k * kHashB) >> shift;
+}
+
+// Group = one wave (Waves == 1) or the whole workgroup (Waves == kWavesPerBlock).
+template <int Waves>
+__device__ __forceinline__ void group_sync() {
+  if (Waves == 1) wave_sync();
+  else __syncthreads();
+}
+
+template <int Waves>
+__device__ __forceinline__ int group_rank() {
+  return Waves == 1 ? lane_id() : (int)threadIdx.x;
+}
+
+// Largest-first bit length helpers.
+__device__ __forceinline__ int side_log2(int keys) {
+  int want = keys + (keys >> 2) + 1;  // load factor <= 0.8 per half-pair -> <= 0.4 overall
+  int b = 4;
+  while ((1 << b) < want) ++b;
+  return b;
+}
+
+template <bool PV>
+__device__ __forceinline__ bool probe(const Table& t, int32_t w, int side, int shift, int stash_n,
+                                      bool overflow, int keys) {
+  if (!overflow) {
+    const uint32_t s1 = hash_a(w, shift);
+    const uint32_t s2 = (uint32_t)side + hash_b(w, shift);
+    const int32_t a = t.slot[s1];
+    const int32_t b = t.slot[s2];
+    bool hit = (a == w) | (b == w);
+    if (PV && hit) atomicAdd(&t.cnt[a == w ? s1 : s2], 1u);
+    if (stash_n > 0) {
+      for (int i = 0; i < stash_n; ++i) {
+        const bool h = t.stash[i] == w;
+        if (PV && h) atomicAdd(&t.stash_cnt[i], 1u);
+        hit |= h;
+      }
+    }
+    return hit;
+  }
+  // Fallback: lower bound over the sorted keys.
+  int lo = 0, len = keys;
+  while (len > 0) {
+    const int half = len >> 1;
+    if (t.sorted[lo + half] < w) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  const bool hit = lo < keys && t.sorted[lo] == w;
+  if (PV && hit) atomicAdd(&t.cnt[lo], 1u);
+  return hit;
+}
+
+// Process one source u with a group of Waves waves sharing table `t`.
+// Returns this wave's hit count (uniform across the wave).
+template <int Waves, bool PV, typename OffT>
+__device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
+                                   const int32_t* __restrict__ col, uint64_t* __restrict__ tv,
+                                   const Table& t, int max_keys) {
+  const int lane = lane_id();
+  const int gwave = Waves == 1 ? 0 : (int)threadIdx.x / kWave;
+  const int gr = group_rank<Waves>();
+  const int64_t beg = row_ptr[u];
+  const int64_t d = (int64_t)row_ptr[u + 1] - beg;
+  uint64_t wave_hits = 0;
+  for (int64_t c0 = 0; c0 < d; c0 += max_keys) {
+    const int keys = (int)(d - c0 < max_keys ? d - c0 : max_keys);
+    const int b = side_log2(keys);
+    const int side = 1 << b;
+    const int shift = 32 - b;
+    for (int s = gr; s < 2 * side; s += Waves * kWave) {
+      t.slot[s] = kEmpty;
+      if (PV) t.cnt[s] = 0;
+    }
+    if (gr < kStash) t.stash_cnt[gr] = 0;
+    if (gr < 2) t.meta[gr] = 0;
+    group_sync<Waves>();
+    for (int i = gr; i < keys; i += Waves * kWave) {
+      int32_t cur = col[beg + c0 + i];
+      t.sorted[i] = cur;
+      int hs = 0;
+      for (int kick = 0; kick < kMaxKicks && cur != kEmpty; ++kick) {
+        const uint32_t s = hs ? (uint32_t)side + hash_b(cur, shift) : hash_a(cur, shift);
+        cur = atomicExch(&t.slot[s], cur);
+        hs ^= 1;
+      }
+      if (cur != kEmpty) {
+        const int at = atomicAdd(&t.meta[0], 1);
+        if (at < kStash) t.stash[at] = cur;
+        else t.meta[1] = 1;
+      }
+    }
+    group_sync<Waves>();
+    const int stash_raw = t.meta[0];
+    const bool overflow = t.meta[1] != 0;
+    const int stash_n = stash_raw < kStash ? stash_raw : kStash;
+    uint64_t src_hits = 0;
+    // Middles v = N+(u)[i], i = gwave, gwave + Waves, ...; 64 of them prefetched per batch.
+    for (int64_t i0 = 0; i0 < d; i0 += (int64_t)Waves * kWave) {
+      const int64_t i = i0 + (int64_t)Waves * lane + gwave;
+      int32_t v = 0;
+      int64_t vb = 0, ve = 0;
+      if (i < d) {
+        v = col[beg + i];
+        vb = row_ptr[v];
+        ve = row_ptr[v + 1];
+      }
+      int64_t rem = d - i0 - gwave;
+      const int nb = rem <= 0 ? 0 : (int)((rem + Waves - 1) / Waves < kWave ? (rem + Waves - 1) / Waves : kWave);
+      for (int j = 0; j < nb; ++j) {
+        const int32_t vj = read_lane(v, j);
+        const int64_t jb = read_lane64(vb, j);
+        const int64_t je = read_lane64(ve, j);
+        uint32_t hv = 0;
+        for (int64_t e0 = jb; e0 < je; e0 += kWave) {
+          const int64_t e = e0 + lane;
+          const int32_t w = e < je ? col[e] : kNoKey;
+          const bool hit = probe<PV>(t, w, side, shift, stash_n, overflow, keys);
+          hv += popc(ballot(hit));
+        }
+        src_hits += hv;
+        if (PV && hv && lane == 0) atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
+      }
+    }
+    wave_hits += src_hits;
+    if (PV) {
+      if (src_hits && lane == 0) atomicAdd((unsigned long long*)&tv[u], (unsigned long long)src_hits);
+      group_sync<Waves>();
+      if (overflow) {
+        for (int p = gr; p < keys; p += Waves * kWave) {
+          const uint32_t c = t.cnt[p];
+          if (c) atomicAdd((unsigned long long*)&tv[t.sorted[p]], (unsigned long long)c);
+        }
+      } else {
+        for (int s = gr; s < 2 * side; s += Waves * kWave) {
+          const int32_t k = t.slot[s];
+          const uint32_t c = t.cnt[s];
+          if (k != kEmpty && c) atomicAdd((unsigned long long*)&tv[k], (unsigned long long)c);
+        }
+        if (gr < stash_n && t.stash_cnt[gr])
+          atomicAdd((unsigned long long*)&tv[t.stash[gr]], (unsigned long long)t.stash_cnt[gr]);
+      }
+    }
+    group_sync<Waves>();
+  }
+  return wave_hits;
+}
+
+// Persistent count kernel: workgroup-mode sources first (dynamic cursor), then
+// wave-mode sources (static round robin over all waves of the grid).
+template <bool PV, typename OffT>
+__global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ list,
+                                                       CountState* __restrict__ st,
+                                                       uint64_t* __restrict__ total,
+                                                       uint64_t* __restrict__ tv) {
+  __shared__ __align__(16) char smem[smem_bytes(PV)];
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  int32_t n_large = 0;
+  for (int c = 0; c < kNumClasses - 1; ++c) n_large += st->class_count[c];
+  const int32_t n_small = st->class_count[kNumClasses - 1];
+  uint64_t hits = 0;
+
+  const Table big = table_at<PV>(smem, kSideMax);
+  for (;;) {
+    if (threadIdx.x == 0) big.meta[2] = atomicAdd(&st->large_cursor, 1);
+    __syncthreads();
+    const int32_t idx = big.meta[2];
+    __syncthreads();
+    if (idx >= n_large) break;
+    hits += process_source<kWavesPerBlock, PV, OffT>(list[idx], row_ptr, col, tv, big, kChunk);
+  }
+
+  const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide);
+  const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave; i < n_small; i += waves) {
+    hits += process_source<1, PV, OffT>(list[n_large + i], row_ptr, col, tv, mine, kSmallMax);
+  }
+  if (lane == 0 && hits) atomicAdd((unsigned long long*)total, (unsigned long long)hits);
+}
+
+struct CountLayout {
+  CountState* st;
+  int32_t* list;
+  uint64_t* total_scratch;
+  size_t bytes;
+};
+
+CountLayout carve_count(void* ws, int64_t n) {
+  Carver c(ws);
+  CountLayout L;
+  L.st = c.take<CountState>(1);
+  L.list = c.take<int32_t>(n);
+  L.total_scratch = c.take<uint64_t>(1);
+  L.bytes = c.used();
+  return L;
+}
+
+template <bool PV, typename OffT>
+int count_grid() {
+  static int cached[64] = {0};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (cached[dev] == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_kernel<PV, OffT>, kBlock, 0) !=
+            hipSuccess ||
+        per_cu <= 0) {
+      per_cu = 2;
+    }
+    cached[dev] = per_cu * device_cu_count();
+  }
+  return cached[dev];
+}
+
+template <bool PV, typename OffT>
+tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_t* total,
+                     uint64_t* tv, const CountLayout& L, hipStream_t s) {
+  uint64_t* tot = total ? total : L.total_scratch;
+  init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
+  if (PV) zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(tv, n);
+  if (n > 0) {
+    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st);
+    bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
+        n, row_ptr, L.st, L.list);
+    count_kernel<PV, OffT><<<count_grid<PV, OffT>(), kBlock, 0, s>>>(row_ptr, col, L.list, L.st,
+                                                                      tot, tv);
+  }
+  return check_hip(hipGetLastError(), "tc_count launch");
+}
+
+tc_status check_dag(const tc_csr* dag) {
+  if (!dag) return fail(TC_ERR_INVALID_ARG, "dag is NULL");
+  if (dag->n < 0) return fail(TC_ERR_INVALID_ARG, "negative n");
+  if (dag->n > INT32_MAX) return fail(TC_ERR_UNSUPPORTED, "n=%lld needs ids beyond int32", (long long)dag->n);
+  if (dag->offset_bytes != 4 && dag->offset_bytes != 8)
+    return fail(TC_ERR_INVALID_ARG, "offset_bytes must be 4 or 8, got %d", dag->offset_bytes);
+  return TC_OK;
+}
+
+template <bool PV>
+tc_status count_dispatch(const tc_csr* dag, uint64_t* total, uint64_t* tv, void* ws,
+                         size_t* ws_bytes, void* stream) {
+  tc_status st = check_dag(dag);
+  if (st != TC_OK) return st;
+  if (workspace_query(ws, ws_bytes, carve_count(nullptr, dag->n).bytes, &st)) return st;
+  if (!dag->row_ptr || (PV && dag->n > 0 && !tv) || (!PV && !total))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const CountLayout L = carve_count(ws, dag->n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dag->offset_bytes == 4)
+    st = count_impl<PV, int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col, total,
+                                 tv, L, s);
+  else
+    st = count_impl<PV, int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, total,
+                                 tv, L, s);
+  return st == TC_OK ? ok() : st;
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_count(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_bytes,
+                              void* stream) {
+  return tc::count_dispatch<false>(dag, total, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C" tc_status tc_count_per_vertex(const tc_csr* dag, uint64_t* per_vertex, uint64_t* total,
+                                         void* ws, size_t* ws_bytes, void* stream) {
+  return tc::count_dispatch<true>(dag, total, per_vertex, ws, ws_bytes, stream);
+}

@@ -1,0 +1,75 @@
+// tc_device.h - device-side helpers shared by the gfx950 kernels of libtc.
+//
+// Everything here targets CDNA wave64 directly: ballots are 64-bit, lane ranks
+// come from mbcnt, and wave-local LDS hand-offs are ordered with wavefront-scope
+// fences (a wave's LDS operations complete in order once lgkmcnt drains).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tc {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot((int)p); }
+
+// Number of set bits of `mask` at lanes below the calling lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc(uint64_t mask) { return (uint32_t)__popcll(mask); }
+
+// Make this wave's earlier LDS writes visible to its later LDS reads from other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Broadcast lane `src`'s value (src wave-uniform) to the whole wave.
+__device__ __forceinline__ int32_t read_lane(int32_t v, int src) {
+  return __builtin_amdgcn_readlane(v, src);
+}
+__device__ __forceinline__ int64_t read_lane64(int64_t v, int src) {
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)v, src);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), src);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int32_t first_lane(int32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Inclusive wave scan (sum) of a 64-bit value.
+__device__ __forceinline__ int64_t wave_inclusive_sum(int64_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int64_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_off(const void* p, int64_t i);
+template <>
+__device__ __forceinline__ int32_t load_off<int32_t>(const void* p, int64_t i) {
+  return static_cast<const int32_t*>(p)[i];
+}
+template <>
+__device__ __forceinline__ int64_t load_off<int64_t>(const void* p, int64_t i) {
+  return static_cast<const int64_t*>(p)[i];
+}
+
+}  // namespace tc

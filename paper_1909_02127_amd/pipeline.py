@@ -1,0 +1,97 @@
+"""Device pipeline over the C ABI: raw pairs -> CSR -> oriented DAG -> counts.
+
+Buffers and workspaces are allocated once with torch (device memory only) and
+reused; every step is a libtc call enqueued on the current stream, so a run has
+no host synchronisation until results are read.  Device-side errors reported by
+the library (an out-of-range id, an output too small) are raised on read.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import TC_ORDER_DEGREE, TC_ORDER_ID, TcError  # noqa: F401
+
+
+def _bytes(n: int, device) -> torch.Tensor:
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Result:
+    total: int
+    per_vertex: torch.Tensor | None
+    nnz: int  # stored entries of the symmetric CSR (2m)
+    m: int    # undirected edges = DAG edges
+
+
+class Pipeline:
+    """Preallocated buffers for graphs with up to `num_pairs` raw pairs on `n` vertices."""
+
+    def __init__(self, n: int, num_pairs: int, *, offset_bytes: int = 4,
+                 order: int = TC_ORDER_DEGREE, device="cuda"):
+        self.n, self.num_pairs, self.order = int(n), int(num_pairs), order
+        self.device = torch.device(device)
+        odt = torch.int32 if offset_bytes == 4 else torch.int64
+        dev = self.device
+        self.row_ptr = torch.empty(n + 1, dtype=odt, device=dev)
+        self.col = torch.empty(max(2 * num_pairs, 1), dtype=torch.int32, device=dev)
+        self.dag_ptr = torch.empty(n + 1, dtype=odt, device=dev)
+        self.dag_col = torch.empty(max(num_pairs, 1), dtype=torch.int32, device=dev)
+        self.nnz = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.m = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.total = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.per_vertex = torch.zeros(max(n, 1), dtype=torch.int64, device=dev)
+        self.ws_build = _bytes(_lib.tc_build_csr_workspace(n, num_pairs, offset_bytes), dev)
+        self.ws_orient = _bytes(_lib.tc_orient_workspace(n), dev)
+        self.ws_count = _bytes(max(_lib.tc_count_workspace(n),
+                                   _lib.tc_count_per_vertex_workspace(n)), dev)
+
+    # -- the steps, each one C ABI call --------------------------------------------------
+    def build(self, src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+        if src.numel() > self.num_pairs:
+            raise ValueError("more pairs than the pipeline was sized for")
+        _lib.tc_build_csr(self.n, src, dst, self.row_ptr, self.col, self.nnz, self.ws_build,
+                          stream=stream)
+
+    def orient(self, stream=None) -> None:
+        _lib.tc_orient(self.n, self.row_ptr, self.col, self.order, self.dag_ptr, self.dag_col,
+                       self.m, self.ws_orient, stream=stream)
+
+    def count(self, stream=None) -> None:
+        _lib.tc_count(self.n, self.dag_ptr, self.dag_col, self.total, self.ws_count, stream=stream)
+
+    def count_per_vertex(self, stream=None) -> None:
+        pv = self.per_vertex[: self.n]
+        _lib.tc_count_per_vertex(self.n, self.dag_ptr, self.dag_col, pv, self.total,
+                                 self.ws_count, stream=stream)
+
+    def enqueue(self, src, dst, *, per_vertex: bool = False, stream=None) -> None:
+        self.build(src, dst, stream)
+        self.orient(stream)
+        if per_vertex:
+            self.count_per_vertex(stream)
+        else:
+            self.count(stream)
+
+    def result(self, *, per_vertex: bool = False) -> Result:
+        """Synchronise and read the counts; raises TcError on a device-side error."""
+        torch.cuda.synchronize(self.device)
+        nnz, m = int(self.nnz.item()), int(self.m.item())
+        if nnz < 0:
+            raise TcError(-nnz, "reported by tc_build_csr on the device")
+        if m < 0:
+            raise TcError(-m, "reported by tc_orient on the device")
+        total = int(self.total.item()) & ((1 << 64) - 1)  # the library writes a uint64
+        pv = self.per_vertex[: self.n].clone() if per_vertex else None
+        return Result(total, pv, nnz, m)
+
+
+def triangle_count(src: torch.Tensor, dst: torch.Tensor, n: int, *, per_vertex: bool = False,
+                   order: int = TC_ORDER_DEGREE, offset_bytes: int = 4) -> Result:
+    """One-shot count of a raw pair list already in device memory."""
+    p = Pipeline(n, src.numel(), offset_bytes=offset_bytes, order=order, device=src.device)
+    p.enqueue(src, dst, per_vertex=per_vertex)
+    return p.result(per_vertex=per_vertex)
