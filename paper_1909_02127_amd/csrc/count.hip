@@ -29,7 +29,10 @@
 // t(w) += the hit counter of w's LDS slot, flushed once per source, so global
 // atomics are at most n + 2m rather than one per triangle.
 #include "tc_device.h"
+#include "tc_hash.h"
 #include "tc_host.h"
+
+#include <stdlib.h>
 
 namespace tc {
 namespace {
@@ -37,17 +40,20 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSmallMax = 64;    // d+(u) <= kSmallMax: one wave per source
-constexpr int kChunk = 1024;     // keys per LDS table slice (workgroup mode)
-constexpr int kSideMax = 2048;   // slots per cuckoo half for kChunk keys (load <= 0.4)
+constexpr int kSideMax = 1024;   // slots per cuckoo half (workgroup mode)
+constexpr int kChunk = 816;      // keys per LDS table slice: side_log2(kChunk) <= log2(kSideMax)
 constexpr int kSmallSide = 128;  // slots per cuckoo half for kSmallMax keys
 constexpr int kStash = 32;
 constexpr int kMaxKicks = 48;
+constexpr int kUnroll = 4;       // 64-wide loads in flight per wave while streaming N+(v)
 constexpr int32_t kEmpty = -1;
 constexpr int32_t kNoKey = -2;  // probe value of an inactive lane: never stored
 constexpr int kNumClasses = 8;  // 0..6: workgroup classes by size (largest first), 7: small
 
-constexpr uint32_t kHashA = 0x9E3779B1u;
-constexpr uint32_t kHashB = 0x7FEB352Du;
+// Probe modes, fixed per table slice after it is built.
+constexpr int kModeCuckoo = 0;  // every key sits in one of its two cuckoo slots
+constexpr int kModeStash = 1;   // plus up to kStash keys in the stash
+constexpr int kModeSorted = 2;  // stash overflowed: binary search the sorted keys
 
 __host__ __device__ constexpr int small_bytes_per_wave(bool pv) {
   return (2 * kSmallSide) * 4 * (pv ? 2 : 1) + kSmallMax * 4 + kStash * 8 + 16;
@@ -87,10 +93,17 @@ __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* _
   __shared__ int32_t h[kNumClasses];
   if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
   __syncthreads();
+  int32_t mine[kNumClasses] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     const int c = source_class((int64_t)(row_ptr[u + 1] - row_ptr[u]));
-    if (c >= 0) atomicAdd(&h[c], 1);
+#pragma unroll
+    for (int k = 0; k < kNumClasses; ++k) mine[k] += (c == k);
+  }
+#pragma unroll
+  for (int k = 0; k < kNumClasses; ++k) {
+    const int64_t s = wave_sum(mine[k]);
+    if (lane_id() == 0 && s) atomicAdd(&h[k], (int32_t)s);
   }
   __syncthreads();
   if (threadIdx.x < kNumClasses && h[threadIdx.x]) atomicAdd(&st->class_count[threadIdx.x], h[threadIdx.x]);
@@ -152,27 +165,20 @@ struct Table {
 };
 
 template <bool PV>
-__device__ __forceinline__ Table table_at(char* base, int side) {
+__device__ __forceinline__ Table table_at(char* base, int side_max, int keys_max) {
   Table t;
   t.slot = reinterpret_cast<int32_t*>(base);
-  char* p = base + 2 * side * 4;
+  char* p = base + 2 * side_max * 4;
   t.cnt = reinterpret_cast<uint32_t*>(p);
-  if (PV) p += 2 * side * 4;
+  if (PV) p += 2 * side_max * 4;
   t.sorted = reinterpret_cast<int32_t*>(p);
-  p += (side == kSideMax ? kChunk : kSmallMax) * 4;
+  p += keys_max * 4;
   t.stash = reinterpret_cast<int32_t*>(p);
   p += kStash * 4;
   t.stash_cnt = reinterpret_cast<uint32_t*>(p);
   p += kStash * 4;
   t.meta = reinterpret_cast<int32_t*>(p);
   return t;
-}
-
-__device__ __forceinline__ uint32_t hash_a(int32_t k, int shift) {
-  return ((uint32_t)k * kHashA) >> shift;
-}
-__device__ __forceinline__ uint32_t hash_b(int32_t k, int shift) {
-  return ((uint32_t)k * kHashB) >> shift;
 }
 
 // Group = one wave (Waves == 1) or the whole workgroup (Waves == kWavesPerBlock).
@@ -187,79 +193,162 @@ __device__ __forceinline__ int group_rank() {
   return Waves == 1 ? lane_id() : (int)threadIdx.x;
 }
 
-// Largest-first bit length helpers.
+// log2 of the slots per half for `keys` keys: load <= 0.4 over both halves.
 __device__ __forceinline__ int side_log2(int keys) {
-  int want = keys + (keys >> 2) + 1;  // load factor <= 0.8 per half-pair -> <= 0.4 overall
+  const int want = keys + (keys >> 2) + 1;
   int b = 4;
   while ((1 << b) < want) ++b;
   return b;
 }
 
-template <bool PV>
-__device__ __forceinline__ bool probe(const Table& t, int32_t w, int side, int shift, int stash_n,
-                                      bool overflow, int keys) {
-  if (!overflow) {
-    const uint32_t s1 = hash_a(w, shift);
-    const uint32_t s2 = (uint32_t)side + hash_b(w, shift);
-    const int32_t a = t.slot[s1];
-    const int32_t b = t.slot[s2];
-    bool hit = (a == w) | (b == w);
-    if (PV && hit) atomicAdd(&t.cnt[a == w ? s1 : s2], 1u);
-    if (stash_n > 0) {
-      for (int i = 0; i < stash_n; ++i) {
-        const bool h = t.stash[i] == w;
-        if (PV && h) atomicAdd(&t.stash_cnt[i], 1u);
-        hit |= h;
+struct Slice {
+  int side;   // slots per cuckoo half
+  int shift;  // 32 - log2(side)
+  int keys;   // keys in this slice
+  int stash_n;
+};
+
+template <bool PV, int Mode, bool Wide>
+__device__ __forceinline__ bool probe(const Table& t, const Slice& sl, int32_t w) {
+  if (Mode == kModeSorted) {
+    int lo = 0, len = sl.keys;
+    while (len > 0) {
+      const int half = len >> 1;
+      if (t.sorted[lo + half] < w) {
+        lo += half + 1;
+        len -= half + 1;
+      } else {
+        len = half;
       }
     }
+    const bool hit = lo < sl.keys && t.sorted[lo] == w;
+    if (PV && hit) atomicAdd(&t.cnt[lo], 1u);
     return hit;
   }
-  // Fallback: lower bound over the sorted keys.
-  int lo = 0, len = keys;
-  while (len > 0) {
-    const int half = len >> 1;
-    if (t.sorted[lo + half] < w) {
-      lo += half + 1;
-      len -= half + 1;
-    } else {
-      len = half;
+  const uint32_t s1 = hash_a<Wide>(w, sl.shift);
+  const uint32_t s2 = (uint32_t)sl.side + hash_b<Wide>(w, sl.shift);
+  const int32_t a = t.slot[s1];
+  const int32_t b = t.slot[s2];
+  bool hit = (a == w) | (b == w);
+  if (PV && hit) atomicAdd(&t.cnt[a == w ? s1 : s2], 1u);
+  if (Mode == kModeStash) {
+    for (int i = 0; i < sl.stash_n; ++i) {
+      const bool h = t.stash[i] == w;
+      if (PV && h) atomicAdd(&t.stash_cnt[i], 1u);
+      hit |= h;
     }
   }
-  const bool hit = lo < keys && t.sorted[lo] == w;
-  if (PV && hit) atomicAdd(&t.cnt[lo], 1u);
   return hit;
+}
+
+// Hits among the `len` ids of one out-neighbour list `lst` (len >= 1).  Four
+// 64-wide loads are issued before any probe so each wave keeps several memory
+// requests in flight; the tail clamps its indices to stay inside the list.
+template <bool PV, int Mode, bool Wide>
+__device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, int len,
+                                              const Table& t, const Slice& sl) {
+  const int lane = lane_id();
+  uint32_t hv = 0;
+  int base = 0;
+  for (; base + kUnroll * kWave <= len; base += kUnroll * kWave) {
+    const int32_t* p = lst + base + lane;
+    int32_t w[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) w[k] = p[k * kWave];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) hv += popc(ballot(probe<PV, Mode, Wide>(t, sl, w[k])));
+  }
+  if (base < len) {
+    const int last = len - 1;
+    int32_t w[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const int i = base + k * kWave + lane;
+      const int32_t x = lst[i < last ? i : last];
+      w[k] = i <= last ? x : kNoKey;
+    }
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      if (base + k * kWave < len) hv += popc(ballot(probe<PV, Mode, Wide>(t, sl, w[k])));
+    }
+  }
+  return hv;
+}
+
+// All middles v of source u handled by this wave: v = N+(u)[i] for
+// i = gwave, gwave + Waves, ...; 64 of them are prefetched per batch.
+template <int Waves, bool PV, int Mode, bool Wide, typename OffT>
+__device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
+                                 const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                 uint64_t* __restrict__ tv, const Table& t, const Slice& sl) {
+  const int lane = lane_id();
+  const int gwave = Waves == 1 ? 0 : (int)threadIdx.x / kWave;
+  uint64_t src_hits = 0;
+  for (int64_t i0 = 0; i0 < d; i0 += (int64_t)Waves * kWave) {
+    const int64_t i = i0 + (int64_t)Waves * lane + gwave;
+    int32_t v = 0;
+    OffT vb = 0, ve = 0;
+    if (i < d) {
+      v = nbrs[i];
+      vb = row_ptr[v];
+      ve = row_ptr[v + 1];
+    }
+    const int64_t rem = d - i0 - gwave;
+    const int64_t cnt = rem <= 0 ? 0 : (rem + Waves - 1) / Waves;
+    const int nb = cnt < kWave ? (int)cnt : kWave;
+    for (int j = 0; j < nb; ++j) {
+      int64_t jb, je;
+      if (sizeof(OffT) == 4) {
+        jb = read_lane((int32_t)vb, j);
+        je = read_lane((int32_t)ve, j);
+      } else {
+        jb = read_lane64((int64_t)vb, j);
+        je = read_lane64((int64_t)ve, j);
+      }
+      if (je <= jb) continue;  // 1-look-ahead: a middle with no out-neighbour adds nothing
+      const uint32_t hv = scan_list<PV, Mode, Wide>(col + jb, (int)(je - jb), t, sl);
+      src_hits += hv;
+      if (PV && hv && lane == 0) {
+        const int32_t vj = read_lane(v, j);
+        atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
+      }
+    }
+  }
+  return src_hits;
 }
 
 // Process one source u with a group of Waves waves sharing table `t`.
 // Returns this wave's hit count (uniform across the wave).
-template <int Waves, bool PV, typename OffT>
+template <int Waves, bool PV, bool Wide, typename OffT>
 __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
                                    const int32_t* __restrict__ col, uint64_t* __restrict__ tv,
-                                   const Table& t, int max_keys) {
+                                   const Table& t, int max_keys, int max_kicks) {
   const int lane = lane_id();
-  const int gwave = Waves == 1 ? 0 : (int)threadIdx.x / kWave;
   const int gr = group_rank<Waves>();
   const int64_t beg = row_ptr[u];
   const int64_t d = (int64_t)row_ptr[u + 1] - beg;
+  const int32_t* nbrs = col + beg;
   uint64_t wave_hits = 0;
   for (int64_t c0 = 0; c0 < d; c0 += max_keys) {
-    const int keys = (int)(d - c0 < max_keys ? d - c0 : max_keys);
-    const int b = side_log2(keys);
-    const int side = 1 << b;
-    const int shift = 32 - b;
-    for (int s = gr; s < 2 * side; s += Waves * kWave) {
+    Slice sl;
+    sl.keys = (int)(d - c0 < max_keys ? d - c0 : max_keys);
+    const int b = side_log2(sl.keys);
+    sl.side = 1 << b;
+    sl.shift = 32 - b;
+    for (int s = gr; s < 2 * sl.side; s += Waves * kWave) {
       t.slot[s] = kEmpty;
       if (PV) t.cnt[s] = 0;
     }
     if (gr < kStash) t.stash_cnt[gr] = 0;
     if (gr < 2) t.meta[gr] = 0;
     group_sync<Waves>();
-    for (int i = gr; i < keys; i += Waves * kWave) {
-      int32_t cur = col[beg + c0 + i];
+    for (int i = gr; i < sl.keys; i += Waves * kWave) {
+      int32_t cur = nbrs[c0 + i];
       t.sorted[i] = cur;
       int hs = 0;
-      for (int kick = 0; kick < kMaxKicks && cur != kEmpty; ++kick) {
-        const uint32_t s = hs ? (uint32_t)side + hash_b(cur, shift) : hash_a(cur, shift);
+      for (int kick = 0; kick < max_kicks && cur != kEmpty; ++kick) {
+        const uint32_t s = hs ? (uint32_t)sl.side + hash_b<Wide>(cur, sl.shift)
+                              : hash_a<Wide>(cur, sl.shift);
         cur = atomicExch(&t.slot[s], cur);
         hs ^= 1;
       }
@@ -271,52 +360,31 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
     }
     group_sync<Waves>();
     const int stash_raw = t.meta[0];
-    const bool overflow = t.meta[1] != 0;
-    const int stash_n = stash_raw < kStash ? stash_raw : kStash;
-    uint64_t src_hits = 0;
-    // Middles v = N+(u)[i], i = gwave, gwave + Waves, ...; 64 of them prefetched per batch.
-    for (int64_t i0 = 0; i0 < d; i0 += (int64_t)Waves * kWave) {
-      const int64_t i = i0 + (int64_t)Waves * lane + gwave;
-      int32_t v = 0;
-      int64_t vb = 0, ve = 0;
-      if (i < d) {
-        v = col[beg + i];
-        vb = row_ptr[v];
-        ve = row_ptr[v + 1];
-      }
-      int64_t rem = d - i0 - gwave;
-      const int nb = rem <= 0 ? 0 : (int)((rem + Waves - 1) / Waves < kWave ? (rem + Waves - 1) / Waves : kWave);
-      for (int j = 0; j < nb; ++j) {
-        const int32_t vj = read_lane(v, j);
-        const int64_t jb = read_lane64(vb, j);
-        const int64_t je = read_lane64(ve, j);
-        uint32_t hv = 0;
-        for (int64_t e0 = jb; e0 < je; e0 += kWave) {
-          const int64_t e = e0 + lane;
-          const int32_t w = e < je ? col[e] : kNoKey;
-          const bool hit = probe<PV>(t, w, side, shift, stash_n, overflow, keys);
-          hv += popc(ballot(hit));
-        }
-        src_hits += hv;
-        if (PV && hv && lane == 0) atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
-      }
-    }
+    sl.stash_n = stash_raw < kStash ? stash_raw : kStash;
+    const int mode = t.meta[1] ? kModeSorted : (sl.stash_n ? kModeStash : kModeCuckoo);
+    uint64_t src_hits;
+    if (mode == kModeCuckoo)
+      src_hits = scan_middles<Waves, PV, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl);
+    else if (mode == kModeStash)
+      src_hits = scan_middles<Waves, PV, kModeStash, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl);
+    else
+      src_hits = scan_middles<Waves, PV, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl);
     wave_hits += src_hits;
     if (PV) {
       if (src_hits && lane == 0) atomicAdd((unsigned long long*)&tv[u], (unsigned long long)src_hits);
       group_sync<Waves>();
-      if (overflow) {
-        for (int p = gr; p < keys; p += Waves * kWave) {
+      if (mode == kModeSorted) {
+        for (int p = gr; p < sl.keys; p += Waves * kWave) {
           const uint32_t c = t.cnt[p];
           if (c) atomicAdd((unsigned long long*)&tv[t.sorted[p]], (unsigned long long)c);
         }
       } else {
-        for (int s = gr; s < 2 * side; s += Waves * kWave) {
+        for (int s = gr; s < 2 * sl.side; s += Waves * kWave) {
           const int32_t k = t.slot[s];
           const uint32_t c = t.cnt[s];
           if (k != kEmpty && c) atomicAdd((unsigned long long*)&tv[k], (unsigned long long)c);
         }
-        if (gr < stash_n && t.stash_cnt[gr])
+        if (gr < sl.stash_n && t.stash_cnt[gr])
           atomicAdd((unsigned long long*)&tv[t.stash[gr]], (unsigned long long)t.stash_cnt[gr]);
       }
     }
@@ -327,13 +395,13 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
 
 // Persistent count kernel: workgroup-mode sources first (dynamic cursor), then
 // wave-mode sources (static round robin over all waves of the grid).
-template <bool PV, typename OffT>
+template <bool PV, bool Wide, typename OffT>
 __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
                                                        const int32_t* __restrict__ list,
                                                        CountState* __restrict__ st,
                                                        uint64_t* __restrict__ total,
-                                                       uint64_t* __restrict__ tv) {
+                                                       uint64_t* __restrict__ tv, int max_kicks) {
   __shared__ __align__(16) char smem[smem_bytes(PV)];
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
@@ -342,20 +410,22 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ 
   const int32_t n_small = st->class_count[kNumClasses - 1];
   uint64_t hits = 0;
 
-  const Table big = table_at<PV>(smem, kSideMax);
+  const Table big = table_at<PV>(smem, kSideMax, kChunk);
   for (;;) {
     if (threadIdx.x == 0) big.meta[2] = atomicAdd(&st->large_cursor, 1);
     __syncthreads();
     const int32_t idx = big.meta[2];
     __syncthreads();
     if (idx >= n_large) break;
-    hits += process_source<kWavesPerBlock, PV, OffT>(list[idx], row_ptr, col, tv, big, kChunk);
+    hits += process_source<kWavesPerBlock, PV, Wide, OffT>(list[idx], row_ptr, col, tv, big, kChunk,
+                                                           max_kicks);
   }
 
-  const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide);
+  const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide, kSmallMax);
   const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave; i < n_small; i += waves) {
-    hits += process_source<1, PV, OffT>(list[n_large + i], row_ptr, col, tv, mine, kSmallMax);
+    hits += process_source<1, PV, Wide, OffT>(list[n_large + i], row_ptr, col, tv, mine, kSmallMax,
+                                              max_kicks);
   }
   if (lane == 0 && hits) atomicAdd((unsigned long long*)total, (unsigned long long)hits);
 }
@@ -377,7 +447,7 @@ CountLayout carve_count(void* ws, int64_t n) {
   return L;
 }
 
-template <bool PV, typename OffT>
+template <bool PV, bool Wide, typename OffT>
 int count_grid() {
   static int cached[64] = {0};
   int dev = 0;
@@ -385,7 +455,7 @@ int count_grid() {
   if (dev < 0 || dev >= 64) dev = 0;
   if (cached[dev] == 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_kernel<PV, OffT>, kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_kernel<PV, Wide, OffT>, kBlock, 0) !=
             hipSuccess ||
         per_cu <= 0) {
       per_cu = 2;
@@ -399,14 +469,22 @@ template <bool PV, typename OffT>
 tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_t* total,
                      uint64_t* tv, const CountLayout& L, hipStream_t s) {
   uint64_t* tot = total ? total : L.total_scratch;
+  // Test hook: TC_TEST_MAX_KICKS caps cuckoo evictions so that tests can drive
+  // keys into the stash (and past it, into the sorted fallback).
+  int max_kicks = kMaxKicks;
+  if (const char* env = getenv("TC_TEST_MAX_KICKS")) max_kicks = atoi(env);
   init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
   if (PV) zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(tv, n);
   if (n > 0) {
     bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st);
     bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
         n, row_ptr, L.st, L.list);
-    count_kernel<PV, OffT><<<count_grid<PV, OffT>(), kBlock, 0, s>>>(row_ptr, col, L.list, L.st,
-                                                                      tot, tv);
+    if (n <= (int64_t(1) << 24))
+      count_kernel<PV, false, OffT><<<count_grid<PV, false, OffT>(), kBlock, 0, s>>>(
+          row_ptr, col, L.list, L.st, tot, tv, max_kicks);
+    else
+      count_kernel<PV, true, OffT><<<count_grid<PV, true, OffT>(), kBlock, 0, s>>>(
+          row_ptr, col, L.list, L.st, tot, tv, max_kicks);
   }
   return check_hip(hipGetLastError(), "tc_count launch");
 }

@@ -256,3 +256,20 @@ def test_rmat_scale20_full_parity(tc):
     rng = np.random.default_rng(0)
     for v in rng.choice(np.flatnonzero(t), 3, replace=False):
         assert oracle.vertex_triangles(n, hs, hd, int(v)) == int(t[v])
+
+
+@pytest.mark.parametrize("kicks", [0, 1, 2])
+def test_probe_fallback_modes(tc, kicks, monkeypatch):
+    """Capping cuckoo evictions pushes keys into the stash (kicks 1-2, small tables) and past
+    it into the sorted binary-search fallback (kicks 0, tables over 32 keys); counts must
+    not change."""
+    monkeypatch.setenv("TC_TEST_MAX_KICKS", str(kicks))
+    cases = [pins.complete(40), pins.wheel(30), _hub_graph(1500, 9000, 3)]
+    s, d, n = graphgen.rmat(12, 16, 8)
+    cases.append((n, s.numpy(), d.numpy()))
+    for n, s, d in cases:
+        T, t = _oracle(n, s, d)
+        for order in (0, 1):
+            res, pv = _gpu(tc, n, s, d, order=order)
+            assert res.total == T
+            np.testing.assert_array_equal(pv, t)
