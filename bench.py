@@ -39,7 +39,36 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the count")
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before timing, run a plain device copy of this many MiB (3 times) so a "
+                         "counter profile can scale FETCH_SIZE/WRITE_SIZE by a known byte count")
     return ap.parse_args()
+
+
+COUNT_SOURCES = ["paper_1909_02127_amd/csrc/count.hip", "paper_1909_02127_amd/csrc/tc_hash.h",
+                 "paper_1909_02127_amd/csrc/tc_device.h"]
+
+
+def count_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in COUNT_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str):
+    """HBM bytes per count-kernel launch from the committed counter summary, or None when
+    the summary is missing or was taken from different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"count_kernel_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_digest") != count_source_digest():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def make_graph(spec, device):
@@ -123,6 +152,15 @@ def main():
         if ev:
             ev[3].record(stream)
 
+    if args.calibrate_copy_mib > 0:
+        a = torch.empty(args.calibrate_copy_mib << 18, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -190,7 +228,7 @@ def main():
                        "triangles_per_s": res.total / t_cnt_s},
         "roofline": {"bound": "hbm", "kernel": "count_kernel (tc_count_per_vertex)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(args.workload),
                      "algorithmic_bytes": alg["bytes"], "wedges": alg["wedges"]},
         "wall_s_timed": t_wall,
     }
