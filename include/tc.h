@@ -17,6 +17,8 @@
  *                        edge (u,w) (Alg. 1 "Store_none_tree_connection"), and
  *                        the reduction to |M|/|Q| (Alg. 1 return value).
  *   tc_count_per_vertex  the same, plus t(v) = number of triangles containing v.
+ *   tc_count_batched     per-graph counts of many graphs packed as one disjoint
+ *                        union, in one launch sequence.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -67,6 +69,22 @@ typedef int32_t tc_status;
 
 #define TC_ORDER_DEGREE 0 /* rank(v) = (deg(v), v) lexicographic: the default */
 #define TC_ORDER_ID 1     /* rank(v) = v: the paper's "destination id larger than source id" */
+
+#define TC_PROBE_AUTO 0   /* LDS cuckoo table of N+(u), with stash and sorted fallbacks */
+#define TC_PROBE_SORTED 1 /* binary search over the sorted N+(u) staged in LDS */
+
+/*
+ * Optional launch parameters of the count entry points (NULL = defaults).  They
+ * change only the speed, never the counts.
+ */
+typedef struct tc_tune {
+  int32_t small_max;     /* sources with 2 <= d+(u) <= small_max are handled by one wave,
+                            larger ones by a workgroup; 0 = default (64), at most 64 */
+  int32_t probe;         /* TC_PROBE_AUTO or TC_PROBE_SORTED */
+  int32_t blocks_per_cu; /* persistent grid = blocks_per_cu x compute units, capped at the
+                            occupancy limit; 0 = occupancy limit */
+  int32_t reserved;      /* must be 0 */
+} tc_tune;
 
 /* Read-only view of a CSR graph in device memory. */
 typedef struct tc_csr {
@@ -136,9 +154,11 @@ tc_status tc_orient(const tc_csr* sym, int32_t order, void* dag_row_ptr, int32_t
  *
  *   dag      oriented CSR (as written by tc_orient; any DAG works)
  *   total    device uint64[1] (written, not accumulated)
+ *   tune     launch parameters or NULL
  *   ws, ws_bytes  workspace; O(n) bytes.
  */
-tc_status tc_count(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_bytes, void* stream);
+tc_status tc_count(const tc_csr* dag, uint64_t* total, const tc_tune* tune, void* ws,
+                   size_t* ws_bytes, void* stream);
 
 /*
  * tc_count_per_vertex - per-vertex triangle counts t(v) and the total.
@@ -150,10 +170,39 @@ tc_status tc_count(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_byte
  *   dag         oriented CSR
  *   per_vertex  device uint64[dag->n] (written, not accumulated)
  *   total       device uint64[1] or NULL (written when non-NULL)
+ *   tune        launch parameters or NULL
  *   ws, ws_bytes  workspace; O(n) bytes.
  */
-tc_status tc_count_per_vertex(const tc_csr* dag, uint64_t* per_vertex, uint64_t* total, void* ws,
-                              size_t* ws_bytes, void* stream);
+tc_status tc_count_per_vertex(const tc_csr* dag, uint64_t* per_vertex, uint64_t* total,
+                              const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
+
+/*
+ * tc_count_batched - per-graph triangle counts of many independent graphs in
+ * one launch.
+ *
+ * The batch is the disjoint union of its graphs: graph g owns the vertex ids
+ * [vtx_off[g], vtx_off[g+1]) of one CSR (global ids, as a concatenation of the
+ * graphs with shifted ids gives).  Every triangle lies inside one graph, so
+ * counting the union with tc_count's method and adding each source's matches to
+ * the total of the source's graph gives every graph's |M|/|Q| (Alg. 1 return
+ * value) at once.  The union is oriented with tc_orient like any graph.
+ *
+ *   dag         oriented CSR of the union (n = vtx_off[num_graphs])
+ *   num_graphs  number of graphs G >= 0
+ *   vtx_off     device int64[G+1], vtx_off[0] = 0, non-decreasing; edges must not
+ *               cross graph boundaries.  Offsets outside [0, n] are clamped;
+ *               vertices outside every range add to no graph total.
+ *   totals      device uint64[G] (written): triangles of each graph
+ *   per_vertex  device uint64[n] or NULL: t(v) for every vertex of the union
+ *   total       device uint64[1] or NULL: triangles of the whole batch
+ *   tune        launch parameters or NULL
+ *   ws, ws_bytes  workspace; O(n) bytes.
+ * The call enqueues a fixed sequence of kernels and allocates nothing, so it can
+ * be captured in a HIP graph and replayed while its buffers stay in place.
+ */
+tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, const int64_t* vtx_off,
+                           uint64_t* totals, uint64_t* per_vertex, uint64_t* total,
+                           const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* tc_status_string(tc_status status);

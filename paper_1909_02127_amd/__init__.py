@@ -7,6 +7,7 @@ Counting on GPUs"): a C ABI library of hand-written gfx950 HIP kernels
 
 Importing the package requires the built library; there is no CPU fallback.
 """
-from ._lib import (TC_ORDER_DEGREE, TC_ORDER_ID, TcError, tc_build_csr, tc_count,  # noqa: F401
+from ._lib import (TC_ORDER_DEGREE, TC_ORDER_ID, TC_PROBE_AUTO, TC_PROBE_SORTED,  # noqa: F401
+                   TcError, make_tune, tc_build_csr, tc_count, tc_count_batched,
                    tc_count_per_vertex, tc_orient, tc_version)
 from .pipeline import Pipeline, Result, triangle_count  # noqa: F401

@@ -25,6 +25,9 @@ TC_ERR_UNSUPPORTED = 6
 TC_ORDER_DEGREE = 0
 TC_ORDER_ID = 1
 
+TC_PROBE_AUTO = 0
+TC_PROBE_SORTED = 1
+
 
 class TcError(RuntimeError):
     def __init__(self, status: int, message: str):
@@ -35,6 +38,27 @@ class TcError(RuntimeError):
 class tc_csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("offset_bytes", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class tc_tune(ctypes.Structure):
+    _fields_ = [("small_max", ctypes.c_int32), ("probe", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"small_max": self.small_max, "probe": self.probe,
+                "blocks_per_cu": self.blocks_per_cu}
+
+
+def make_tune(small_max: int = 0, probe: int = TC_PROBE_AUTO, blocks_per_cu: int = 0) -> tc_tune:
+    return tc_tune(small_max, probe, blocks_per_cu, 0)
+
+
+def _tune_ref(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        tune = make_tune(**tune)
+    return ctypes.byref(tune)
 
 
 def _load() -> ctypes.CDLL:
@@ -48,10 +72,13 @@ def _load() -> ctypes.CDLL:
     lib.tc_build_csr.argtypes = [i64, i64, p, p, i32, p, p, i64, p, p, sz, p]
     lib.tc_orient.restype = i32
     lib.tc_orient.argtypes = [csr, i32, p, p, i64, p, p, sz, p]
+    tune = ctypes.POINTER(tc_tune)
     lib.tc_count.restype = i32
-    lib.tc_count.argtypes = [csr, p, p, sz, p]
+    lib.tc_count.argtypes = [csr, p, tune, p, sz, p]
     lib.tc_count_per_vertex.restype = i32
-    lib.tc_count_per_vertex.argtypes = [csr, p, p, p, sz, p]
+    lib.tc_count_per_vertex.argtypes = [csr, p, p, tune, p, sz, p]
+    lib.tc_count_batched.restype = i32
+    lib.tc_count_batched.argtypes = [csr, i64, p, p, p, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
     lib.tc_status_string.argtypes = [i32]
     lib.tc_last_error.restype = ctypes.c_char_p
@@ -137,28 +164,47 @@ def tc_orient(n: int, row_ptr: torch.Tensor, col: torch.Tensor, order: int,
 
 def tc_count_workspace(n: int) -> int:
     csr = tc_csr(n, 4, None, None)
-    return _ws_query(LIB.tc_count, ctypes.byref(csr), None)
+    return _ws_query(LIB.tc_count, ctypes.byref(csr), None, None)
 
 
 def tc_count(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor, total: torch.Tensor,
-             ws: torch.Tensor, *, stream=None) -> None:
+             ws: torch.Tensor, *, tune=None, stream=None) -> None:
     csr = make_csr(n, dag_row_ptr, dag_col)
-    _ws_call(LIB.tc_count, ws, ctypes.byref(csr), _ptr(total), stream=stream)
+    _ws_call(LIB.tc_count, ws, ctypes.byref(csr), _ptr(total), _tune_ref(tune), stream=stream)
 
 
 def tc_count_per_vertex_workspace(n: int) -> int:
     csr = tc_csr(n, 4, None, None)
-    return _ws_query(LIB.tc_count_per_vertex, ctypes.byref(csr), None, None)
+    return _ws_query(LIB.tc_count_per_vertex, ctypes.byref(csr), None, None, None)
 
 
 def tc_count_per_vertex(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
                         per_vertex: torch.Tensor, total: torch.Tensor | None, ws: torch.Tensor, *,
-                        stream=None) -> None:
+                        tune=None, stream=None) -> None:
     if per_vertex.numel() != n:
         raise ValueError("per_vertex must hold n counts")
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_per_vertex, ws, ctypes.byref(csr), _ptr(per_vertex), _ptr(total),
-             stream=stream)
+             _tune_ref(tune), stream=stream)
+
+
+def tc_count_batched_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_count_batched, ctypes.byref(csr), 0, None, None, None, None, None)
+
+
+def tc_count_batched(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                     vtx_off: torch.Tensor, totals: torch.Tensor, ws: torch.Tensor, *,
+                     per_vertex: torch.Tensor | None = None, total: torch.Tensor | None = None,
+                     tune=None, stream=None) -> None:
+    g = vtx_off.numel() - 1
+    if vtx_off.dtype != torch.int64 or g < 0 or totals.numel() != g:
+        raise ValueError("vtx_off must be int64[G+1] and totals must hold G counts")
+    if per_vertex is not None and per_vertex.numel() != n:
+        raise ValueError("per_vertex must hold n counts")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count_batched, ws, ctypes.byref(csr), g, _ptr(vtx_off), _ptr(totals),
+             _ptr(per_vertex), _ptr(total), _tune_ref(tune), stream=stream)
 
 
 def tc_version() -> int:

@@ -68,9 +68,10 @@ __host__ __device__ constexpr int smem_bytes(bool pv) {
 }
 
 // Size class of a source by out-degree; -1 when it cannot close a wedge.
-__device__ __forceinline__ int source_class(int64_t d) {
+// Sources with d+ <= small_max (<= kSmallMax) take the one-wave path.
+__device__ __forceinline__ int source_class(int64_t d, int small_max) {
   if (d < 2) return -1;
-  if (d <= kSmallMax) return 7;
+  if (d <= small_max) return 7;
   if (d <= 128) return 6;
   if (d <= 256) return 5;
   if (d <= 512) return 4;
@@ -89,14 +90,14 @@ struct CountState {
 
 template <typename OffT>
 __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* __restrict__ row_ptr,
-                                                        CountState* __restrict__ st) {
+                                                        CountState* __restrict__ st, int small_max) {
   __shared__ int32_t h[kNumClasses];
   if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
   __syncthreads();
   int32_t mine[kNumClasses] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-    const int c = source_class((int64_t)(row_ptr[u + 1] - row_ptr[u]));
+    const int c = source_class((int64_t)(row_ptr[u + 1] - row_ptr[u]), small_max);
 #pragma unroll
     for (int k = 0; k < kNumClasses; ++k) mine[k] += (c == k);
   }
@@ -114,7 +115,7 @@ constexpr int kBinItems = 16;
 template <typename OffT>
 __global__ __launch_bounds__(256) void bin_write_kernel(int64_t n, const OffT* __restrict__ row_ptr,
                                                         CountState* __restrict__ st,
-                                                        int32_t* __restrict__ list) {
+                                                        int32_t* __restrict__ list, int small_max) {
   __shared__ int32_t lcnt[kNumClasses];
   __shared__ int32_t gbase[kNumClasses];
   if (threadIdx.x < kNumClasses) lcnt[threadIdx.x] = 0;
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(256) void bin_write_kernel(int64_t n, const OffT* _
 #pragma unroll
   for (int r = 0; r < kBinItems; ++r) {
     const int64_t u = base + r * 256 + threadIdx.x;
-    cls[r] = u < n ? source_class((int64_t)(row_ptr[u + 1] - row_ptr[u])) : -1;
+    cls[r] = u < n ? source_class((int64_t)(row_ptr[u + 1] - row_ptr[u]), small_max) : -1;
     lr[r] = cls[r] >= 0 ? atomicAdd(&lcnt[cls[r]], 1) : 0;
   }
   __syncthreads();
@@ -322,7 +323,7 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
 template <int Waves, bool PV, bool Wide, typename OffT>
 __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
                                    const int32_t* __restrict__ col, uint64_t* __restrict__ tv,
-                                   const Table& t, int max_keys, int max_kicks) {
+                                   const Table& t, int max_keys, int max_kicks, bool force_sorted) {
   const int lane = lane_id();
   const int gr = group_rank<Waves>();
   const int64_t beg = row_ptr[u];
@@ -361,7 +362,8 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
     group_sync<Waves>();
     const int stash_raw = t.meta[0];
     sl.stash_n = stash_raw < kStash ? stash_raw : kStash;
-    const int mode = t.meta[1] ? kModeSorted : (sl.stash_n ? kModeStash : kModeCuckoo);
+    const int mode =
+        (force_sorted || t.meta[1]) ? kModeSorted : (sl.stash_n ? kModeStash : kModeCuckoo);
     uint64_t src_hits;
     if (mode == kModeCuckoo)
       src_hits = scan_middles<Waves, PV, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl);
@@ -393,15 +395,24 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
   return wave_hits;
 }
 
+// Runtime parameters of one count launch.
+struct CountArgs {
+  const int32_t* gid;  // batched mode: graph of each vertex (-1: none); else null
+  uint64_t* totals;    // batched mode: per-graph totals; else null
+  int max_kicks;
+  int force_sorted;
+};
+
 // Persistent count kernel: workgroup-mode sources first (dynamic cursor), then
-// wave-mode sources (static round robin over all waves of the grid).
+// wave-mode sources (static round robin over all waves of the grid).  In batched
+// mode each source's hits are also added to the total of its graph.
 template <bool PV, bool Wide, typename OffT>
 __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
                                                        const int32_t* __restrict__ list,
                                                        CountState* __restrict__ st,
                                                        uint64_t* __restrict__ total,
-                                                       uint64_t* __restrict__ tv, int max_kicks) {
+                                                       uint64_t* __restrict__ tv, CountArgs args) {
   __shared__ __align__(16) char smem[smem_bytes(PV)];
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
@@ -417,38 +428,96 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ 
     const int32_t idx = big.meta[2];
     __syncthreads();
     if (idx >= n_large) break;
-    hits += process_source<kWavesPerBlock, PV, Wide, OffT>(list[idx], row_ptr, col, tv, big, kChunk,
-                                                           max_kicks);
+    const int32_t u = list[idx];
+    const uint64_t h = process_source<kWavesPerBlock, PV, Wide, OffT>(
+        u, row_ptr, col, tv, big, kChunk, args.max_kicks, args.force_sorted);
+    hits += h;
+    if (args.totals && h && lane == 0) {
+      const int32_t g = args.gid[u];
+      if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
+    }
   }
 
   const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide, kSmallMax);
   const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave; i < n_small; i += waves) {
-    hits += process_source<1, PV, Wide, OffT>(list[n_large + i], row_ptr, col, tv, mine, kSmallMax,
-                                              max_kicks);
+    const int32_t u = list[n_large + i];
+    const uint64_t h = process_source<1, PV, Wide, OffT>(u, row_ptr, col, tv, mine, kSmallMax,
+                                                         args.max_kicks, args.force_sorted);
+    hits += h;
+    if (args.totals && h && lane == 0) {
+      const int32_t g = args.gid[u];
+      if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
+    }
   }
   if (lane == 0 && hits) atomicAdd((unsigned long long*)total, (unsigned long long)hits);
+}
+
+// Graph id of every vertex of a batch: -1 first, then graph g writes its range
+// [vtx_off[g], vtx_off[g+1]) clamped to [0, n), so a malformed offset table can
+// only leave vertices unattributed, never write out of bounds.
+__global__ void graph_map_kernel(int64_t num_graphs, const int64_t* __restrict__ vtx_off, int64_t n,
+                                 int32_t* __restrict__ gid) {
+  for (int64_t g = blockIdx.x; g < num_graphs; g += gridDim.x) {
+    int64_t b = vtx_off[g], e = vtx_off[g + 1];
+    b = b < 0 ? 0 : (b > n ? n : b);
+    e = e < b ? b : (e > n ? n : e);
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) gid[i] = (int32_t)g;
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t len, int32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = v;
 }
 
 struct CountLayout {
   CountState* st;
   int32_t* list;
   uint64_t* total_scratch;
+  int32_t* gid;  // batched mode only
   size_t bytes;
 };
 
-CountLayout carve_count(void* ws, int64_t n) {
+CountLayout carve_count(void* ws, int64_t n, bool batched) {
   Carver c(ws);
   CountLayout L;
   L.st = c.take<CountState>(1);
   L.list = c.take<int32_t>(n);
   L.total_scratch = c.take<uint64_t>(1);
+  L.gid = batched ? c.take<int32_t>(n) : nullptr;
   L.bytes = c.used();
   return L;
 }
 
+struct Tune {
+  int small_max;
+  int force_sorted;
+  int blocks_per_cu;  // 0: occupancy limit
+};
+
+tc_status read_tune(const tc_tune* tune, Tune* out) {
+  out->small_max = kSmallMax;
+  out->force_sorted = 0;
+  out->blocks_per_cu = 0;
+  if (!tune) return TC_OK;
+  if (tune->reserved != 0) return fail(TC_ERR_INVALID_ARG, "tc_tune.reserved must be 0");
+  if (tune->small_max != 0) {
+    if (tune->small_max < 1 || tune->small_max > kSmallMax)
+      return fail(TC_ERR_INVALID_ARG, "tc_tune.small_max must be 0 or in [1, %d]", kSmallMax);
+    out->small_max = tune->small_max;
+  }
+  if (tune->probe != TC_PROBE_AUTO && tune->probe != TC_PROBE_SORTED)
+    return fail(TC_ERR_INVALID_ARG, "unknown tc_tune.probe %d", tune->probe);
+  out->force_sorted = tune->probe == TC_PROBE_SORTED;
+  if (tune->blocks_per_cu < 0 || tune->blocks_per_cu > 64)
+    return fail(TC_ERR_INVALID_ARG, "tc_tune.blocks_per_cu must be in [0, 64]");
+  out->blocks_per_cu = tune->blocks_per_cu;
+  return TC_OK;
+}
+
 template <bool PV, bool Wide, typename OffT>
-int count_grid() {
+int count_grid(int blocks_per_cu) {
   static int cached[64] = {0};
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -460,31 +529,45 @@ int count_grid() {
         per_cu <= 0) {
       per_cu = 2;
     }
-    cached[dev] = per_cu * device_cu_count();
+    cached[dev] = per_cu;
   }
-  return cached[dev];
+  const int per_cu = blocks_per_cu > 0 && blocks_per_cu < cached[dev] ? blocks_per_cu : cached[dev];
+  return per_cu * device_cu_count();
 }
 
 template <bool PV, typename OffT>
 tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_t* total,
-                     uint64_t* tv, const CountLayout& L, hipStream_t s) {
+                     uint64_t* tv, int64_t num_graphs, const int64_t* vtx_off, uint64_t* totals,
+                     const Tune& tune, const CountLayout& L, hipStream_t s) {
   uint64_t* tot = total ? total : L.total_scratch;
+  CountArgs args;
+  args.gid = nullptr;
+  args.totals = nullptr;
+  args.force_sorted = tune.force_sorted;
   // Test hook: TC_TEST_MAX_KICKS caps cuckoo evictions so that tests can drive
   // keys into the stash (and past it, into the sorted fallback).
-  int max_kicks = kMaxKicks;
-  if (const char* env = getenv("TC_TEST_MAX_KICKS")) max_kicks = atoi(env);
+  args.max_kicks = kMaxKicks;
+  if (const char* env = getenv("TC_TEST_MAX_KICKS")) args.max_kicks = atoi(env);
   init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
   if (PV) zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(tv, n);
+  if (totals) {
+    zero_u64_kernel<<<grid_for(num_graphs, 256, 1024), 256, 0, s>>>(totals, num_graphs);
+    fill_i32_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(L.gid, n, -1);
+    if (num_graphs > 0)
+      graph_map_kernel<<<grid_for(num_graphs, 1, 8192), 256, 0, s>>>(num_graphs, vtx_off, n, L.gid);
+    args.gid = L.gid;
+    args.totals = totals;
+  }
   if (n > 0) {
-    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st);
+    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st, tune.small_max);
     bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
-        n, row_ptr, L.st, L.list);
+        n, row_ptr, L.st, L.list, tune.small_max);
     if (n <= (int64_t(1) << 24))
-      count_kernel<PV, false, OffT><<<count_grid<PV, false, OffT>(), kBlock, 0, s>>>(
-          row_ptr, col, L.list, L.st, tot, tv, max_kicks);
+      count_kernel<PV, false, OffT><<<count_grid<PV, false, OffT>(tune.blocks_per_cu), kBlock, 0, s>>>(
+          row_ptr, col, L.list, L.st, tot, tv, args);
     else
-      count_kernel<PV, true, OffT><<<count_grid<PV, true, OffT>(), kBlock, 0, s>>>(
-          row_ptr, col, L.list, L.st, tot, tv, max_kicks);
+      count_kernel<PV, true, OffT><<<count_grid<PV, true, OffT>(tune.blocks_per_cu), kBlock, 0, s>>>(
+          row_ptr, col, L.list, L.st, tot, tv, args);
   }
   return check_hip(hipGetLastError(), "tc_count launch");
 }
@@ -498,34 +581,57 @@ tc_status check_dag(const tc_csr* dag) {
   return TC_OK;
 }
 
+// Shared front end of the three count entry points.  batched: num_graphs /
+// vtx_off / totals are meaningful.
 template <bool PV>
-tc_status count_dispatch(const tc_csr* dag, uint64_t* total, uint64_t* tv, void* ws,
-                         size_t* ws_bytes, void* stream) {
+tc_status count_dispatch(const tc_csr* dag, uint64_t* total, uint64_t* tv, bool batched,
+                         int64_t num_graphs, const int64_t* vtx_off, uint64_t* totals,
+                         const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream) {
   tc_status st = check_dag(dag);
   if (st != TC_OK) return st;
-  if (workspace_query(ws, ws_bytes, carve_count(nullptr, dag->n).bytes, &st)) return st;
-  if (!dag->row_ptr || (PV && dag->n > 0 && !tv) || (!PV && !total))
+  Tune t;
+  if ((st = read_tune(tune, &t)) != TC_OK) return st;
+  if (batched && (num_graphs < 0 || num_graphs > INT32_MAX))
+    return fail(TC_ERR_INVALID_ARG, "num_graphs=%lld out of range", (long long)num_graphs);
+  if (workspace_query(ws, ws_bytes, carve_count(nullptr, dag->n, batched).bytes, &st)) return st;
+  if (!dag->row_ptr || (PV && dag->n > 0 && !tv) || (!PV && !batched && !total) ||
+      (batched && num_graphs > 0 && (!vtx_off || !totals)))
     return fail(TC_ERR_INVALID_ARG, "null device pointer");
-  const CountLayout L = carve_count(ws, dag->n);
+  const CountLayout L = carve_count(ws, dag->n, batched);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  uint64_t* gt = batched && num_graphs > 0 ? totals : nullptr;
   if (dag->offset_bytes == 4)
     st = count_impl<PV, int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col, total,
-                                 tv, L, s);
+                                 tv, num_graphs, vtx_off, gt, t, L, s);
   else
     st = count_impl<PV, int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, total,
-                                 tv, L, s);
+                                 tv, num_graphs, vtx_off, gt, t, L, s);
   return st == TC_OK ? ok() : st;
 }
 
 }  // namespace
 }  // namespace tc
 
-extern "C" tc_status tc_count(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_bytes,
-                              void* stream) {
-  return tc::count_dispatch<false>(dag, total, nullptr, ws, ws_bytes, stream);
+extern "C" tc_status tc_count(const tc_csr* dag, uint64_t* total, const tc_tune* tune, void* ws,
+                              size_t* ws_bytes, void* stream) {
+  return tc::count_dispatch<false>(dag, total, nullptr, false, 0, nullptr, nullptr, tune, ws,
+                                   ws_bytes, stream);
 }
 
 extern "C" tc_status tc_count_per_vertex(const tc_csr* dag, uint64_t* per_vertex, uint64_t* total,
-                                         void* ws, size_t* ws_bytes, void* stream) {
-  return tc::count_dispatch<true>(dag, total, per_vertex, ws, ws_bytes, stream);
+                                         const tc_tune* tune, void* ws, size_t* ws_bytes,
+                                         void* stream) {
+  return tc::count_dispatch<true>(dag, total, per_vertex, false, 0, nullptr, nullptr, tune, ws,
+                                  ws_bytes, stream);
+}
+
+extern "C" tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, const int64_t* vtx_off,
+                                      uint64_t* totals, uint64_t* per_vertex, uint64_t* total,
+                                      const tc_tune* tune, void* ws, size_t* ws_bytes,
+                                      void* stream) {
+  if (per_vertex)
+    return tc::count_dispatch<true>(dag, total, per_vertex, true, num_graphs, vtx_off, totals, tune,
+                                    ws, ws_bytes, stream);
+  return tc::count_dispatch<false>(dag, total, nullptr, true, num_graphs, vtx_off, totals, tune, ws,
+                                   ws_bytes, stream);
 }

@@ -60,13 +60,14 @@ class Pipeline:
         _lib.tc_orient(self.n, self.row_ptr, self.col, self.order, self.dag_ptr, self.dag_col,
                        self.m, self.ws_orient, stream=stream)
 
-    def count(self, stream=None) -> None:
-        _lib.tc_count(self.n, self.dag_ptr, self.dag_col, self.total, self.ws_count, stream=stream)
+    def count(self, stream=None, tune=None) -> None:
+        _lib.tc_count(self.n, self.dag_ptr, self.dag_col, self.total, self.ws_count, tune=tune,
+                      stream=stream)
 
-    def count_per_vertex(self, stream=None) -> None:
+    def count_per_vertex(self, stream=None, tune=None) -> None:
         pv = self.per_vertex[: self.n]
         _lib.tc_count_per_vertex(self.n, self.dag_ptr, self.dag_col, pv, self.total,
-                                 self.ws_count, stream=stream)
+                                 self.ws_count, tune=tune, stream=stream)
 
     def enqueue(self, src, dst, *, per_vertex: bool = False, stream=None) -> None:
         self.build(src, dst, stream)
