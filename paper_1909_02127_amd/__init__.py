@@ -5,9 +5,27 @@ Counting on GPUs"): a C ABI library of hand-written gfx950 HIP kernels
     from paper_1909_02127_amd import triangle_count
     res = triangle_count(src, dst, n, per_vertex=True)   # src/dst: int32 CUDA tensors
 
-Importing the package requires the built library; there is no CPU fallback.
+The library is loaded on first use of any of the names below, so the build
+module (paper_1909_02127_amd.build) imports without it; using the package
+without a built libtc.so raises ImportError (there is no CPU fallback).
 """
-from ._lib import (TC_ORDER_DEGREE, TC_ORDER_ID, TC_PROBE_AUTO, TC_PROBE_SORTED,  # noqa: F401
-                   TcError, make_tune, tc_build_csr, tc_count, tc_count_batched,
-                   tc_count_per_vertex, tc_orient, tc_version)
-from .pipeline import Pipeline, Result, triangle_count  # noqa: F401
+import importlib
+
+_EXPORTS = {
+    "TC_ORDER_DEGREE": "_lib", "TC_ORDER_ID": "_lib", "TC_PROBE_AUTO": "_lib",
+    "TC_PROBE_SORTED": "_lib", "TcError": "_lib", "make_tune": "_lib", "tc_build_csr": "_lib",
+    "tc_count": "_lib", "tc_count_batched": "_lib", "tc_count_per_vertex": "_lib",
+    "tc_orient": "_lib", "tc_version": "_lib",
+    "Pipeline": "pipeline", "Result": "pipeline", "triangle_count": "pipeline",
+}
+
+__all__ = sorted(_EXPORTS)
+
+
+def __getattr__(name):
+    if name in _EXPORTS:
+        mod = importlib.import_module(f".{_EXPORTS[name]}", __name__)
+        value = getattr(mod, name)
+        globals()[name] = value
+        return value
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")

@@ -46,6 +46,9 @@ constexpr int kSmallSide = 128;  // slots per cuckoo half for kSmallMax keys
 constexpr int kStash = 32;
 constexpr int kMaxKicks = 48;
 constexpr int kUnroll = 4;       // 64-wide loads in flight per wave while streaming N+(v)
+constexpr int kShortMax = 64;    // middles with d+(v) < kShortMax may be walked as one concatenation
+constexpr int kShortMinLists = 4;  // ... when a batch of 64 middles holds at least this many
+constexpr int kWin = 2;          // 64-wide windows per step of that walk
 constexpr int32_t kEmpty = -1;
 constexpr int32_t kNoKey = -2;  // probe value of an inactive lane: never stored
 constexpr int kNumClasses = 8;  // 0..6: workgroup classes by size (largest first), 7: small
@@ -66,6 +69,18 @@ __host__ __device__ constexpr int smem_bytes(bool pv) {
              ? group_bytes(pv)
              : kWavesPerBlock * small_bytes_per_wave(pv);
 }
+// Per-wave scratch of the short-list walk: segment-start markers (+ hit counters).
+__host__ __device__ constexpr int seg_bytes_per_wave(bool pv) {
+  return kWin * kWave * 4 + (pv ? kWave * 4 : 0);
+}
+__host__ __device__ constexpr int smem_total(bool pv) {
+  return smem_bytes(pv) + kWavesPerBlock * seg_bytes_per_wave(pv);
+}
+
+struct WaveScratch {
+  int32_t* mark;    // [kWin * kWave] segment starting at each position of the window, or -1
+  uint32_t* shits;  // [kWave] hits per segment (per-vertex mode)
+};
 
 // Size class of a source by out-degree; -1 when it cannot close a wedge.
 // Sources with d+ <= small_max (<= kSmallMax) take the one-wave path.
@@ -276,12 +291,76 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
   return hv;
 }
 
+// The short out-lists of up to 64 middles held one per lane (len = 0 for lanes
+// without one) walked as one concatenation, kWin * 64 wedges per step, so a
+// wave is not spent on a single short list.  Lane l's segment is the last lane
+// whose list starts at or before its position: each list's first position is
+// marked in LDS and propagated with a wave max-scan.  The marker array holds -1
+// between walks (the writer clears its own entry after the step; a wave's LDS
+// operations complete in program order).  Returns the hits (uniform).
+template <bool PV, int Mode, bool Wide, typename OffT>
+__device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
+                                               const int32_t* __restrict__ col, const Table& t,
+                                               const Slice& sl, const WaveScratch& ws,
+                                               uint64_t* __restrict__ tv) {
+  const int lane = lane_id();
+  const int32_t incl = wave_inclusive_sum32(len);
+  const int32_t start = incl - len;
+  const int32_t total = read_lane(incl, kWave - 1);
+  if (PV) ws.shits[lane] = 0;
+  int32_t carry = -1;
+  uint32_t hv = 0;
+  for (int32_t base = 0; base < total; base += kWin * kWave) {
+    const bool marks = len > 0 && start >= base && start < base + kWin * kWave;
+    if (marks) ws.mark[start - base] = lane;
+    wave_sync();
+    int32_t seg[kWin];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      int32_t sk = wave_inclusive_max32(ws.mark[k * kWave + lane]);
+      sk = sk > carry ? sk : carry;
+      carry = read_lane(sk, kWave - 1);
+      seg[k] = sk;
+    }
+    wave_sync();
+    if (marks) ws.mark[start - base] = -1;
+    int32_t w[kWin];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      const int32_t pos = base + k * kWave + lane;
+      const int32_t sk = seg[k] < 0 ? 0 : seg[k];
+      const int32_t off = pos - __shfl(start, sk, kWave);
+      const int32_t slen = __shfl(len, sk, kWave);
+      const OffT sb = __shfl(vb, sk, kWave);
+      // pos < total implies 0 <= off < slen; the check also keeps every read in bounds
+      w[k] = (pos < total && (uint32_t)off < (uint32_t)slen) ? col[sb + off] : kNoKey;
+    }
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      if (base + k * kWave < total) {
+        const bool hit = probe<PV, Mode, Wide>(t, sl, w[k]);
+        hv += popc(ballot(hit));
+        if (PV && hit) atomicAdd(&ws.shits[seg[k]], 1u);
+      }
+    }
+  }
+  if (PV) {
+    wave_sync();
+    const uint32_t c = ws.shits[lane];
+    if (c) atomicAdd((unsigned long long*)&tv[v], (unsigned long long)c);
+  }
+  return hv;
+}
+
 // All middles v of source u handled by this wave: v = N+(u)[i] for
-// i = gwave, gwave + Waves, ...; 64 of them are prefetched per batch.
+// i = gwave, gwave + Waves, ...; 64 of them are prefetched per batch.  Lists of
+// kShortMax or more ids are streamed one at a time; shorter ones are walked
+// together by scan_short.  Empty lists add nothing (1-look-ahead).
 template <int Waves, bool PV, int Mode, bool Wide, typename OffT>
 __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
                                  const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                 uint64_t* __restrict__ tv, const Table& t, const Slice& sl) {
+                                 uint64_t* __restrict__ tv, const Table& t, const Slice& sl,
+                                 const WaveScratch& ws) {
   const int lane = lane_id();
   const int gwave = Waves == 1 ? 0 : (int)threadIdx.x / kWave;
   uint64_t src_hits = 0;
@@ -294,10 +373,14 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
       vb = row_ptr[v];
       ve = row_ptr[v + 1];
     }
-    const int64_t rem = d - i0 - gwave;
-    const int64_t cnt = rem <= 0 ? 0 : (rem + Waves - 1) / Waves;
-    const int nb = cnt < kWave ? (int)cnt : kWave;
-    for (int j = 0; j < nb; ++j) {
+    const int64_t len = (int64_t)(ve - vb);
+    // Only the main probe mode walks short lists together (keeps the rare modes small).
+    const uint64_t shorts = Mode == kModeCuckoo ? ballot(len > 0 && len < kShortMax) : 0;
+    const bool walk_short = popc(shorts) >= kShortMinLists;
+    uint64_t longs = walk_short ? ballot(len >= kShortMax) : ballot(len > 0);
+    while (longs) {
+      const int j = __builtin_ctzll(longs);
+      longs &= longs - 1;
       int64_t jb, je;
       if (sizeof(OffT) == 4) {
         jb = read_lane((int32_t)vb, j);
@@ -306,13 +389,17 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
         jb = read_lane64((int64_t)vb, j);
         je = read_lane64((int64_t)ve, j);
       }
-      if (je <= jb) continue;  // 1-look-ahead: a middle with no out-neighbour adds nothing
       const uint32_t hv = scan_list<PV, Mode, Wide>(col + jb, (int)(je - jb), t, sl);
       src_hits += hv;
       if (PV && hv && lane == 0) {
         const int32_t vj = read_lane(v, j);
         atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
       }
+    }
+    if (walk_short) {
+      const bool is_short = len > 0 && len < kShortMax;
+      src_hits += scan_short<PV, Mode, Wide, OffT>(v, vb, is_short ? (int32_t)len : 0, col, t, sl,
+                                                   ws, tv);
     }
   }
   return src_hits;
@@ -323,7 +410,8 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
 template <int Waves, bool PV, bool Wide, typename OffT>
 __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
                                    const int32_t* __restrict__ col, uint64_t* __restrict__ tv,
-                                   const Table& t, int max_keys, int max_kicks, bool force_sorted) {
+                                   const Table& t, const WaveScratch& ws, int max_keys,
+                                   int max_kicks, bool force_sorted) {
   const int lane = lane_id();
   const int gr = group_rank<Waves>();
   const int64_t beg = row_ptr[u];
@@ -366,11 +454,11 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
         (force_sorted || t.meta[1]) ? kModeSorted : (sl.stash_n ? kModeStash : kModeCuckoo);
     uint64_t src_hits;
     if (mode == kModeCuckoo)
-      src_hits = scan_middles<Waves, PV, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl);
+      src_hits = scan_middles<Waves, PV, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws);
     else if (mode == kModeStash)
-      src_hits = scan_middles<Waves, PV, kModeStash, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl);
+      src_hits = scan_middles<Waves, PV, kModeStash, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws);
     else
-      src_hits = scan_middles<Waves, PV, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl);
+      src_hits = scan_middles<Waves, PV, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws);
     wave_hits += src_hits;
     if (PV) {
       if (src_hits && lane == 0) atomicAdd((unsigned long long*)&tv[u], (unsigned long long)src_hits);
@@ -413,9 +501,18 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ 
                                                        CountState* __restrict__ st,
                                                        uint64_t* __restrict__ total,
                                                        uint64_t* __restrict__ tv, CountArgs args) {
-  __shared__ __align__(16) char smem[smem_bytes(PV)];
+  __shared__ __align__(16) char smem[smem_total(PV)];
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
+  WaveScratch ws;
+  {
+    char* p = smem + smem_bytes(PV) + wave * seg_bytes_per_wave(PV);
+    ws.mark = reinterpret_cast<int32_t*>(p);
+    ws.shits = reinterpret_cast<uint32_t*>(p + kWin * kWave * 4);
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) ws.mark[k * kWave + lane] = -1;
+    wave_sync();
+  }
   int32_t n_large = 0;
   for (int c = 0; c < kNumClasses - 1; ++c) n_large += st->class_count[c];
   const int32_t n_small = st->class_count[kNumClasses - 1];
@@ -430,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ 
     if (idx >= n_large) break;
     const int32_t u = list[idx];
     const uint64_t h = process_source<kWavesPerBlock, PV, Wide, OffT>(
-        u, row_ptr, col, tv, big, kChunk, args.max_kicks, args.force_sorted);
+        u, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted);
     hits += h;
     if (args.totals && h && lane == 0) {
       const int32_t g = args.gid[u];
@@ -442,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ 
   const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave; i < n_small; i += waves) {
     const int32_t u = list[n_large + i];
-    const uint64_t h = process_source<1, PV, Wide, OffT>(u, row_ptr, col, tv, mine, kSmallMax,
+    const uint64_t h = process_source<1, PV, Wide, OffT>(u, row_ptr, col, tv, mine, ws, kSmallMax,
                                                          args.max_kicks, args.force_sorted);
     hits += h;
     if (args.totals && h && lane == 0) {

@@ -55,6 +55,26 @@ __device__ __forceinline__ int64_t wave_inclusive_sum(int64_t x) {
   return x;
 }
 
+__device__ __forceinline__ int32_t wave_inclusive_sum32(int32_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int32_t wave_inclusive_max32(int32_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x = x > y ? x : y;
+  }
+  return x;
+}
+
 __device__ __forceinline__ int64_t wave_sum(int64_t x) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);

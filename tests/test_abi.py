@@ -72,3 +72,19 @@ def test_host_side_argument_errors_need_no_gpu():
     st = _lib.LIB.tc_orient(ctypes.byref(csr), 7, None, None, 0, None, None, ctypes.byref(size), None)
     assert st == _lib.TC_ERR_INVALID_ARG
     assert "order" in _lib.LIB.tc_last_error().decode()
+
+
+def test_fresh_checkout_builds_without_a_library(tmp_path):
+    """The build module must import before libtc.so exists; the binding must then refuse."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = os.path.join(ROOT, "paper_1909_02127_amd")
+    dst = tmp_path / "paper_1909_02127_amd"
+    shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__"))
+    code = ("import paper_1909_02127_amd.build as b\n"
+            "import paper_1909_02127_amd as tc\n"
+            "try:\n    tc.triangle_count\nexcept ImportError:\n    print('refused')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert "refused" in r.stdout
