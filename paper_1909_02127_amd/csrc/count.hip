@@ -18,7 +18,8 @@
 // multiplicative hashes into two halves of the table, load <= 0.4), so a probe
 // is exactly two LDS reads with no data-dependent loop.  Keys that do not settle
 // within kMaxKicks evictions go to a small stash; if the stash overflows the
-// group falls back to binary search over the sorted N+(u) it also keeps in LDS.
+// group falls back to binary search: it refills the (then unused) slot array
+// with N+(u), which is sorted, from global memory.
 //
 // Load balance: sources are binned by d+(u); sources with d+(u) > kSmallMax are
 // handed out largest class first through a global cursor, one workgroup each
@@ -33,6 +34,8 @@
 #include "tc_host.h"
 
 #include <stdlib.h>
+
+#include <algorithm>
 
 namespace tc {
 namespace {
@@ -56,13 +59,13 @@ constexpr int kNumClasses = 8;  // 0..6: workgroup classes by size (largest firs
 // Probe modes, fixed per table slice after it is built.
 constexpr int kModeCuckoo = 0;  // every key sits in one of its two cuckoo slots
 constexpr int kModeStash = 1;   // plus up to kStash keys in the stash
-constexpr int kModeSorted = 2;  // stash overflowed: binary search the sorted keys
+constexpr int kModeSorted = 2;  // stash overflowed: binary search the keys, sorted in the slots
 
 __host__ __device__ constexpr int small_bytes_per_wave(bool pv) {
-  return (2 * kSmallSide) * 4 * (pv ? 2 : 1) + kSmallMax * 4 + kStash * 8 + 16;
+  return (2 * kSmallSide) * 4 * (pv ? 2 : 1) + kStash * 8 + 16;
 }
 __host__ __device__ constexpr int group_bytes(bool pv) {
-  return (2 * kSideMax) * 4 * (pv ? 2 : 1) + kChunk * 4 + kStash * 8 + 16;
+  return (2 * kSideMax) * 4 * (pv ? 2 : 1) + kStash * 8 + 16;
 }
 __host__ __device__ constexpr int smem_bytes(bool pv) {
   return group_bytes(pv) > kWavesPerBlock * small_bytes_per_wave(pv)
@@ -100,8 +103,11 @@ struct CountState {
   int32_t class_count[kNumClasses];
   int32_t class_cursor[kNumClasses];
   int32_t large_cursor;
-  int32_t pad[7];
+  int32_t small_cursor;
+  int32_t pad[6];
 };
+
+constexpr int kSmallGrab = 16;  // wave-mode sources a wave takes per cursor step
 
 template <typename OffT>
 __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* __restrict__ row_ptr,
@@ -170,25 +176,23 @@ __global__ void zero_u64_kernel(uint64_t* p, int64_t len) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
 }
 
-// One LDS cuckoo table (plus stash and the sorted keys it was built from).
+// One LDS cuckoo table (plus its stash).  In the sorted mode slot[0, keys)
+// holds the keys in ascending order instead.
 struct Table {
   int32_t* slot;       // [2 * side]; halves [0, side) and [side, 2 * side)
   uint32_t* cnt;       // [2 * side] hit counters (per-vertex mode only)
-  int32_t* sorted;     // [keys] the keys in ascending order
   int32_t* stash;      // [kStash]
   uint32_t* stash_cnt; // [kStash]
   int32_t* meta;       // [0] stash entries, [1] overflow flag, [2] broadcast slot
 };
 
 template <bool PV>
-__device__ __forceinline__ Table table_at(char* base, int side_max, int keys_max) {
+__device__ __forceinline__ Table table_at(char* base, int side_max) {
   Table t;
   t.slot = reinterpret_cast<int32_t*>(base);
   char* p = base + 2 * side_max * 4;
   t.cnt = reinterpret_cast<uint32_t*>(p);
   if (PV) p += 2 * side_max * 4;
-  t.sorted = reinterpret_cast<int32_t*>(p);
-  p += keys_max * 4;
   t.stash = reinterpret_cast<int32_t*>(p);
   p += kStash * 4;
   t.stash_cnt = reinterpret_cast<uint32_t*>(p);
@@ -230,14 +234,14 @@ __device__ __forceinline__ bool probe(const Table& t, const Slice& sl, int32_t w
     int lo = 0, len = sl.keys;
     while (len > 0) {
       const int half = len >> 1;
-      if (t.sorted[lo + half] < w) {
+      if (t.slot[lo + half] < w) {
         lo += half + 1;
         len -= half + 1;
       } else {
         len = half;
       }
     }
-    const bool hit = lo < sl.keys && t.sorted[lo] == w;
+    const bool hit = lo < sl.keys && t.slot[lo] == w;
     if (PV && hit) atomicAdd(&t.cnt[lo], 1u);
     return hit;
   }
@@ -433,7 +437,6 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
     group_sync<Waves>();
     for (int i = gr; i < sl.keys; i += Waves * kWave) {
       int32_t cur = nbrs[c0 + i];
-      t.sorted[i] = cur;
       int hs = 0;
       for (int kick = 0; kick < max_kicks && cur != kEmpty; ++kick) {
         const uint32_t s = hs ? (uint32_t)sl.side + hash_b<Wide>(cur, sl.shift)
@@ -452,6 +455,12 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
     sl.stash_n = stash_raw < kStash ? stash_raw : kStash;
     const int mode =
         (force_sorted || t.meta[1]) ? kModeSorted : (sl.stash_n ? kModeStash : kModeCuckoo);
+    if (mode == kModeSorted) {
+      // N+(u) rows are sorted: copy the slice into the slot array for binary search
+      group_sync<Waves>();
+      for (int i = gr; i < sl.keys; i += Waves * kWave) t.slot[i] = nbrs[c0 + i];
+      group_sync<Waves>();
+    }
     uint64_t src_hits;
     if (mode == kModeCuckoo)
       src_hits = scan_middles<Waves, PV, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws);
@@ -466,7 +475,7 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
       if (mode == kModeSorted) {
         for (int p = gr; p < sl.keys; p += Waves * kWave) {
           const uint32_t c = t.cnt[p];
-          if (c) atomicAdd((unsigned long long*)&tv[t.sorted[p]], (unsigned long long)c);
+          if (c) atomicAdd((unsigned long long*)&tv[t.slot[p]], (unsigned long long)c);
         }
       } else {
         for (int s = gr; s < 2 * sl.side; s += Waves * kWave) {
@@ -491,11 +500,13 @@ struct CountArgs {
   int force_sorted;
 };
 
-// Persistent count kernel: workgroup-mode sources first (dynamic cursor), then
-// wave-mode sources (static round robin over all waves of the grid).  In batched
-// mode each source's hits are also added to the total of its graph.
+// Persistent count kernel: workgroup-mode sources first, then wave-mode sources,
+// both handed out through global cursors (a workgroup takes one large source, a
+// wave kSmallGrab small ones per step), so the run time does not depend on how
+// many of the launched workgroups are resident at once.  In batched mode each
+// source's hits are also added to the total of its graph.
 template <bool PV, bool Wide, typename OffT>
-__global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ row_ptr,
+__global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
                                                        const int32_t* __restrict__ list,
                                                        CountState* __restrict__ st,
@@ -518,13 +529,10 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ 
   const int32_t n_small = st->class_count[kNumClasses - 1];
   uint64_t hits = 0;
 
-  const Table big = table_at<PV>(smem, kSideMax, kChunk);
-  for (;;) {
-    if (threadIdx.x == 0) big.meta[2] = atomicAdd(&st->large_cursor, 1);
-    __syncthreads();
-    const int32_t idx = big.meta[2];
-    __syncthreads();
-    if (idx >= n_large) break;
+  // First item of each workgroup / wave is static (its id); later ones come from
+  // the cursors, offset past the static round, so small launches need few atomics.
+  const Table big = table_at<PV>(smem, kSideMax);
+  for (int32_t idx = blockIdx.x; idx < n_large;) {
     const int32_t u = list[idx];
     const uint64_t h = process_source<kWavesPerBlock, PV, Wide, OffT>(
         u, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted);
@@ -533,19 +541,31 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const OffT* __restrict__ 
       const int32_t g = args.gid[u];
       if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
     }
+    if (threadIdx.x == 0) big.meta[2] = (int32_t)gridDim.x + atomicAdd(&st->large_cursor, 1);
+    __syncthreads();
+    idx = big.meta[2];
+    __syncthreads();
   }
 
-  const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide, kSmallMax);
-  const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave; i < n_small; i += waves) {
-    const int32_t u = list[n_large + i];
-    const uint64_t h = process_source<1, PV, Wide, OffT>(u, row_ptr, col, tv, mine, ws, kSmallMax,
-                                                         args.max_kicks, args.force_sorted);
-    hits += h;
-    if (args.totals && h && lane == 0) {
-      const int32_t g = args.gid[u];
-      if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
+  const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide);
+  const int32_t waves = (int32_t)gridDim.x * kWavesPerBlock;
+  for (int32_t first = ((int32_t)blockIdx.x * kWavesPerBlock + wave) * kSmallGrab;
+       first < n_small;) {
+    const int32_t last = first + kSmallGrab < n_small ? first + kSmallGrab : n_small;
+    for (int32_t i = first; i < last; ++i) {
+      const int32_t u = list[n_large + i];
+      const uint64_t h = process_source<1, PV, Wide, OffT>(u, row_ptr, col, tv, mine, ws,
+                                                           kSmallMax, args.max_kicks,
+                                                           args.force_sorted);
+      hits += h;
+      if (args.totals && h && lane == 0) {
+        const int32_t g = args.gid[u];
+        if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
+      }
     }
+    int32_t next = 0;
+    if (lane == 0) next = waves * kSmallGrab + atomicAdd(&st->small_cursor, kSmallGrab);
+    first = first_lane(next);
   }
   if (lane == 0 && hits) atomicAdd((unsigned long long*)total, (unsigned long long)hits);
 }
@@ -659,12 +679,16 @@ tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_
     bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st, tune.small_max);
     bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
         n, row_ptr, L.st, L.list, tune.small_max);
-    if (n <= (int64_t(1) << 24))
-      count_kernel<PV, false, OffT><<<count_grid<PV, false, OffT>(tune.blocks_per_cu), kBlock, 0, s>>>(
-          row_ptr, col, L.list, L.st, tot, tv, args);
-    else
-      count_kernel<PV, true, OffT><<<count_grid<PV, true, OffT>(tune.blocks_per_cu), kBlock, 0, s>>>(
-          row_ptr, col, L.list, L.st, tot, tv, args);
+    // The persistent grid, capped at one workgroup per 64 vertices: every wave
+    // polls the global cursors, so a small graph gets a small grid.
+    const int64_t cap = (n + 63) / 64;
+    if (n <= (int64_t(1) << 24)) {
+      const int grid = (int)std::min<int64_t>(count_grid<PV, false, OffT>(tune.blocks_per_cu), cap);
+      count_kernel<PV, false, OffT><<<grid, kBlock, 0, s>>>(row_ptr, col, L.list, L.st, tot, tv, args);
+    } else {
+      const int grid = (int)std::min<int64_t>(count_grid<PV, true, OffT>(tune.blocks_per_cu), cap);
+      count_kernel<PV, true, OffT><<<grid, kBlock, 0, s>>>(row_ptr, col, L.list, L.st, tot, tv, args);
+    }
   }
   return check_hip(hipGetLastError(), "tc_count launch");
 }
