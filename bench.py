@@ -29,6 +29,8 @@ WORKLOADS = {
     "er-n1024-m8192": dict(kind="er", n=1024, m=8192, seed=0, offset_bytes=4),
     # 4096 graphs, n log-uniform in [2^8, 2^16], average degree U(4, 64), ER/R-MAT alternating
     "batch-4096": dict(kind="batch", count=4096, seed=4, offset_bytes=8),
+    # Poisson request stream: batch-suite graphs plus 2% R-MAT scale 22 (edge factor 16)
+    "serve-poisson": dict(kind="serve", pool=256, seed=5, large_scale=22, large_frac=0.02),
 }
 
 
@@ -41,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the count")
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
+    ap.add_argument("--requests", type=int, default=3000, help="serve: requests after warm-up")
+    ap.add_argument("--qps", type=float, default=500.0, help="serve: Poisson arrival rate")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, run a plain device copy of this many MiB (3 times) so a "
                          "counter profile can scale FETCH_SIZE/WRITE_SIZE by a known byte count")
@@ -212,6 +216,83 @@ def batch_main(args, spec):
     print(json.dumps(out), flush=True)
 
 
+def serve_main(args, spec):
+    """Continuous-batching engine vs a plain engine (one request per launch, serialized)
+    on the same Poisson request stream."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import oracle
+    from paper_1909_02127_amd.serve import DeviceExecutor, Engine, Request
+
+    def say(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    rng = np.random.default_rng(spec["seed"])
+    specs = graphgen.batch_suite_spec(4096, seed=4)
+    pick = rng.choice(len(specs), size=spec["pool"], replace=False)
+    pool = []
+    for i in pick:
+        s_, d_, n_ = graphgen.batch_graph(specs[int(i)], device="cuda")
+        pool.append((s_.cpu().pin_memory(), d_.cpu().pin_memory(), n_))
+    large = []
+    for k in range(2):
+        s_, d_, n_ = graphgen.rmat(spec["large_scale"], 16, 220 + k, device="cuda")
+        large.append((s_.cpu().pin_memory(), d_.cpu().pin_memory(), n_))
+    torch.cuda.synchronize()
+    say(f"pool: {len(pool)} graphs + {len(large)} scale-{spec['large_scale']} graphs")
+
+    def stream(count, seed):
+        r = np.random.default_rng(seed)
+        t, out = 0.0, []
+        for i in range(count):
+            t += float(r.exponential(1.0 / args.qps))
+            g = large[int(r.integers(len(large)))] if r.random() < spec["large_frac"] \
+                else pool[int(r.integers(len(pool)))]
+            out.append(Request(i, g[2], g[0], g[1], arrival=t))
+        return out
+
+    warm = max(1, args.requests // 10)
+    budget = 64 << 30
+    ex = DeviceExecutor()
+    eng = Engine(ex, budget_bytes=budget, max_inflight=3, max_batch=256, large_pairs=8_000_000)
+    reqs = stream(warm + args.requests, 51)
+    st = eng.run(reqs)
+    summ = st.summary(warmup=warm)
+    say(f"continuous batching: {summ}")
+    # exactness: sample requests against the oracle (small ones) and against each other
+    ok = True
+    for r in reqs[:: max(1, len(reqs) // 20)]:
+        if r.num_pairs < 2_000_000:
+            ok &= r.total == oracle.triangles(r.n, r.src.numpy(), r.dst.numpy())
+    plain_n = max(1, args.requests // 3)
+    peng = Engine(DeviceExecutor(), budget_bytes=budget, max_inflight=1, max_batch=1,
+                  large_pairs=1 << 62)
+    preqs = stream(warm + plain_n, 51)
+    pst = peng.run(preqs)
+    psumm = pst.summary(warmup=warm)
+    say(f"plain: {psumm}")
+    same = all(a.total == b.total for a, b in zip(reqs, preqs))
+    out = {
+        "metric": "serving graphs/s (bit-exact vs oracle)",
+        "value": summ["graphs_per_s"],
+        "unit": "graphs/s",
+        "n_gpus": 1, "steps": args.requests, "warmup": warm,
+        "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "qps": args.qps, "requests": args.requests,
+                   "pool": len(pool), "large_scale": spec["large_scale"],
+                   "large_frac": spec["large_frac"], "budget_bytes": budget,
+                   "parallelism": "single-gpu"},
+        "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "serving": summ,
+        "plain": psumm, "plain_requests": plain_n,
+        "oracle_match": bool(ok), "plain_equals_batched": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def _with_tune(runner, tune):
     runner.tune = tune
     return runner
@@ -232,6 +313,8 @@ def main():
     torch.cuda.set_device(dev)
     if spec["kind"] == "batch":
         return batch_main(args, spec)
+    if spec["kind"] == "serve":
+        return serve_main(args, spec)
     s, d, n = make_graph(spec, dev)
     ob = spec["offset_bytes"]
     pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, order=tc.TC_ORDER_DEGREE, device=dev)

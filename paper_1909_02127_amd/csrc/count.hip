@@ -107,7 +107,7 @@ struct CountState {
   int32_t pad[6];
 };
 
-constexpr int kSmallGrab = 16;  // wave-mode sources a wave takes per cursor step
+constexpr int kSmallGrab = 16;  // wave-mode sources per run in the dynamic hand-out
 
 template <typename OffT>
 __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* __restrict__ row_ptr,
@@ -500,11 +500,10 @@ struct CountArgs {
   int force_sorted;
 };
 
-// Persistent count kernel: workgroup-mode sources first, then wave-mode sources,
-// both handed out through global cursors (a workgroup takes one large source, a
-// wave kSmallGrab small ones per step), so the run time does not depend on how
-// many of the launched workgroups are resident at once.  In batched mode each
-// source's hits are also added to the total of its graph.
+// Persistent count kernel: workgroup-mode sources first (largest class first,
+// through a global cursor after a static first round), then wave-mode sources
+// round robin.  In batched mode each source's hits are also added to the total
+// of its graph.
 template <bool PV, bool Wide, typename OffT>
 __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
@@ -529,8 +528,8 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   const int32_t n_small = st->class_count[kNumClasses - 1];
   uint64_t hits = 0;
 
-  // First item of each workgroup / wave is static (its id); later ones come from
-  // the cursors, offset past the static round, so small launches need few atomics.
+  // A workgroup's first source is static (its id); later ones come from the
+  // cursor, offset past that first round, so small launches need few atomics.
   const Table big = table_at<PV>(smem, kSideMax);
   for (int32_t idx = blockIdx.x; idx < n_large;) {
     const int32_t u = list[idx];
@@ -548,10 +547,18 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   }
 
   const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide);
+  // Wave-mode sources.  With many per wave (large graphs, batches) a wave takes
+  // runs of kSmallGrab consecutive list entries -- nearby vertices, which share
+  // cache lines -- its first run by its id, later ones from a global cursor, so
+  // the waves finish together.  With few per wave (small graphs) the cursor's
+  // atomics would come in one burst, so the sources go round robin instead.
   const int32_t waves = (int32_t)gridDim.x * kWavesPerBlock;
-  for (int32_t first = ((int32_t)blockIdx.x * kWavesPerBlock + wave) * kSmallGrab;
-       first < n_small;) {
-    const int32_t last = first + kSmallGrab < n_small ? first + kSmallGrab : n_small;
+  const int32_t w_id = (int32_t)blockIdx.x * kWavesPerBlock + wave;
+  const bool dynamic = n_small >= 2 * kSmallGrab * waves;
+  int32_t first = dynamic ? w_id * kSmallGrab : w_id;
+  while (first < n_small) {
+    const int32_t last = dynamic ? (first + kSmallGrab < n_small ? first + kSmallGrab : n_small)
+                                 : first + 1;
     for (int32_t i = first; i < last; ++i) {
       const int32_t u = list[n_large + i];
       const uint64_t h = process_source<1, PV, Wide, OffT>(u, row_ptr, col, tv, mine, ws,
@@ -563,9 +570,13 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
         if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
       }
     }
-    int32_t next = 0;
-    if (lane == 0) next = waves * kSmallGrab + atomicAdd(&st->small_cursor, kSmallGrab);
-    first = first_lane(next);
+    if (dynamic) {
+      int32_t next = 0;
+      if (lane == 0) next = waves * kSmallGrab + atomicAdd(&st->small_cursor, kSmallGrab);
+      first = first_lane(next);
+    } else {
+      first += waves;
+    }
   }
   if (lane == 0 && hits) atomicAdd((unsigned long long*)total, (unsigned long long)hits);
 }
@@ -679,9 +690,9 @@ tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_
     bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st, tune.small_max);
     bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
         n, row_ptr, L.st, L.list, tune.small_max);
-    // The persistent grid, capped at one workgroup per 64 vertices: every wave
-    // polls the global cursors, so a small graph gets a small grid.
-    const int64_t cap = (n + 63) / 64;
+    // The persistent grid, capped at one workgroup per 16 vertices so that a small
+    // graph launches a small grid.
+    const int64_t cap = (n + 15) / 16;
     if (n <= (int64_t(1) << 24)) {
       const int grid = (int)std::min<int64_t>(count_grid<PV, false, OffT>(tune.blocks_per_cu), cap);
       count_kernel<PV, false, OffT><<<grid, kBlock, 0, s>>>(row_ptr, col, L.list, L.st, tot, tv, args);
