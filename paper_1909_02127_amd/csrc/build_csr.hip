@@ -10,8 +10,9 @@
 //      that sorts last; an out-of-range id raises a device error flag.
 //   2. LSD radix sort of the 2*num_pairs keys over their 2*cb significant bits,
 //      8 bits per pass: per-tile digit histograms, one scan over the
-//      digit-major histogram table, and a stable scatter whose in-tile ranks
-//      come from 8 wave ballots per key.
+//      digit-major histogram table, and a stable scatter that sorts each tile by
+//      digit in LDS (in-tile ranks from 8 wave ballots per key) and then writes
+//      every digit's run to consecutive addresses.
 //   3. One scan over "first of its run" flags drops duplicates and sentinels,
 //      writes col, and records the first position of every non-empty row.
 //   4. A suffix-minimum scan turns the row starts into row_ptr (empty rows take
@@ -75,38 +76,72 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
   hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile: keys of equal digit keep their input order.
+// Stable scatter of one tile: keys of equal digit keep their input order.  The
+// tile is first sorted by digit in LDS (ranks from 8 wave ballots per key and a
+// running count per digit), then written out so that each digit's run lands at
+// consecutive global addresses (coalesced stores).
 __global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
     const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int64_t nk, int shift, int bits,
     const uint32_t* __restrict__ offsets, int64_t num_tiles) {
-  __shared__ uint32_t base_s[256];
+  __shared__ uint64_t lkeys[kRadixTile];
+  __shared__ uint32_t gbase[256];   // global start of this tile's run of each digit
+  __shared__ uint32_t lstart[256];  // start of each digit's run inside the tile
+  __shared__ uint32_t run[256];     // keys of each digit placed so far
   __shared__ uint32_t wcnt[kRadixBlock / kWave][256];
+  __shared__ uint32_t wave_tot[kRadixBlock / kWave];
   const int t = threadIdx.x;
   const int wave = t / kWave;
   const uint32_t mask = (1u << bits) - 1u;
-  base_s[t] = offsets[(int64_t)t * num_tiles + blockIdx.x];
+  const int64_t tile = (int64_t)blockIdx.x * kRadixTile;
+  const int valid_n = (int)(nk - tile < kRadixTile ? nk - tile : kRadixTile);
+  gbase[t] = offsets[(int64_t)t * num_tiles + blockIdx.x];
+  run[t] = 0;
 #pragma unroll
   for (int w = 0; w < kRadixBlock / kWave; ++w) wcnt[w][t] = 0;
   __syncthreads();
-  const int64_t tile = (int64_t)blockIdx.x * kRadixTile;
+  // digit histogram of the tile -> exclusive starts
+  uint64_t k[kRadixItems];
+#pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const int64_t i = tile + (int64_t)r * kRadixBlock + t;
-    const bool valid = i < nk;
-    const uint64_t k = valid ? in[i] : 0;
-    const uint32_t d = (uint32_t)(k >> shift) & mask;
-    uint64_t peers = ballot(valid);
+    const int i = r * kRadixBlock + t;
+    k[r] = i < valid_n ? in[tile + i] : 0;
+    if (i < valid_n) atomicAdd(&run[(uint32_t)(k[r] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  {
+    const uint32_t c = run[t];
+    uint32_t x = c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, kWave);
+      if (lane_id() >= off) x += y;
+    }
+    if (lane_id() == kWave - 1) wave_tot[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    lstart[t] = before + x - c;
+    run[t] = 0;
+  }
+  __syncthreads();
+  // stable placement, one round of 256 keys at a time
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int i = r * kRadixBlock + t;
+    const bool ok = i < valid_n;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
+    uint64_t peers = ballot(ok);
     for (int b = 0; b < bits; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bal = ballot(bit);
       peers &= bit ? bal : ~bal;
     }
     const uint32_t rank = rank_below(peers);
-    if (valid && rank == 0) wcnt[wave][d] = popc(peers);
+    if (ok && rank == 0) wcnt[wave][d] = popc(peers);
     __syncthreads();
-    if (valid) {
-      uint32_t pos = base_s[d] + rank;
+    if (ok) {
+      uint32_t pos = lstart[d] + run[d] + rank;
       for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      out[pos] = k;
+      lkeys[pos] = k[r];
     }
     __syncthreads();
     uint32_t add = 0;
@@ -115,8 +150,14 @@ __global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
       add += wcnt[w][t];
       wcnt[w][t] = 0;
     }
-    base_s[t] += add;
+    run[t] += add;
     __syncthreads();
+  }
+  // coalesced write-out of the digit-sorted tile
+  for (int j = t; j < valid_n; j += kRadixBlock) {
+    const uint64_t key = lkeys[j];
+    const uint32_t d = (uint32_t)(key >> shift) & mask;
+    out[gbase[d] + (uint32_t)j - lstart[d]] = key;
   }
 }
 

@@ -8,12 +8,16 @@
 // the paper's own "destination id larger than source id" rule.
 //
 // Pass 1 counts kept entries per row, a scan turns the counts into the DAG's
-// row offsets, pass 2 writes the kept entries in row order.  Rows up to
-// kLongRow entries are walked by one wave (ballot + mbcnt keeps the order);
-// longer rows are queued and walked by a whole workgroup.
+// row offsets, pass 2 writes the kept entries in row order (ballot + mbcnt keeps
+// the order).  A wave takes four rows at a time: when all four have at most
+// kShortRow entries it gives each 16 lanes, otherwise it walks them one after
+// the other with all 64 lanes.  Rows longer than kLongRow are queued and walked
+// by a whole workgroup.
 #include "tc_device.h"
 #include "tc_host.h"
 #include "tc_scan.h"
+
+#include <algorithm>
 
 namespace tc {
 namespace {
@@ -21,6 +25,9 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int64_t kLongRow = 2048;
+constexpr int32_t kShortRow = 64;
+constexpr int kGroup = 16;  // lanes per short row
+constexpr int kGroupsPerWave = kWave / kGroup;
 
 template <typename OffT>
 __global__ __launch_bounds__(256) void degree_kernel(int64_t n, const OffT* __restrict__ row_ptr,
@@ -38,32 +45,65 @@ __device__ __forceinline__ bool keep_edge(int64_t u, int32_t du, int32_t v,
   return du < dv || (du == dv && u < v);
 }
 
+// Largest length among the four 16-lane groups of a wave (uniform).
+__device__ __forceinline__ int32_t group_max(int32_t len) {
+  int32_t a = read_lane(len, 0), b = read_lane(len, 16), c = read_lane(len, 32),
+          d = read_lane(len, 48);
+  a = a > b ? a : b;
+  c = c > d ? c : d;
+  return a > c ? a : c;
+}
+
 __global__ void clear_counter_kernel(int32_t* c) { *c = 0; }
 
-// Pass 1 (short rows): one wave per row.
+// Pass 1 (rows up to kLongRow): four rows per wave; short rows counted 16 lanes
+// each, otherwise one row at a time with the whole wave; long rows are queued.
 template <typename OffT, int Order>
-__global__ __launch_bounds__(kBlock) void count_rows_kernel(int64_t n,
-                                                            const OffT* __restrict__ row_ptr,
-                                                            const int32_t* __restrict__ col,
-                                                            const int32_t* __restrict__ deg,
-                                                            int64_t* __restrict__ outdeg,
-                                                            int32_t* __restrict__ long_rows,
-                                                            int32_t* __restrict__ long_count) {
+__global__ __launch_bounds__(kBlock) void count_rows_kernel(
+    int64_t n, const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ deg, int64_t* __restrict__ outdeg, int32_t* __restrict__ long_rows,
+    int32_t* __restrict__ long_count) {
   const int lane = lane_id();
+  const int g = lane / kGroup, gl = lane % kGroup;
+  const uint64_t gmask = 0xFFFFull << (kGroup * g);
   const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; u < n; u += waves) {
-    const int64_t beg = row_ptr[u], end = row_ptr[u + 1];
-    if (end - beg > kLongRow) {
-      if (lane == 0) long_rows[atomicAdd(long_count, 1)] = (int32_t)u;
+  for (int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kGroupsPerWave;
+       r0 < n; r0 += waves * kGroupsPerWave) {
+    const int64_t u = r0 + g;
+    int64_t beg = 0, end = 0;
+    if (u < n) {
+      beg = row_ptr[u];
+      end = row_ptr[u + 1];
+    }
+    const int64_t len64 = end - beg;
+    const int32_t len = len64 > kShortRow ? kShortRow + 1 : (int32_t)len64;
+    const int32_t widest = group_max(len);
+    if (widest <= kShortRow) {
+      const int32_t iters = (widest + kGroup - 1) / kGroup;
+      uint32_t kept = 0;
+      for (int32_t k = 0; k < iters; ++k) {
+        const int32_t j = k * kGroup + gl;
+        const bool kk = j < len && keep_edge<Order>(u, len, col[beg + j], deg);
+        kept += popc(ballot(kk) & gmask);
+      }
+      if (gl == 0 && u < n) outdeg[u] = kept;
       continue;
     }
-    const int32_t du = (int32_t)(end - beg);
-    uint32_t kept = 0;
-    for (int64_t e = beg + lane; e - lane < end; e += kWave) {
-      const bool k = e < end && keep_edge<Order>(u, du, col[e], deg);
-      kept += popc(ballot(k));
+    for (int r = 0; r < kGroupsPerWave && r0 + r < n; ++r) {
+      const int64_t ur = r0 + r;
+      const int64_t rb = read_lane64(beg, r * kGroup), re = read_lane64(end, r * kGroup);
+      if (re - rb > kLongRow) {
+        if (lane == 0) long_rows[atomicAdd(long_count, 1)] = (int32_t)ur;
+        continue;
+      }
+      const int32_t du = (int32_t)(re - rb);
+      uint32_t kept = 0;
+      for (int64_t e = rb + lane; e - lane < re; e += kWave) {
+        const bool kk = e < re && keep_edge<Order>(ur, du, col[e], deg);
+        kept += popc(ballot(kk));
+      }
+      if (lane == 0) outdeg[ur] = kept;
     }
-    if (lane == 0) outdeg[u] = kept;
   }
 }
 
@@ -115,28 +155,55 @@ __global__ void finalize_kernel(const int64_t* total, int64_t cap, int64_t* m_ou
   *m_out = m > cap ? -(int64_t)TC_ERR_CAPACITY : m;
 }
 
-// Pass 2 (short rows): write kept entries in row order.
+// Pass 2 (rows up to kLongRow): the same walk as pass 1, writing kept entries in
+// row order.
 template <typename OffT, int Order>
-__global__ __launch_bounds__(kBlock) void fill_rows_kernel(int64_t n, const OffT* __restrict__ row_ptr,
-                                                           const int32_t* __restrict__ col,
-                                                           const int32_t* __restrict__ deg,
-                                                           const OffT* __restrict__ dag_ptr,
-                                                           int32_t* __restrict__ dag_col,
-                                                           const int64_t* __restrict__ m_out) {
+__global__ __launch_bounds__(kBlock) void fill_rows_kernel(
+    int64_t n, const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ deg, const OffT* __restrict__ dag_ptr,
+    int32_t* __restrict__ dag_col, const int64_t* __restrict__ m_out) {
   if (*m_out < 0) return;
   const int lane = lane_id();
+  const int g = lane / kGroup, gl = lane % kGroup;
+  const uint64_t gmask = 0xFFFFull << (kGroup * g);
   const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; u < n; u += waves) {
-    const int64_t beg = row_ptr[u], end = row_ptr[u + 1];
-    if (end - beg > kLongRow) continue;
-    const int32_t du = (int32_t)(end - beg);
-    int64_t out = dag_ptr[u];
-    for (int64_t e = beg + lane; e - lane < end; e += kWave) {
-      const int32_t v = e < end ? col[e] : 0;
-      const bool k = e < end && keep_edge<Order>(u, du, v, deg);
-      const uint64_t m = ballot(k);
-      if (k) dag_col[out + rank_below(m)] = v;
-      out += popc(m);
+  for (int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kGroupsPerWave;
+       r0 < n; r0 += waves * kGroupsPerWave) {
+    const int64_t u = r0 + g;
+    int64_t beg = 0, end = 0, out = 0;
+    if (u < n) {
+      beg = row_ptr[u];
+      end = row_ptr[u + 1];
+      out = dag_ptr[u];
+    }
+    const int64_t len64 = end - beg;
+    const int32_t len = len64 > kShortRow ? kShortRow + 1 : (int32_t)len64;
+    const int32_t widest = group_max(len);
+    if (widest <= kShortRow) {
+      const int32_t iters = (widest + kGroup - 1) / kGroup;
+      for (int32_t k = 0; k < iters; ++k) {
+        const int32_t j = k * kGroup + gl;
+        const int32_t v = j < len ? col[beg + j] : 0;
+        const bool kk = j < len && keep_edge<Order>(u, len, v, deg);
+        const uint64_t m = ballot(kk) & gmask;
+        if (kk) dag_col[out + rank_below(m)] = v;
+        out += popc(m);
+      }
+      continue;
+    }
+    for (int r = 0; r < kGroupsPerWave && r0 + r < n; ++r) {
+      const int64_t ur = r0 + r;
+      const int64_t rb = read_lane64(beg, r * kGroup), re = read_lane64(end, r * kGroup);
+      if (re - rb > kLongRow) continue;
+      const int32_t du = (int32_t)(re - rb);
+      int64_t o = read_lane64(out, r * kGroup);
+      for (int64_t e = rb + lane; e - lane < re; e += kWave) {
+        const int32_t v = e < re ? col[e] : 0;
+        const bool kk = e < re && keep_edge<Order>(ur, du, v, deg);
+        const uint64_t m = ballot(kk);
+        if (kk) dag_col[o + rank_below(m)] = v;
+        o += popc(m);
+      }
     }
   }
 }
@@ -211,8 +278,10 @@ template <typename OffT, int Order>
 tc_status orient_impl(int64_t n, const OffT* row_ptr, const int32_t* col, OffT* dag_ptr,
                       int32_t* dag_col, int64_t cap, int64_t* m_out, const OrientLayout& L,
                       hipStream_t s) {
-  const int grid_rows = grid_for(n, kWavesPerBlock, 16384);
-  const int grid_long = 2 * device_cu_count();
+  const int grid_rows = grid_for(n, kWavesPerBlock * kGroupsPerWave, 16384);
+  // at most n / kLongRow rows can be long
+  const int grid_long = (int)std::max<int64_t>(
+      1, std::min<int64_t>(2 * device_cu_count(), (n + kLongRow - 1) / kLongRow));
   clear_counter_kernel<<<1, 1, 0, s>>>(L.long_count);
   if (n > 0) {
     if (Order == TC_ORDER_DEGREE)
