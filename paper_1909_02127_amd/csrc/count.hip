@@ -245,8 +245,9 @@ __device__ __forceinline__ bool probe(const Table& t, const Slice& sl, int32_t w
     if (PV && hit) atomicAdd(&t.cnt[lo], 1u);
     return hit;
   }
-  const uint32_t s1 = hash_a<Wide>(w, sl.shift);
-  const uint32_t s2 = (uint32_t)sl.side + hash_b<Wide>(w, sl.shift);
+  const uint32_t x = hash_input<Wide>(w);
+  const uint32_t s1 = hash_a_of(x, sl.shift);
+  const uint32_t s2 = (uint32_t)sl.side + hash_b_of(x, sl.shift);
   const int32_t a = t.slot[s1];
   const int32_t b = t.slot[s2];
   bool hit = (a == w) | (b == w);

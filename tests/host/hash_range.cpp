@@ -23,6 +23,15 @@ int main() {
     // signed shift of that product gives a negative slot
     if (tc::hash_a<false>(208, shift) >= side) ++bad;
   }
+  // the wide variant spreads a block of consecutive ids above 2^24 as well
+  {
+    int wload[1024] = {0}, wmx = 0;
+    for (int32_t k = (1 << 25) + 12345; k < (1 << 25) + 12345 + 1024; ++k) {
+      int s = (int)tc::hash_a<true>(k, 22);
+      if (++wload[s] > wmx) wmx = wload[s];
+    }
+    if (wmx > 8) ++bad;
+  }
   // balance: 1024 consecutive ids into 1024 slots, max load per slot
   int load[1024] = {0}, mx = 0;
   for (int32_t k = 0; k < 1024; ++k) {

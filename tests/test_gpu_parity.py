@@ -273,3 +273,21 @@ def test_probe_fallback_modes(tc, kicks, monkeypatch):
             res, pv = _gpu(tc, n, s, d, order=order)
             assert res.total == T
             np.testing.assert_array_equal(pv, t)
+
+
+def test_ids_above_2_24(tc):
+    """Vertex ids beyond 2^24 take the folded (wide) hash; counts must not change."""
+    rng = np.random.default_rng(24)
+    base = (1 << 24) + 777
+    n = base + 6000
+    k = 60000
+    s = rng.integers(base, n, k)
+    d = rng.integers(base, n, k)
+    # some edges between high and low ids, and a dense block of consecutive high ids
+    s = np.concatenate([s, rng.integers(0, 5000, 3000), np.repeat(np.arange(base, base + 40), 40)])
+    d = np.concatenate([d, rng.integers(base, n, 3000), np.tile(np.arange(base, base + 40), 40)])
+    T, t = _oracle(n, s, d)
+    for order in (0, 1):
+        res, pv = _gpu(tc, n, s, d, order=order)
+        assert res.total == T
+        np.testing.assert_array_equal(pv, t)
