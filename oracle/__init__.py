@@ -54,6 +54,8 @@ def _load():
         lib.oracle_count.argtypes = [i64, p, p, p, i32]
         lib.oracle_vertex_triangles.restype = i64
         lib.oracle_vertex_triangles.argtypes = [i64, i64, p, p, i32]
+        lib.oracle_list.restype = i64
+        lib.oracle_list.argtypes = [i64, p, p, p, i64]
         lib.oracle_max_threads.restype = i32
         lib.oracle_max_threads.argtypes = []
         _lib = lib
@@ -121,6 +123,21 @@ def count(dag_ptr: np.ndarray, dag_col: np.ndarray, *, per_vertex: bool = False,
     if per_vertex:
         return total, t[:n].copy()
     return total
+
+
+def list_triangles(dag_ptr: np.ndarray, dag_col: np.ndarray) -> np.ndarray:
+    """The triangles of an oriented graph as an int32 array of shape (T, 3): rows
+    (u, v, w) with v, w in N+(u) and w in N+(v), in lexicographic order."""
+    lib = _load()
+    dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
+    dag_col = _i32(dag_col)
+    n = dag_ptr.size - 1
+    total = int(lib.oracle_list(n, _ptr(dag_ptr), _ptr(dag_col), None, 0))
+    out = np.zeros((max(total, 1), 3), dtype=np.int32)
+    got = int(lib.oracle_list(n, _ptr(dag_ptr), _ptr(dag_col), _ptr(out), total))
+    if got != total:
+        raise OracleError("oracle_list changed its answer")
+    return out[:total].copy()
 
 
 def max_threads() -> int:

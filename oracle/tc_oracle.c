@@ -26,6 +26,10 @@
  *    Per-vertex counts t(x) = number of triangles containing x.
  *  - oracle_vertex_triangles: t(v) by its definition straight from the raw
  *    input pairs: the number of distinct edges among the neighbours of v.
+ *  - oracle_list: the match set M itself (Sec. II-A: the output of subgraph
+ *    matching is every match; Alg. 1 collects the complete matches in M).  Each
+ *    triangle is one match under the orientation, written as the triple
+ *    (u, v, w) = (u1, u2, u3) of the query path with its non-tree edge.
  *
  * Every function is pinned by the CPU test suite against brute force over
  * vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms and invariants.
@@ -230,4 +234,42 @@ int64_t oracle_vertex_triangles(int64_t n, int64_t num_pairs, const int32_t* src
   free(keys);
   free(nbr);
   return distinct;
+}
+
+/*
+ * The triangles of an oriented graph as triples (u, v, w) with v and w in
+ * N+(u) and w in N+(v): for every u in id order, every v in N+(u) in row
+ * order, the common out-neighbours w of u and v in increasing order, so the
+ * triples come out in lexicographic (u, v, w) order (rows are sorted).
+ * out (nullable): int32[3 * cap], receives the first min(T, cap) triples.
+ * Returns T.  Single-threaded.
+ */
+int64_t oracle_list(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col, int32_t* out,
+                    int64_t cap) {
+  int64_t found = 0;
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
+      int64_t v = dag_col[e];
+      int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];
+      int64_t j = dag_ptr[v], jend = dag_ptr[v + 1];
+      while (i < iend && j < jend) {
+        int32_t a = dag_col[i], b = dag_col[j];
+        if (a < b) {
+          ++i;
+        } else if (b < a) {
+          ++j;
+        } else {
+          if (out && found < cap) {
+            out[3 * found + 0] = (int32_t)u;
+            out[3 * found + 1] = (int32_t)v;
+            out[3 * found + 2] = a;
+          }
+          ++found;
+          ++i;
+          ++j;
+        }
+      }
+    }
+  }
+  return found;
 }

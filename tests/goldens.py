@@ -19,6 +19,7 @@ class Fixture:
     per_vertex: np.ndarray
     src: np.ndarray
     dst: np.ndarray
+    triangle_sets: list  # sorted list of sorted vertex triples, hand-derived from `why`
 
 
 def load(path: str) -> Fixture:
@@ -35,9 +36,11 @@ def load(path: str) -> Fixture:
             a, b = line.split()
             s.append(int(a))
             d.append(int(b))
+    sets = sorted(tuple(sorted(int(x) for x in t.split(",")))
+                  for t in meta.get("triangle_sets", "").split())
     return Fixture(meta["name"], meta["why"], int(meta["n"]), int(meta["triangles"]),
                    np.array([int(x) for x in meta["per_vertex"].split()], dtype=np.uint64),
-                   np.array(s, dtype=np.int32), np.array(d, dtype=np.int32))
+                   np.array(s, dtype=np.int32), np.array(d, dtype=np.int32), sets)
 
 
 def all_fixtures() -> list[Fixture]:

@@ -36,6 +36,20 @@ def brute_force(n: int, src, dst) -> tuple[int, np.ndarray]:
     return total, t
 
 
+def brute_force_sets(n: int, src, dst) -> list[tuple[int, int, int]]:
+    """Every triangle {a, b, c} as a sorted triple, by checking all vertex triples."""
+    e = edge_set(src, dst)
+    out = []
+    for a in range(n):
+        for b in range(a + 1, n):
+            if frozenset((a, b)) not in e:
+                continue
+            for c in range(b + 1, n):
+                if frozenset((a, c)) in e and frozenset((b, c)) in e:
+                    out.append((a, b, c))
+    return out
+
+
 def trace_cube(n: int, src, dst) -> tuple[int, np.ndarray]:
     """T = trace(A^3)/6 and t = diag(A^3)/2 for the 0/1 symmetric adjacency A."""
     A = np.zeros((n, n), dtype=np.float64)

@@ -200,3 +200,88 @@ def test_golden_config1_counts_pinned_by_trace():
         tt, tper = pins.trace_cube(n, s.numpy(), d.numpy())
         assert g["triangles"] == tt
         np.testing.assert_array_equal(np.array(g["per_vertex"], dtype=np.uint64), tper)
+
+
+# -- the listing M (triangle triples) ------------------------------------------------------
+
+
+def _listing(n, s, d, order=oracle.ORDER_DEGREE):
+    rp, col = oracle.clean(n, s, d)
+    dp, dc = oracle.orient(rp, col, order)
+    return dp, dc, oracle.list_triangles(dp, dc)
+
+
+def _dag_edges(dp, dc):
+    return {(u, int(v)) for u in range(dp.size - 1) for v in dc[dp[u]:dp[u + 1]]}
+
+
+def _check_listing_shape(dp, dc, lst):
+    """Every row is a wedge u -> v -> w closed by u -> w; rows are strictly increasing."""
+    edges = _dag_edges(dp, dc)
+    for u, v, w in lst.tolist():
+        assert (u, v) in edges and (v, w) in edges and (u, w) in edges
+    if len(lst) > 1:
+        keys = [tuple(r) for r in lst.tolist()]
+        assert all(a < b for a, b in zip(keys, keys[1:]))
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_list_brute_force_random_tiny(seed):
+    """The listed vertex sets are exactly the brute-force triangles, once each."""
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(1, 30))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.1, 0.3, 0.6, 1.0])), seed)
+    want = pins.brute_force_sets(n, s, d)
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        dp, dc, lst = _listing(n, s, d, order)
+        assert sorted(tuple(sorted(r)) for r in lst.tolist()) == want
+        _check_listing_shape(dp, dc, lst)
+
+
+@pytest.mark.parametrize("fx", goldens.all_fixtures(), ids=lambda f: f.name)
+def test_list_golden_fixtures(fx):
+    """Hand-derived triangle sets of the fixtures (each from the fact its header states)."""
+    assert len(fx.triangle_sets) == fx.triangles
+    assert pins.brute_force_sets(fx.n, fx.src, fx.dst) == fx.triangle_sets
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        dp, dc, lst = _listing(fx.n, fx.src, fx.dst, order)
+        assert sorted(tuple(sorted(r)) for r in lst.tolist()) == fx.triangle_sets
+        _check_listing_shape(dp, dc, lst)
+
+
+def test_list_closed_forms():
+    from math import comb
+    # K_n: every 3-subset once
+    for n in (3, 4, 7, 12):
+        _, s, d = pins.complete(n)
+        _, _, lst = _listing(n, s, d)
+        sets = {tuple(sorted(r)) for r in lst.tolist()}
+        assert len(lst) == len(sets) == comb(n, 3)
+    # friendship F_k: k triangles, all through the centre
+    for k in (1, 3, 6):
+        n, s, d = pins.friendship(k)
+        _, _, lst = _listing(n, s, d)
+        assert len(lst) == k
+        centre = np.bincount(lst.ravel(), minlength=n).argmax()
+        assert all(centre in r for r in lst.tolist())
+    # K_{a,b,c}: a*b*c triangles, one vertex from each part
+    a, b, c = 2, 3, 4
+    n, s, d = pins.complete_tripartite(a, b, c)
+    _, _, lst = _listing(n, s, d)
+    assert len(lst) == a * b * c
+    part = np.array([0] * a + [1] * b + [2] * c)
+    assert all(sorted(part[list(r)]) == [0, 1, 2] for r in lst.tolist())
+    # triangle-free families list nothing
+    for n, s, d in (pins.cycle(9), pins.petersen(), pins.complete_bipartite(4, 5)):
+        assert len(_listing(n, s, d)[2]) == 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_list_counts_agree_with_trace(seed):
+    """G(1024, 8192): the listing has trace(A^3)/6 rows and vertex x appears in diag(A^3)_x / 2."""
+    s, d, n = graphgen.erdos_renyi(1024, 8192, seed)
+    tt, tper = pins.trace_cube(n, s.numpy(), d.numpy())
+    dp, dc, lst = _listing(n, s.numpy(), d.numpy())
+    assert len(lst) == tt
+    np.testing.assert_array_equal(np.bincount(lst.ravel(), minlength=n), tper)
+    _check_listing_shape(dp, dc, lst)
