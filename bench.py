@@ -31,6 +31,8 @@ WORKLOADS = {
     "batch-4096": dict(kind="batch", count=4096, seed=4, offset_bytes=8),
     # Poisson request stream: batch-suite graphs plus 2% R-MAT scale 22 (edge factor 16)
     "serve-poisson": dict(kind="serve", pool=256, seed=5, large_scale=22, large_frac=0.02),
+    # triangle listing (every triangle as a (u, v, w) row) on the scale-20 graph
+    "list-rmat-s20-ef16": dict(kind="list", scale=20, ef=16, seed=20, offset_bytes=4),
 }
 
 
@@ -45,9 +47,21 @@ def parse():
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
     ap.add_argument("--requests", type=int, default=3000, help="serve: requests after warm-up")
     ap.add_argument("--qps", type=float, default=500.0, help="serve: Poisson arrival rate")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="serve: measure the mix's capacity (all requests queued at once), then "
+                         "run 1000 warm-up + --requests requests at 0.3/0.5/0.7/0.9 of it; the "
+                         "reported point is 0.7")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, run a plain device copy of this many MiB (3 times) so a "
                          "counter profile can scale FETCH_SIZE/WRITE_SIZE by a known byte count")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="write the rocprofv3 --kernel-trace --stats CSV under DIR as a text summary "
+                         "in profiles/ and exit (no GPU use)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the FETCH_SIZE / WRITE_SIZE counter runs under the two dirs as the "
+                         "count kernel's traffic record in profiles/ and exit (no GPU use)")
+    ap.add_argument("--profile-command", action="append", default=[],
+                    help="with --summarize-*: the command that produced the data (repeatable)")
     return ap.parse_args()
 
 
@@ -75,6 +89,92 @@ def counter_traffic(workload: str):
     if rec.get("source_digest") != count_source_digest():
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def _short_kernel_name(name: str) -> str:
+    import re
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", name)[:110]
+
+
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    import glob
+    paths = glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)
+    if not paths:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    rows = []
+    for p in paths:
+        with open(p) as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def summarize_trace(args) -> str:
+    """profiles/<kernel>_<workload>_kernel_trace.txt from a --kernel-trace --stats run."""
+    rows = _csv_rows(args.summarize_trace, "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel-trace summary: workload {args.workload}, library kernels (tc::) only",
+             "# command (repository root on the MI355X, after: cd /tmp && export TMPDIR=/tmp):"]
+    lines += [f"#   {c}" for c in args.profile_command]
+    lines.append("# calls  avg_us  min_us  max_us  total_ms  kernel")
+    for r in rows:
+        name = _short_kernel_name(r["Name"])
+        if not name.startswith("tc::"):
+            continue
+        lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:11.2f} "
+                     f"{float(r['MinNs']) / 1e3:11.2f} {float(r['MaxNs']) / 1e3:11.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.3f}  {name}")
+    out = os.path.join(ROOT, "profiles", f"count_kernel_{args.workload}_kernel_trace.txt")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
+
+
+def summarize_pmc(args) -> str:
+    """profiles/count_kernel_<workload>_pmc.json: HBM bytes per count launch from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for the calibration copy
+    (a plain device copy of --calibrate-copy-mib MiB, the largest copy dispatches of the run)."""
+    import collections
+    rec = {"workload": args.workload, "source_digest": count_source_digest(),
+           "commands": args.profile_command}
+    per = {}
+    for counter, directory in zip(("FETCH_SIZE", "WRITE_SIZE"), args.summarize_pmc):
+        vals = collections.defaultdict(list)
+        for r in _csv_rows(directory, "counter_collection.csv"):
+            if r["Counter_Name"] == counter:
+                vals[_short_kernel_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        copies = [v for k, vs in vals.items() if "copyBuffer" in k for v in vs]
+        if not copies:
+            raise SystemExit(f"{counter}: no calibration copy dispatches under {directory}")
+        top = max(copies)
+        cal = [v for v in copies if v >= 0.95 * top]
+        cal_kib = sum(cal) / len(cal)
+        per[counter] = (vals, cal_kib)
+    mib = args.calibrate_copy_mib or 1024
+    copy_bytes = mib << 20
+    f_fac = copy_bytes / (per["FETCH_SIZE"][1] * 1024)
+    w_fac = copy_bytes / (per["WRITE_SIZE"][1] * 1024)
+    rec["calibration"] = {"copy_bytes": copy_bytes, "copy_fetch_kib": per["FETCH_SIZE"][1],
+                          "copy_write_kib": per["WRITE_SIZE"][1], "fetch_factor": f_fac,
+                          "write_factor": w_fac}
+    # count_kernel<kind, wide, offset>: kind 1 = per-vertex, 0 = total only
+    for key, kind in (("count_per_vertex", "1"), ("count_total_only", "0")):
+        name = next((k for k in per["FETCH_SIZE"][0] if k.startswith(f"tc::count_kernel<{kind},")),
+                    None)
+        if name is None:
+            continue
+        fv, wv = per["FETCH_SIZE"][0][name], per["WRITE_SIZE"][0].get(name, [0.0])
+        fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+        rec[key] = {"kernel": name, "dispatches": len(fv), "fetch_kib": fk, "write_kib": wk,
+                    "fetch_bytes_scaled": fk * 1024 * f_fac, "write_bytes_scaled": wk * 1024 * w_fac,
+                    "traffic_bytes_per_launch": fk * 1024 * f_fac + wk * 1024 * w_fac}
+    rec["traffic_bytes_per_launch"] = rec.get("count_per_vertex", {}).get("traffic_bytes_per_launch")
+    out = os.path.join(ROOT, "profiles", f"count_kernel_{args.workload}_pmc.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    return out
 
 
 def make_graph(spec, device):
@@ -243,33 +343,63 @@ def serve_main(args, spec):
     torch.cuda.synchronize()
     say(f"pool: {len(pool)} graphs + {len(large)} scale-{spec['large_scale']} graphs")
 
-    def stream(count, seed):
+    def stream(count, seed, qps=None):
+        """Requests with Poisson arrivals at `qps` (None: args.qps; 0: all at time 0)."""
+        qps = args.qps if qps is None else qps
         r = np.random.default_rng(seed)
         t, out = 0.0, []
         for i in range(count):
-            t += float(r.exponential(1.0 / args.qps))
+            t += float(r.exponential(1.0 / qps)) if qps > 0 else 0.0
             g = large[int(r.integers(len(large)))] if r.random() < spec["large_frac"] \
                 else pool[int(r.integers(len(pool)))]
             out.append(Request(i, g[2], g[0], g[1], arrival=t))
         return out
 
-    warm = max(1, args.requests // 10)
     budget = 64 << 30
     ex = DeviceExecutor()
-    eng = Engine(ex, budget_bytes=budget, max_inflight=3, max_batch=256, large_pairs=8_000_000)
-    reqs = stream(warm + args.requests, 51)
+
+    def engine():
+        return Engine(ex, budget_bytes=budget, max_inflight=3, max_batch=256,
+                      large_pairs=8_000_000)
+
+    sweep = None
+    qps = args.qps
+    if args.serve_sweep:
+        # capacity of the mix: every request queued at time 0, completions per second
+        cap_n = 3000
+        cst = engine().run(stream(cap_n, 50, qps=0))
+        capacity = cst.summary(warmup=cap_n // 10)["graphs_per_s"]
+        say(f"capacity: {capacity:.1f} graphs/s")
+        sweep = {"capacity_graphs_per_s": capacity, "points": []}
+        warm = 1000
+        for frac in (0.3, 0.5, 0.9):
+            pst_ = engine().run(stream(warm + args.requests, 60 + int(frac * 10),
+                                       qps=frac * capacity))
+            pt = pst_.summary(warmup=warm)
+            pt["load"] = frac
+            pt["qps"] = frac * capacity
+            sweep["points"].append(pt)
+            say(f"load {frac}: {pt}")
+        qps = 0.7 * capacity
+    else:
+        warm = max(1, args.requests // 10)
+    eng = engine()
+    reqs = stream(warm + args.requests, 51, qps=qps)
     st = eng.run(reqs)
     summ = st.summary(warmup=warm)
-    say(f"continuous batching: {summ}")
+    say(f"continuous batching at {qps:.1f} requests/s: {summ}")
+    if sweep is not None:
+        summ_pt = dict(summ, load=0.7, qps=qps)
+        sweep["points"].insert(2, summ_pt)
     # exactness: sample requests against the oracle (small ones) and against each other
     ok = True
     for r in reqs[:: max(1, len(reqs) // 20)]:
         if r.num_pairs < 2_000_000:
             ok &= r.total == oracle.triangles(r.n, r.src.numpy(), r.dst.numpy())
-    plain_n = max(1, args.requests // 3)
+    plain_n = max(1, min(args.requests // 3, 2000))
     peng = Engine(DeviceExecutor(), budget_bytes=budget, max_inflight=1, max_batch=1,
                   large_pairs=1 << 62)
-    preqs = stream(warm + plain_n, 51)
+    preqs = stream(warm + plain_n, 51, qps=qps)
     pst = peng.run(preqs)
     psumm = pst.summary(warmup=warm)
     say(f"plain: {psumm}")
@@ -282,13 +412,65 @@ def serve_main(args, spec):
         "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": args.workload, "qps": args.qps, "requests": args.requests,
+        "config": {"workload": args.workload, "qps": qps, "requests": args.requests,
+                   "warmup_requests": warm,
                    "pool": len(pool), "large_scale": spec["large_scale"],
                    "large_frac": spec["large_frac"], "budget_bytes": budget,
                    "parallelism": "single-gpu"},
         "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "serving": summ,
-        "plain": psumm, "plain_requests": plain_n,
+        "plain": psumm, "plain_requests": plain_n, "sweep": sweep,
         "oracle_match": bool(ok), "plain_equals_batched": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def list_main(args, spec):
+    """tc_list_triangles on the resident DAG of an R-MAT graph: rows/s and its roofline."""
+    import torch
+    import paper_1909_02127_amd as tc
+
+    dev = torch.device("cuda:0")
+    s, d, n = make_graph(dict(spec, kind="rmat"), dev)
+    ob = spec["offset_bytes"]
+    pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, device=dev)
+    pipe.enqueue(s, d)
+    res = pipe.result()
+    T = res.total
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        pipe.list_triangles(T)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        pipe.list_triangles(T)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    rows = pipe.listing()
+    ok = rows.shape[0] == T
+    if not args.no_check:
+        import oracle
+        rp, col = oracle.clean(n, s.cpu().numpy(), d.cpu().numpy())
+        dp, dc = oracle.orient(rp, col)
+        ok = ok and oracle.count(dp, dc) == T
+    alg = algorithmic_bytes(pipe.dag_ptr, pipe.dag_col, n, ob, per_vertex=False)
+    # two enumeration passes, 12 B per row written, a count and an offset per vertex
+    b = 2 * alg["bytes"] + 12 * T + 16 * n
+    achieved = b / (ms / 1e3) / 1e9
+    out = {
+        "metric": "triangles listed/s (count vs oracle)",
+        "value": T / (ms / 1e3),
+        "unit": "triangles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": res.m, "triangles": T,
+                   "offset_bytes": ob, "order": "degree", "parallelism": "single-gpu"},
+        "oracle_match": bool(ok),
+        "roofline": {"bound": "hbm", "kernel": "count_kernel (listing: both passes)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b},
     }
     print(json.dumps(out), flush=True)
 
@@ -300,6 +482,12 @@ def _with_tune(runner, tune):
 
 def main():
     args = parse()
+    if args.summarize_trace or args.summarize_pmc:
+        if args.summarize_trace:
+            print(summarize_trace(args))
+        if args.summarize_pmc:
+            print(summarize_pmc(args))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
               "(the multi-GPU sharding is described in DESIGN.md but not implemented)",
@@ -315,6 +503,8 @@ def main():
         return batch_main(args, spec)
     if spec["kind"] == "serve":
         return serve_main(args, spec)
+    if spec["kind"] == "list":
+        return list_main(args, spec)
     s, d, n = make_graph(spec, dev)
     ob = spec["offset_bytes"]
     pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, order=tc.TC_ORDER_DEGREE, device=dev)

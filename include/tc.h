@@ -19,6 +19,8 @@
  *   tc_count_per_vertex  the same, plus t(v) = number of triangles containing v.
  *   tc_count_batched     per-graph counts of many graphs packed as one disjoint
  *                        union, in one launch sequence.
+ *   tc_list_triangles    the match set M itself: every triangle as one row
+ *                        (u, v, w) of the oriented graph.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -135,9 +137,13 @@ tc_status tc_build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const i
  *   dag_col      device int32[dag_col_capacity] (written): for each u the v with
  *                rank(u) < rank(v), ascending by id (a subsequence of u's row)
  *   dag_col_capacity  entries available in dag_col; m = row_ptr[n]/2 are needed
- *   m_out        device int64[1] (written): m, or -TC_ERR_CAPACITY (then
- *                dag_row_ptr is all zeros)
- *   ws, ws_bytes workspace; O(n) bytes.
+ *                (at most 2^40)
+ *   m_out        device int64[1] (written): m, or -TC_ERR_CAPACITY when the DAG
+ *                needs more than dag_col_capacity entries or row_ptr[n] exceeds
+ *                2 * dag_col_capacity (then dag_row_ptr is all zeros)
+ *   ws, ws_bytes workspace; depends on n and dag_col_capacity: about
+ *                4 n + dag_col_capacity / 4 bytes (per-tile state for up to
+ *                2 * dag_col_capacity symmetric entries).
  */
 tc_status tc_orient(const tc_csr* sym, int32_t order, void* dag_row_ptr, int32_t* dag_col,
                     int64_t dag_col_capacity, int64_t* m_out, void* ws, size_t* ws_bytes,
@@ -203,6 +209,29 @@ tc_status tc_count_per_vertex(const tc_csr* dag, uint64_t* per_vertex, uint64_t*
 tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, const int64_t* vtx_off,
                            uint64_t* totals, uint64_t* per_vertex, uint64_t* total,
                            const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
+
+/*
+ * tc_list_triangles - the matches themselves.  Sec. II-A defines the output of
+ * subgraph matching as every match; Alg. 1 collects the complete matches in M,
+ * and under the unique mapping order each triangle is one match.  Each is
+ * written as the row (u, v, w) = (u1, u2, u3) of the query path: v and w in
+ * N+(u), w in N+(v).
+ *
+ *   dag        oriented CSR (as written by tc_orient)
+ *   triples    device int32[3 * capacity] (written): rows (u, v, w).  The rows
+ *              of one u are contiguous and sources come in increasing id order;
+ *              within one u the order is unspecified (the set is unique).
+ *   capacity   rows available in triples (at most 2^40)
+ *   count_out  device int64[1] (written): T, or -TC_ERR_CAPACITY when T >
+ *              capacity (then no row is written)
+ *   tune       launch parameters or NULL (as for tc_count)
+ *   ws, ws_bytes  workspace; O(n) bytes.
+ * Two passes: the per-source counts (the tc_count enumeration), their
+ * exclusive scan into row offsets, and the same enumeration writing rows.
+ */
+tc_status tc_list_triangles(const tc_csr* dag, int32_t* triples, int64_t capacity,
+                            int64_t* count_out, const tc_tune* tune, void* ws, size_t* ws_bytes,
+                            void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* tc_status_string(tc_status status);

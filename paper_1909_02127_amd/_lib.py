@@ -79,6 +79,8 @@ def _load() -> ctypes.CDLL:
     lib.tc_count_per_vertex.argtypes = [csr, p, p, tune, p, sz, p]
     lib.tc_count_batched.restype = i32
     lib.tc_count_batched.argtypes = [csr, i64, p, p, p, p, tune, p, sz, p]
+    lib.tc_list_triangles.restype = i32
+    lib.tc_list_triangles.argtypes = [csr, p, i64, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
     lib.tc_status_string.argtypes = [i32]
     lib.tc_last_error.restype = ctypes.c_char_p
@@ -147,9 +149,12 @@ def tc_build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, row_ptr: torch.Te
              _ptr(row_ptr), _ptr(col), col.numel(), _ptr(nnz_out), stream=stream)
 
 
-def tc_orient_workspace(n: int) -> int:
+def tc_orient_workspace(n: int, dag_col_capacity: int) -> int:
+    """Workspace bytes of tc_orient for n vertices and a DAG column capacity (the
+    workspace holds per-tile state for up to 2 * dag_col_capacity symmetric entries)."""
     csr = tc_csr(n, 4, None, None)
-    return _ws_query(LIB.tc_orient, ctypes.byref(csr), TC_ORDER_DEGREE, None, None, 0, None)
+    return _ws_query(LIB.tc_orient, ctypes.byref(csr), TC_ORDER_DEGREE, None, None,
+                     dag_col_capacity, None)
 
 
 def tc_orient(n: int, row_ptr: torch.Tensor, col: torch.Tensor, order: int,
@@ -205,6 +210,25 @@ def tc_count_batched(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_batched, ws, ctypes.byref(csr), g, _ptr(vtx_off), _ptr(totals),
              _ptr(per_vertex), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_list_triangles_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_list_triangles, ctypes.byref(csr), None, 0, None, None)
+
+
+def tc_list_triangles(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                      triples: torch.Tensor, count_out: torch.Tensor, ws: torch.Tensor, *,
+                      tune=None, stream=None) -> None:
+    """Rows (u, v, w) of every triangle into triples (int32[capacity, 3]); count_out
+    (int64[1]) receives T or -TC_ERR_CAPACITY."""
+    if triples.dtype != torch.int32 or triples.dim() != 2 or triples.shape[1] != 3:
+        raise ValueError("triples must be an int32 tensor of shape (capacity, 3)")
+    if count_out.dtype != torch.int64 or count_out.numel() != 1:
+        raise ValueError("count_out must be int64[1]")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_list_triangles, ws, ctypes.byref(csr), _ptr(triples), triples.shape[0],
+             _ptr(count_out), _tune_ref(tune), stream=stream)
 
 
 def tc_version() -> int:

@@ -96,7 +96,7 @@ class BatchRunner:
         self.totals = torch.zeros(max(batch.G, 1), dtype=torch.int64, device=dev)
         self.total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.pv = torch.zeros(max(batch.n, 1), dtype=torch.int64, device=dev) if per_vertex else None
-        self.ws_orient = _bytes(_lib.tc_orient_workspace(batch.n), dev)
+        self.ws_orient = _bytes(_lib.tc_orient_workspace(batch.n, self.dag_col.numel()), dev)
         self.ws_count = _bytes(_lib.tc_count_batched_workspace(batch.n), dev)
         self.graph = None
 
@@ -148,7 +148,8 @@ class PlainRunner:
         self.dag_col = torch.empty(max(batch.m, 1), dtype=torch.int32, device=dev)
         self.m_out = torch.zeros(max(batch.G, 1), dtype=torch.int64, device=dev)
         self.totals = torch.zeros(max(batch.G, 1), dtype=torch.int64, device=dev)
-        self.ws_orient = _bytes(_lib.tc_orient_workspace(nmax), dev)
+        mmax = max([v[2].numel() // 2 for v in self.views], default=0)
+        self.ws_orient = _bytes(_lib.tc_orient_workspace(nmax, mmax), dev)
         self.ws_count = _bytes(_lib.tc_count_workspace(nmax), dev)
         # per-graph DAG slices: rows at the same place as the local CSR, edges packed
         off = batch.vtx_off.cpu().tolist()

@@ -11,8 +11,9 @@
 //   2. LSD radix sort of the 2*num_pairs keys over their 2*cb significant bits,
 //      8 bits per pass: per-tile digit histograms, one scan over the
 //      digit-major histogram table, and a stable scatter that sorts each tile by
-//      digit in LDS (in-tile ranks from 8 wave ballots per key) and then writes
-//      every digit's run to consecutive addresses.
+//      digit in LDS (in-tile ranks from 8 wave ballots per key, each wave on its
+//      own quarter of the tile) and then writes every digit's run to
+//      consecutive addresses.
 //   3. One scan over "first of its run" flags drops duplicates and sentinels,
 //      writes col, and records the first position of every non-empty row.
 //   4. A suffix-minimum scan turns the row starts into row_ptr (empty rows take
@@ -76,58 +77,44 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
   hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile: keys of equal digit keep their input order.  The
-// tile is first sorted by digit in LDS (ranks from 8 wave ballots per key and a
-// running count per digit), then written out so that each digit's run lands at
-// consecutive global addresses (coalesced stores).
+// Stable scatter of one tile: keys of equal digit keep their input order.  Each
+// wave ranks its own contiguous quarter of the tile, 64 keys per round (peers of
+// equal digit from 8 ballots, a per-wave running count per digit), so the only
+// workgroup barriers are the few between the phases.  The tile is then sorted by
+// digit in LDS and written so that each digit's run lands at consecutive global
+// addresses (coalesced stores).
 __global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
     const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int64_t nk, int shift, int bits,
     const uint32_t* __restrict__ offsets, int64_t num_tiles) {
+  constexpr int kWaves = kRadixBlock / kWave;
+  constexpr int kPerWave = kRadixItems * kWave;
   __shared__ uint64_t lkeys[kRadixTile];
-  __shared__ uint32_t gbase[256];   // global start of this tile's run of each digit
-  __shared__ uint32_t lstart[256];  // start of each digit's run inside the tile
-  __shared__ uint32_t run[256];     // keys of each digit placed so far
-  __shared__ uint32_t wcnt[kRadixBlock / kWave][256];
-  __shared__ uint32_t wave_tot[kRadixBlock / kWave];
+  __shared__ uint32_t gbase[256];        // global start of this tile's run of each digit
+  __shared__ uint32_t lstart[256];       // start of each digit's run inside the tile
+  __shared__ uint32_t wcnt[kWaves][256]; // per-wave digit counts, then per-wave starts
+  __shared__ uint32_t wave_tot[kWaves];
   const int t = threadIdx.x;
   const int wave = t / kWave;
+  const int lane = lane_id();
   const uint32_t mask = (1u << bits) - 1u;
   const int64_t tile = (int64_t)blockIdx.x * kRadixTile;
   const int valid_n = (int)(nk - tile < kRadixTile ? nk - tile : kRadixTile);
   gbase[t] = offsets[(int64_t)t * num_tiles + blockIdx.x];
-  run[t] = 0;
 #pragma unroll
-  for (int w = 0; w < kRadixBlock / kWave; ++w) wcnt[w][t] = 0;
+  for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
   __syncthreads();
-  // digit histogram of the tile -> exclusive starts
+  const int wbase = wave * kPerWave;
   uint64_t k[kRadixItems];
+  uint32_t rk[kRadixItems];
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const int i = r * kRadixBlock + t;
+    const int i = wbase + r * kWave + lane;
     k[r] = i < valid_n ? in[tile + i] : 0;
-    if (i < valid_n) atomicAdd(&run[(uint32_t)(k[r] >> shift) & mask], 1u);
   }
-  __syncthreads();
-  {
-    const uint32_t c = run[t];
-    uint32_t x = c;
+  // rank of every key among the equal-digit keys before it in this wave's quarter
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t y = __shfl_up(x, off, kWave);
-      if (lane_id() >= off) x += y;
-    }
-    if (lane_id() == kWave - 1) wave_tot[wave] = x;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int w = 0; w < wave; ++w) before += wave_tot[w];
-    lstart[t] = before + x - c;
-    run[t] = 0;
-  }
-  __syncthreads();
-  // stable placement, one round of 256 keys at a time
   for (int r = 0; r < kRadixItems; ++r) {
-    const int i = r * kRadixBlock + t;
-    const bool ok = i < valid_n;
+    const bool ok = wbase + r * kWave + lane < valid_n;
     const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
     uint64_t peers = ballot(ok);
     for (int b = 0; b < bits; ++b) {
@@ -136,23 +123,43 @@ __global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
       peers &= bit ? bal : ~bal;
     }
     const uint32_t rank = rank_below(peers);
-    if (ok && rank == 0) wcnt[wave][d] = popc(peers);
-    __syncthreads();
-    if (ok) {
-      uint32_t pos = lstart[d] + run[d] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      lkeys[pos] = k[r];
-    }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int w = 0; w < kRadixBlock / kWave; ++w) {
-      add += wcnt[w][t];
-      wcnt[w][t] = 0;
-    }
-    run[t] += add;
-    __syncthreads();
+    const uint32_t before = wcnt[wave][d];
+    rk[r] = before + rank;
+    wave_sync();
+    if (ok && rank == 0) wcnt[wave][d] = before + popc(peers);
+    wave_sync();
   }
+  __syncthreads();
+  // digit t: start of each wave's run inside the digit, and the digit's total
+  uint32_t tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t c = wcnt[w][t];
+    wcnt[w][t] = tot;
+    tot += c;
+  }
+  {
+    uint32_t x = tot;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, kWave);
+      if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) wave_tot[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    lstart[t] = before + x - tot;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    if (wbase + r * kWave + lane < valid_n) {
+      const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
+      lkeys[lstart[d] + wcnt[wave][d] + rk[r]] = k[r];
+    }
+  }
+  __syncthreads();
   // coalesced write-out of the digit-sorted tile
   for (int j = t; j < valid_n; j += kRadixBlock) {
     const uint64_t key = lkeys[j];

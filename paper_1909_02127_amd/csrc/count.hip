@@ -32,6 +32,7 @@
 #include "tc_device.h"
 #include "tc_hash.h"
 #include "tc_host.h"
+#include "tc_scan.h"
 
 #include <stdlib.h>
 
@@ -55,6 +56,11 @@ constexpr int kWin = 2;          // 64-wide windows per step of that walk
 constexpr int32_t kEmpty = -1;
 constexpr int32_t kNoKey = -2;  // probe value of an inactive lane: never stored
 constexpr int kNumClasses = 8;  // 0..6: workgroup classes by size (largest first), 7: small
+
+// What a count launch produces.
+constexpr int kKindTotal = 0;      // the total (and optionally per-graph / per-source sums)
+constexpr int kKindPerVertex = 1;  // plus t(v) for every vertex
+constexpr int kKindList = 2;       // every triangle as a (u, v, w) row
 
 // Probe modes, fixed per table slice after it is built.
 constexpr int kModeCuckoo = 0;  // every key sits in one of its two cuckoo slots
@@ -262,12 +268,43 @@ __device__ __forceinline__ bool probe(const Table& t, const Slice& sl, int32_t w
   return hit;
 }
 
+// Listing output of one source u: its rows start at `base`; a group-shared LDS
+// cursor hands out row slots as hits arrive (rows of one source are
+// contiguous, in no particular order).
+struct ListCtx {
+  int32_t* out;     // int32[3 * cap]
+  int64_t base;
+  int64_t cap;
+  int32_t* cursor;  // LDS
+  int32_t u;
+};
+
+// Writes the wedges u -> v -> w of the lanes set in `hits` as rows (u, v, w).
+// Called by the whole wave (lane 0 takes the slots).
+__device__ __forceinline__ void emit(const ListCtx& c, uint64_t hits, int32_t v, int32_t w) {
+  if (!hits) return;
+  int32_t start = 0;
+  if (lane_id() == 0) start = atomicAdd(c.cursor, (int32_t)popc(hits));
+  start = __shfl(start, 0, kWave);
+  if ((hits >> lane_id()) & 1u) {
+    const int64_t row = c.base + start + rank_below(hits);
+    if (row < c.cap) {
+      int32_t* o = c.out + 3 * row;
+      o[0] = c.u;
+      o[1] = v;
+      o[2] = w;
+    }
+  }
+}
+
 // Hits among the `len` ids of one out-neighbour list `lst` (len >= 1).  Four
 // 64-wide loads are issued before any probe so each wave keeps several memory
 // requests in flight; the tail clamps its indices to stay inside the list.
-template <bool PV, int Mode, bool Wide>
+template <int K, int Mode, bool Wide>
 __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, int len,
-                                              const Table& t, const Slice& sl) {
+                                              const Table& t, const Slice& sl, int32_t v,
+                                              const ListCtx& lc) {
+  constexpr bool PV = K == kKindPerVertex;
   const int lane = lane_id();
   uint32_t hv = 0;
   int base = 0;
@@ -277,7 +314,11 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) w[k] = p[k * kWave];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) hv += popc(ballot(probe<PV, Mode, Wide>(t, sl, w[k])));
+    for (int k = 0; k < kUnroll; ++k) {
+      const uint64_t b = ballot(probe<PV, Mode, Wide>(t, sl, w[k]));
+      hv += popc(b);
+      if (K == kKindList) emit(lc, b, v, w[k]);
+    }
   }
   if (base < len) {
     const int last = len - 1;
@@ -290,7 +331,11 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
     }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
-      if (base + k * kWave < len) hv += popc(ballot(probe<PV, Mode, Wide>(t, sl, w[k])));
+      if (base + k * kWave < len) {
+        const uint64_t b = ballot(probe<PV, Mode, Wide>(t, sl, w[k]));
+        hv += popc(b);
+        if (K == kKindList) emit(lc, b, v, w[k]);
+      }
     }
   }
   return hv;
@@ -303,11 +348,12 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
 // marked in LDS and propagated with a wave max-scan.  The marker array holds -1
 // between walks (the writer clears its own entry after the step; a wave's LDS
 // operations complete in program order).  Returns the hits (uniform).
-template <bool PV, int Mode, bool Wide, typename OffT>
+template <int K, int Mode, bool Wide, typename OffT>
 __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
                                                const int32_t* __restrict__ col, const Table& t,
                                                const Slice& sl, const WaveScratch& ws,
-                                               uint64_t* __restrict__ tv) {
+                                               uint64_t* __restrict__ tv, const ListCtx& lc) {
+  constexpr bool PV = K == kKindPerVertex;
   const int lane = lane_id();
   const int32_t incl = wave_inclusive_sum32(len);
   const int32_t start = incl - len;
@@ -329,11 +375,12 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
     }
     wave_sync();
     if (marks) ws.mark[start - base] = -1;
-    int32_t w[kWin];
+    int32_t w[kWin], mid[kWin];
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       const int32_t pos = base + k * kWave + lane;
       const int32_t sk = seg[k] < 0 ? 0 : seg[k];
+      mid[k] = K == kKindList ? __shfl(v, sk, kWave) : 0;
       const int32_t off = pos - __shfl(start, sk, kWave);
       const int32_t slen = __shfl(len, sk, kWave);
       const OffT sb = __shfl(vb, sk, kWave);
@@ -344,8 +391,10 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
     for (int k = 0; k < kWin; ++k) {
       if (base + k * kWave < total) {
         const bool hit = probe<PV, Mode, Wide>(t, sl, w[k]);
-        hv += popc(ballot(hit));
+        const uint64_t b = ballot(hit);
+        hv += popc(b);
         if (PV && hit) atomicAdd(&ws.shits[seg[k]], 1u);
+        if (K == kKindList) emit(lc, b, mid[k], w[k]);
       }
     }
   }
@@ -361,11 +410,12 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
 // i = gwave, gwave + Waves, ...; 64 of them are prefetched per batch.  Lists of
 // kShortMax or more ids are streamed one at a time; shorter ones are walked
 // together by scan_short.  Empty lists add nothing (1-look-ahead).
-template <int Waves, bool PV, int Mode, bool Wide, typename OffT>
+template <int Waves, int K, int Mode, bool Wide, typename OffT>
 __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
                                  const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                  uint64_t* __restrict__ tv, const Table& t, const Slice& sl,
-                                 const WaveScratch& ws) {
+                                 const WaveScratch& ws, const ListCtx& lc) {
+  constexpr bool PV = K == kKindPerVertex;
   const int lane = lane_id();
   const int gwave = Waves == 1 ? 0 : (int)threadIdx.x / kWave;
   uint64_t src_hits = 0;
@@ -394,17 +444,15 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
         jb = read_lane64((int64_t)vb, j);
         je = read_lane64((int64_t)ve, j);
       }
-      const uint32_t hv = scan_list<PV, Mode, Wide>(col + jb, (int)(je - jb), t, sl);
+      const int32_t vj = read_lane(v, j);
+      const uint32_t hv = scan_list<K, Mode, Wide>(col + jb, (int)(je - jb), t, sl, vj, lc);
       src_hits += hv;
-      if (PV && hv && lane == 0) {
-        const int32_t vj = read_lane(v, j);
-        atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
-      }
+      if (PV && hv && lane == 0) atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
     }
     if (walk_short) {
       const bool is_short = len > 0 && len < kShortMax;
-      src_hits += scan_short<PV, Mode, Wide, OffT>(v, vb, is_short ? (int32_t)len : 0, col, t, sl,
-                                                   ws, tv);
+      src_hits += scan_short<K, Mode, Wide, OffT>(v, vb, is_short ? (int32_t)len : 0, col, t, sl,
+                                                  ws, tv, lc);
     }
   }
   return src_hits;
@@ -412,17 +460,30 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
 
 // Process one source u with a group of Waves waves sharing table `t`.
 // Returns this wave's hit count (uniform across the wave).
-template <int Waves, bool PV, bool Wide, typename OffT>
+// Where the listing pass writes: rows of source u start at off[u].
+struct ListArgs {
+  int32_t* out;
+  const int64_t* off;
+  int64_t cap;
+};
+
+template <int Waves, int K, bool Wide, typename OffT>
 __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
                                    const int32_t* __restrict__ col, uint64_t* __restrict__ tv,
                                    const Table& t, const WaveScratch& ws, int max_keys,
-                                   int max_kicks, bool force_sorted) {
+                                   int max_kicks, bool force_sorted, const ListArgs& la) {
+  constexpr bool PV = K == kKindPerVertex;
   const int lane = lane_id();
   const int gr = group_rank<Waves>();
   const int64_t beg = row_ptr[u];
   const int64_t d = (int64_t)row_ptr[u + 1] - beg;
   const int32_t* nbrs = col + beg;
   uint64_t wave_hits = 0;
+  ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u};
+  if (K == kKindList) {
+    lc.base = la.off[u];
+    if (gr == 0) t.meta[3] = 0;  // ordered before any hit by the slice's first barrier
+  }
   for (int64_t c0 = 0; c0 < d; c0 += max_keys) {
     Slice sl;
     sl.keys = (int)(d - c0 < max_keys ? d - c0 : max_keys);
@@ -464,11 +525,11 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
     }
     uint64_t src_hits;
     if (mode == kModeCuckoo)
-      src_hits = scan_middles<Waves, PV, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws);
+      src_hits = scan_middles<Waves, K, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
     else if (mode == kModeStash)
-      src_hits = scan_middles<Waves, PV, kModeStash, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws);
+      src_hits = scan_middles<Waves, K, kModeStash, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
     else
-      src_hits = scan_middles<Waves, PV, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws);
+      src_hits = scan_middles<Waves, K, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
     wave_hits += src_hits;
     if (PV) {
       if (src_hits && lane == 0) atomicAdd((unsigned long long*)&tv[u], (unsigned long long)src_hits);
@@ -497,6 +558,9 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
 struct CountArgs {
   const int32_t* gid;  // batched mode: graph of each vertex (-1: none); else null
   uint64_t* totals;    // batched mode: per-graph totals; else null
+  uint64_t* src_cnt;   // listing, first pass: hits of each source; else null
+  const int64_t* list_status;  // listing pass: the row count, negative if over capacity
+  ListArgs list;
   int max_kicks;
   int force_sorted;
 };
@@ -505,14 +569,16 @@ struct CountArgs {
 // through a global cursor after a static first round), then wave-mode sources
 // round robin.  In batched mode each source's hits are also added to the total
 // of its graph.
-template <bool PV, bool Wide, typename OffT>
+template <int K, bool Wide, typename OffT>
 __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
                                                        const int32_t* __restrict__ list,
                                                        CountState* __restrict__ st,
                                                        uint64_t* __restrict__ total,
                                                        uint64_t* __restrict__ tv, CountArgs args) {
+  constexpr bool PV = K == kKindPerVertex;
   __shared__ __align__(16) char smem[smem_total(PV)];
+  if (K == kKindList && *args.list_status < 0) return;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   WaveScratch ws;
@@ -534,13 +600,15 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   const Table big = table_at<PV>(smem, kSideMax);
   for (int32_t idx = blockIdx.x; idx < n_large;) {
     const int32_t u = list[idx];
-    const uint64_t h = process_source<kWavesPerBlock, PV, Wide, OffT>(
-        u, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted);
+    const uint64_t h = process_source<kWavesPerBlock, K, Wide, OffT>(
+        u, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, args.list);
     hits += h;
     if (args.totals && h && lane == 0) {
       const int32_t g = args.gid[u];
       if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
     }
+    if (args.src_cnt && h && lane == 0)
+      atomicAdd((unsigned long long*)&args.src_cnt[u], (unsigned long long)h);
     if (threadIdx.x == 0) big.meta[2] = (int32_t)gridDim.x + atomicAdd(&st->large_cursor, 1);
     __syncthreads();
     idx = big.meta[2];
@@ -562,14 +630,16 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
                                  : first + 1;
     for (int32_t i = first; i < last; ++i) {
       const int32_t u = list[n_large + i];
-      const uint64_t h = process_source<1, PV, Wide, OffT>(u, row_ptr, col, tv, mine, ws,
-                                                           kSmallMax, args.max_kicks,
-                                                           args.force_sorted);
+      const uint64_t h = process_source<1, K, Wide, OffT>(u, row_ptr, col, tv, mine, ws,
+                                                          kSmallMax, args.max_kicks,
+                                                          args.force_sorted, args.list);
       hits += h;
       if (args.totals && h && lane == 0) {
         const int32_t g = args.gid[u];
         if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
       }
+      if (args.src_cnt && h && lane == 0)
+        atomicAdd((unsigned long long*)&args.src_cnt[u], (unsigned long long)h);
     }
     if (dynamic) {
       int32_t next = 0;
@@ -645,7 +715,7 @@ tc_status read_tune(const tc_tune* tune, Tune* out) {
   return TC_OK;
 }
 
-template <bool PV, bool Wide, typename OffT>
+template <int K, bool Wide, typename OffT>
 int count_grid(int blocks_per_cu) {
   static int cached[64] = {0};
   int dev = 0;
@@ -653,7 +723,7 @@ int count_grid(int blocks_per_cu) {
   if (dev < 0 || dev >= 64) dev = 0;
   if (cached[dev] == 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_kernel<PV, Wide, OffT>, kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_kernel<K, Wide, OffT>, kBlock, 0) !=
             hipSuccess ||
         per_cu <= 0) {
       per_cu = 2;
@@ -664,19 +734,44 @@ int count_grid(int blocks_per_cu) {
   return per_cu * device_cu_count();
 }
 
-template <bool PV, typename OffT>
-tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_t* total,
-                     uint64_t* tv, int64_t num_graphs, const int64_t* vtx_off, uint64_t* totals,
-                     const Tune& tune, const CountLayout& L, hipStream_t s) {
-  uint64_t* tot = total ? total : L.total_scratch;
+CountArgs base_args(const Tune& tune) {
   CountArgs args;
   args.gid = nullptr;
   args.totals = nullptr;
+  args.src_cnt = nullptr;
+  args.list_status = nullptr;
+  args.list = ListArgs{nullptr, nullptr, 0};
   args.force_sorted = tune.force_sorted;
   // Test hook: TC_TEST_MAX_KICKS caps cuckoo evictions so that tests can drive
   // keys into the stash (and past it, into the sorted fallback).
   args.max_kicks = kMaxKicks;
   if (const char* env = getenv("TC_TEST_MAX_KICKS")) args.max_kicks = atoi(env);
+  return args;
+}
+
+// The persistent count launch over the binned sources, capped at one workgroup
+// per 16 vertices so that a small graph launches a small grid.
+template <int K, typename OffT>
+void launch_count(int64_t n, const OffT* row_ptr, const int32_t* col, const CountLayout& L,
+                  uint64_t* tot, uint64_t* tv, const CountArgs& args, const Tune& tune,
+                  hipStream_t s) {
+  const int64_t cap = (n + 15) / 16;
+  if (n <= (int64_t(1) << 24)) {
+    const int grid = (int)std::min<int64_t>(count_grid<K, false, OffT>(tune.blocks_per_cu), cap);
+    count_kernel<K, false, OffT><<<grid, kBlock, 0, s>>>(row_ptr, col, L.list, L.st, tot, tv, args);
+  } else {
+    const int grid = (int)std::min<int64_t>(count_grid<K, true, OffT>(tune.blocks_per_cu), cap);
+    count_kernel<K, true, OffT><<<grid, kBlock, 0, s>>>(row_ptr, col, L.list, L.st, tot, tv, args);
+  }
+}
+
+template <bool PV, typename OffT>
+tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_t* total,
+                     uint64_t* tv, int64_t num_graphs, const int64_t* vtx_off, uint64_t* totals,
+                     const Tune& tune, const CountLayout& L, hipStream_t s) {
+  constexpr int K = PV ? kKindPerVertex : kKindTotal;
+  uint64_t* tot = total ? total : L.total_scratch;
+  CountArgs args = base_args(tune);
   init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
   if (PV) zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(tv, n);
   if (totals) {
@@ -691,16 +786,7 @@ tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_
     bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st, tune.small_max);
     bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
         n, row_ptr, L.st, L.list, tune.small_max);
-    // The persistent grid, capped at one workgroup per 16 vertices so that a small
-    // graph launches a small grid.
-    const int64_t cap = (n + 15) / 16;
-    if (n <= (int64_t(1) << 24)) {
-      const int grid = (int)std::min<int64_t>(count_grid<PV, false, OffT>(tune.blocks_per_cu), cap);
-      count_kernel<PV, false, OffT><<<grid, kBlock, 0, s>>>(row_ptr, col, L.list, L.st, tot, tv, args);
-    } else {
-      const int grid = (int)std::min<int64_t>(count_grid<PV, true, OffT>(tune.blocks_per_cu), cap);
-      count_kernel<PV, true, OffT><<<grid, kBlock, 0, s>>>(row_ptr, col, L.list, L.st, tot, tv, args);
-    }
+    launch_count<K, OffT>(n, row_ptr, col, L, tot, tv, args, tune, s);
   }
   return check_hip(hipGetLastError(), "tc_count launch");
 }
@@ -742,8 +828,109 @@ tc_status count_dispatch(const tc_csr* dag, uint64_t* total, uint64_t* tv, bool 
   return st == TC_OK ? ok() : st;
 }
 
+// ---- listing: per-source counts -> row offsets -> the rows themselves ----------
+
+__global__ void reset_cursors_kernel(CountState* st, uint64_t* total) {
+  st->large_cursor = 0;
+  st->small_cursor = 0;
+  *total = 0;
+}
+
+struct SrcLoad {
+  const uint64_t* cnt;
+  __device__ int64_t operator()(int64_t i) const { return (int64_t)cnt[i]; }
+};
+struct SrcStore {
+  int64_t* off;
+  __device__ void operator()(int64_t i, int64_t p) const { off[i] = p; }
+};
+
+__global__ void list_finalize_kernel(const int64_t* total, int64_t cap, int64_t* count_out) {
+  const int64_t t = *total;
+  *count_out = t > cap ? -(int64_t)TC_ERR_CAPACITY : t;
+}
+
+struct ListLayout {
+  CountLayout c;
+  uint64_t* src_cnt;
+  int64_t* src_off;
+  int64_t* partial;
+  size_t bytes;
+};
+
+ListLayout carve_list(void* ws, int64_t n) {
+  Carver c(ws);
+  ListLayout L;
+  L.c.st = c.take<CountState>(1);
+  L.c.list = c.take<int32_t>(n);
+  L.c.total_scratch = c.take<uint64_t>(1);
+  L.c.gid = nullptr;
+  L.src_cnt = c.take<uint64_t>(n);
+  L.src_off = c.take<int64_t>(n);
+  L.partial = c.take<int64_t>(scan_partial_len(n));
+  L.bytes = c.used();
+  L.c.bytes = L.bytes;
+  return L;
+}
+
+// Pass 1 counts the hits of every source (the same persistent launch as
+// tc_count), a scan turns them into row offsets, and pass 2 repeats the
+// enumeration writing each hit as a row.  Both passes find exactly the same
+// hits per source, so every source writes inside its own range.
+template <typename OffT>
+tc_status list_impl(int64_t n, const OffT* row_ptr, const int32_t* col, int32_t* out, int64_t cap,
+                    int64_t* count_out, const Tune& tune, const ListLayout& L, hipStream_t s) {
+  uint64_t* tot = L.c.total_scratch;
+  init_state_kernel<<<1, 64, 0, s>>>(L.c.st, tot);
+  zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(L.src_cnt, n);
+  if (n > 0) {
+    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.c.st, tune.small_max);
+    bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
+        n, row_ptr, L.c.st, L.c.list, tune.small_max);
+    CountArgs a1 = base_args(tune);
+    a1.src_cnt = L.src_cnt;
+    launch_count<kKindTotal, OffT>(n, row_ptr, col, L.c, tot, nullptr, a1, tune, s);
+  }
+  hipError_t e = scan_exclusive<OpSum>(n, SrcLoad{L.src_cnt}, SrcStore{L.src_off}, L.partial, s);
+  if (e != hipSuccess) return check_hip(e, "listing offset scan");
+  list_finalize_kernel<<<1, 1, 0, s>>>(L.partial + scan_num_tiles(n), cap, count_out);
+  if (n > 0) {
+    reset_cursors_kernel<<<1, 1, 0, s>>>(L.c.st, tot);
+    CountArgs a2 = base_args(tune);
+    a2.list_status = count_out;
+    a2.list = ListArgs{out, L.src_off, cap};
+    launch_count<kKindList, OffT>(n, row_ptr, col, L.c, tot, nullptr, a2, tune, s);
+  }
+  return check_hip(hipGetLastError(), "tc_list_triangles launch");
+}
+
 }  // namespace
 }  // namespace tc
+
+extern "C" tc_status tc_list_triangles(const tc_csr* dag, int32_t* triples, int64_t capacity,
+                                       int64_t* count_out, const tc_tune* tune, void* ws,
+                                       size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  tc_status st = check_dag(dag);
+  if (st != TC_OK) return st;
+  Tune t;
+  if ((st = read_tune(tune, &t)) != TC_OK) return st;
+  if (capacity < 0) return fail(TC_ERR_INVALID_ARG, "negative capacity");
+  if (capacity > ((int64_t)1 << 40))
+    return fail(TC_ERR_UNSUPPORTED, "capacity=%lld is beyond 2^40", (long long)capacity);
+  if (workspace_query(ws, ws_bytes, carve_list(nullptr, dag->n).bytes, &st)) return st;
+  if (!dag->row_ptr || !count_out || (capacity > 0 && !triples))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const ListLayout L = carve_list(ws, dag->n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dag->offset_bytes == 4)
+    st = list_impl<int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col, triples,
+                            capacity, count_out, t, L, s);
+  else
+    st = list_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, triples,
+                            capacity, count_out, t, L, s);
+  return st == TC_OK ? ok() : st;
+}
 
 extern "C" tc_status tc_count(const tc_csr* dag, uint64_t* total, const tc_tune* tune, void* ws,
                               size_t* ws_bytes, void* stream) {

@@ -7,12 +7,19 @@
 // out-degree O(sqrt(m)) so N+(u) fits in LDS during counting.  TC_ORDER_ID is
 // the paper's own "destination id larger than source id" rule.
 //
-// Pass 1 counts kept entries per row, a scan turns the counts into the DAG's
-// row offsets, pass 2 writes the kept entries in row order (ballot + mbcnt keeps
-// the order).  A wave takes four rows at a time: when all four have at most
-// kShortRow entries it gives each 16 lanes, otherwise it walks them one after
-// the other with all 64 lanes.  Rows longer than kLongRow are queued and walked
-// by a whole workgroup.
+// Orientation is a stream compaction of the symmetric column array: rows are
+// stored in order and each row's entries in order, so the DAG position of a kept
+// entry is the number of kept entries before it in the whole array, and
+// dag_row_ptr[u] is that count at row_ptr[u].  The entries are cut into tiles of
+// kTile consecutive positions, whatever the row boundaries, so a hub row is
+// spread over many workgroups and a tile of short rows costs the same as a tile
+// of one long row:
+//   rows   deg[u], and for every tile the first row starting at or after it
+//   flags  per tile: the row of each entry (segment-start markers + max-scan),
+//          the keep bit of each entry, the kept count
+//   scan   exclusive scan of the tile counts
+//   write  per tile: the kept entries compacted through LDS and written
+//          contiguously, and dag_row_ptr of the rows starting in the tile
 #include "tc_device.h"
 #include "tc_host.h"
 #include "tc_scan.h"
@@ -24,225 +31,222 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int64_t kLongRow = 2048;
-constexpr int32_t kShortRow = 64;
-constexpr int kGroup = 16;  // lanes per short row
-constexpr int kGroupsPerWave = kWave / kGroup;
+constexpr int kItems = 16;              // entries per thread and tile
+constexpr int kTile = kBlock * kItems;  // entries per tile
+constexpr int kPadded = kTile + kTile / kItems;
+constexpr int kTileBlocksPerCu = 4;     // LDS: about 35 KB per workgroup
 
-template <typename OffT>
-__global__ __launch_bounds__(256) void degree_kernel(int64_t n, const OffT* __restrict__ row_ptr,
-                                                     int32_t* __restrict__ deg) {
+// LDS index of tile entry i, padded so that a thread's kItems consecutive
+// entries fall into distinct banks across a wave.
+__device__ __forceinline__ int padded(int i) { return i + (i >> 4); }
+
+struct TileInfo {
+  int64_t nnz;        // row_ptr[n]
+  int64_t num_tiles;  // ceil(nnz / kTile)
+  int32_t over;       // nnz needs more tiles than the workspace provides
+  int32_t pad[3];
+};
+
+template <typename OffT, int Order>
+__global__ __launch_bounds__(256) void rows_kernel(int64_t n, const OffT* __restrict__ row_ptr,
+                                                   int32_t* __restrict__ deg,
+                                                   int32_t* __restrict__ row_start,
+                                                   int64_t tiles_max, TileInfo* __restrict__ info) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    deg[v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n; u += stride) {
+    const int64_t here = row_ptr[u];
+    if (Order == TC_ORDER_DEGREE && u < n) deg[u] = (int32_t)(row_ptr[u + 1] - here);
+    // the tiles t with row_ptr[u-1] < t * kTile <= row_ptr[u] first reach row u
+    const int64_t t0 = u == 0 ? 0 : (int64_t)row_ptr[u - 1] / kTile + 1;
+    int64_t t1 = here / kTile;
+    if (t1 > tiles_max) t1 = tiles_max;
+    for (int64_t t = t0; t <= t1; ++t) row_start[t] = (int32_t)u;
+    if (u == n) {
+      const int64_t tiles = (here + kTile - 1) / kTile;
+      info->nnz = here;
+      info->num_tiles = tiles;
+      info->over = tiles > tiles_max;
+    }
+  }
 }
 
 template <int Order>
-__device__ __forceinline__ bool keep_edge(int64_t u, int32_t du, int32_t v,
-                                          const int32_t* __restrict__ deg) {
+__device__ __forceinline__ bool keep_edge(int32_t u, int32_t v, const int32_t* __restrict__ deg) {
   if (Order == TC_ORDER_ID) return u < v;
-  const int32_t dv = deg[v];
+  const int32_t du = deg[u], dv = deg[v];
   return du < dv || (du == dv && u < v);
 }
 
-// Largest length among the four 16-lane groups of a wave (uniform).
-__device__ __forceinline__ int32_t group_max(int32_t len) {
-  int32_t a = read_lane(len, 0), b = read_lane(len, 16), c = read_lane(len, 32),
-          d = read_lane(len, 48);
-  a = a > b ? a : b;
-  c = c > d ? c : d;
-  return a > c ? a : c;
-}
-
-__global__ void clear_counter_kernel(int32_t* c) { *c = 0; }
-
-// Pass 1 (rows up to kLongRow): four rows per wave; short rows counted 16 lanes
-// each, otherwise one row at a time with the whole wave; long rows are queued.
-template <typename OffT, int Order>
-__global__ __launch_bounds__(kBlock) void count_rows_kernel(
-    int64_t n, const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ deg, int64_t* __restrict__ outdeg, int32_t* __restrict__ long_rows,
-    int32_t* __restrict__ long_count) {
-  const int lane = lane_id();
-  const int g = lane / kGroup, gl = lane % kGroup;
-  const uint64_t gmask = 0xFFFFull << (kGroup * g);
-  const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kGroupsPerWave;
-       r0 < n; r0 += waves * kGroupsPerWave) {
-    const int64_t u = r0 + g;
-    int64_t beg = 0, end = 0;
-    if (u < n) {
-      beg = row_ptr[u];
-      end = row_ptr[u + 1];
-    }
-    const int64_t len64 = end - beg;
-    const int32_t len = len64 > kShortRow ? kShortRow + 1 : (int32_t)len64;
-    const int32_t widest = group_max(len);
-    if (widest <= kShortRow) {
-      const int32_t iters = (widest + kGroup - 1) / kGroup;
-      uint32_t kept = 0;
-      for (int32_t k = 0; k < iters; ++k) {
-        const int32_t j = k * kGroup + gl;
-        const bool kk = j < len && keep_edge<Order>(u, len, col[beg + j], deg);
-        kept += popc(ballot(kk) & gmask);
-      }
-      if (gl == 0 && u < n) outdeg[u] = kept;
-      continue;
-    }
-    for (int r = 0; r < kGroupsPerWave && r0 + r < n; ++r) {
-      const int64_t ur = r0 + r;
-      const int64_t rb = read_lane64(beg, r * kGroup), re = read_lane64(end, r * kGroup);
-      if (re - rb > kLongRow) {
-        if (lane == 0) long_rows[atomicAdd(long_count, 1)] = (int32_t)ur;
-        continue;
-      }
-      const int32_t du = (int32_t)(re - rb);
-      uint32_t kept = 0;
-      for (int64_t e = rb + lane; e - lane < re; e += kWave) {
-        const bool kk = e < re && keep_edge<Order>(ur, du, col[e], deg);
-        kept += popc(ballot(kk));
-      }
-      if (lane == 0) outdeg[ur] = kept;
-    }
-  }
-}
-
-// Pass 1 (long rows): one workgroup per queued row.
-template <typename OffT, int Order>
-__global__ __launch_bounds__(kBlock) void count_long_kernel(const OffT* __restrict__ row_ptr,
-                                                            const int32_t* __restrict__ col,
-                                                            const int32_t* __restrict__ deg,
-                                                            int64_t* __restrict__ outdeg,
-                                                            const int32_t* __restrict__ long_rows,
-                                                            const int32_t* __restrict__ long_count) {
-  __shared__ uint32_t wave_kept[kWavesPerBlock];
+// Block-wide exclusive max-scan of one int32 per thread (-1 before the first).
+// Contains barriers: all threads call.
+__device__ __forceinline__ int32_t block_exclusive_max(int32_t x, int32_t* wave_tot) {
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
-  const int32_t count = *long_count;
-  for (int32_t li = blockIdx.x; li < count; li += gridDim.x) {
-    const int64_t u = long_rows[li];
-    const int64_t beg = row_ptr[u], end = row_ptr[u + 1];
-    const int32_t du = (int32_t)(end - beg);
-    uint32_t kept = 0;
-    for (int64_t e = beg + threadIdx.x; e - threadIdx.x < end; e += kBlock) {
-      const bool k = e < end && keep_edge<Order>(u, du, col[e], deg);
-      kept += popc(ballot(k));
-    }
-    if (lane == 0) wave_kept[wave] = kept;
+  const int32_t inc = wave_inclusive_max32(x);
+  if (lane == kWave - 1) wave_tot[wave] = inc;
+  __syncthreads();
+  int32_t before = -1;
+#pragma unroll
+  for (int w = 0; w < kWavesPerBlock; ++w)
+    if (w < wave) before = before > wave_tot[w] ? before : wave_tot[w];
+  __syncthreads();
+  int32_t exc = __shfl_up(inc, 1, kWave);
+  if (lane == 0) exc = -1;
+  return before > exc ? before : exc;
+}
+
+// Block-wide exclusive sum of one int32 per thread; *total gets the sum.
+// Contains barriers: all threads call.
+__device__ __forceinline__ int32_t block_exclusive_sum(int32_t x, int32_t* wave_tot,
+                                                       int32_t* total) {
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int32_t inc = wave_inclusive_sum32(x);
+  if (lane == kWave - 1) wave_tot[wave] = inc;
+  __syncthreads();
+  int32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWavesPerBlock; ++w) {
+    if (w < wave) before += wave_tot[w];
+    all += wave_tot[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - x;
+}
+
+// The tile's entries into LDS with coalesced reads (entry i at padded(i)).
+__device__ __forceinline__ void load_tile(const int32_t* __restrict__ col, int64_t e0, int len,
+                                          int32_t* sval) {
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int i = k * kBlock + (int)threadIdx.x;
+    sval[padded(i)] = i < len ? col[e0 + i] : 0;
+  }
+}
+
+// Pass 1: the keep bit of every entry (kItems bits per thread, in entry order)
+// and the kept count of every tile.
+template <typename OffT, int Order>
+__global__ __launch_bounds__(kBlock) void flags_kernel(
+    int64_t n, const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ deg, const int32_t* __restrict__ row_start,
+    const TileInfo* __restrict__ info, uint16_t* __restrict__ bits, int32_t* __restrict__ tile_cnt) {
+  __shared__ int32_t sval[kPadded];
+  __shared__ int32_t smark[kPadded];
+  __shared__ int32_t wave_tot[kWavesPerBlock];
+  if (info->over) return;
+  const int64_t num_tiles = info->num_tiles, nnz = info->nnz;
+  const int tid = threadIdx.x;
+  for (int64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
+    const int64_t e0 = t * kTile;
+    const int len = (int)(nnz - e0 < kTile ? nnz - e0 : kTile);
+    const int32_t r_lo = row_start[t];
+    const int64_t r_hi = t + 1 < num_tiles ? (int64_t)row_start[t + 1] : n;
+    load_tile(col, e0, len, sval);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) smark[padded(k * kBlock + tid)] = -1;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t s = 0;
-      for (int w = 0; w < kWavesPerBlock; ++w) s += wave_kept[w];
-      outdeg[u] = s;
+    // each non-empty row starting in the tile marks its first entry
+    for (int64_t u = r_lo + tid; u < r_hi; u += kBlock) {
+      const int64_t b = (int64_t)row_ptr[u] - e0;
+      if (row_ptr[u + 1] > row_ptr[u] && b >= 0 && b < len) smark[padded((int)b)] = (int32_t)u;
     }
+    __syncthreads();
+    int32_t agg = -1;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int32_t mk = smark[padded(tid * kItems + k)];
+      agg = agg > mk ? agg : mk;
+    }
+    // entries before the tile's first marker belong to the row before r_lo
+    int32_t cur = block_exclusive_max(agg, wave_tot);
+    cur = cur > r_lo - 1 ? cur : r_lo - 1;
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int i = tid * kItems + k;
+      const int32_t mk = smark[padded(i)];
+      cur = cur > mk ? cur : mk;
+      const int32_t v = sval[padded(i)];
+      if (i < len && cur >= 0 && keep_edge<Order>(cur, v, deg)) mask |= 1u << k;
+    }
+    bits[t * kBlock + tid] = (uint16_t)mask;
+    int32_t kept;
+    (void)block_exclusive_sum((int32_t)popc(mask), wave_tot, &kept);
+    if (tid == 0) tile_cnt[t] = kept;
     __syncthreads();
   }
 }
 
-struct DegLoad {
-  const int64_t* outdeg;
-  int64_t n;
-  __device__ int64_t operator()(int64_t i) const { return i < n ? outdeg[i] : 0; }
+struct TileCountLoad {
+  const int32_t* cnt;
+  const TileInfo* info;
+  __device__ int64_t operator()(int64_t i) const {
+    return (!info->over && i < info->num_tiles) ? cnt[i] : 0;
+  }
 };
-template <typename OffT>
-struct OffStore {
-  OffT* dag_ptr;
-  __device__ void operator()(int64_t i, int64_t p) const { dag_ptr[i] = (OffT)p; }
+struct TileOffStore {
+  int64_t* off;
+  __device__ void operator()(int64_t i, int64_t p) const { off[i] = p; }
 };
 
-__global__ void finalize_kernel(const int64_t* total, int64_t cap, int64_t* m_out) {
+__global__ void finalize_kernel(const int64_t* total, const TileInfo* info, int64_t cap,
+                                int64_t* m_out) {
   const int64_t m = *total;
-  *m_out = m > cap ? -(int64_t)TC_ERR_CAPACITY : m;
+  *m_out = (info->over || m > cap) ? -(int64_t)TC_ERR_CAPACITY : m;
 }
 
-// Pass 2 (rows up to kLongRow): the same walk as pass 1, writing kept entries in
-// row order.
-template <typename OffT, int Order>
-__global__ __launch_bounds__(kBlock) void fill_rows_kernel(
+// Pass 2: compact each tile's kept entries through LDS, write them contiguously
+// at the tile's offset, and write dag_row_ptr of the rows starting in the tile
+// (the last tile also takes the rows starting at nnz, through index n).
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void write_kernel(
     int64_t n, const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ deg, const OffT* __restrict__ dag_ptr,
-    int32_t* __restrict__ dag_col, const int64_t* __restrict__ m_out) {
+    const int32_t* __restrict__ row_start, const TileInfo* __restrict__ info,
+    const uint16_t* __restrict__ bits, const int64_t* __restrict__ tile_off,
+    const int64_t* __restrict__ m_out, OffT* __restrict__ dag_ptr, int32_t* __restrict__ dag_col) {
+  __shared__ int32_t sval[kPadded];
+  __shared__ int32_t stage[kTile];
+  __shared__ int32_t toff[kBlock];
+  __shared__ uint32_t tmask[kBlock];
+  __shared__ int32_t wave_tot[kWavesPerBlock];
   if (*m_out < 0) return;
-  const int lane = lane_id();
-  const int g = lane / kGroup, gl = lane % kGroup;
-  const uint64_t gmask = 0xFFFFull << (kGroup * g);
-  const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kGroupsPerWave;
-       r0 < n; r0 += waves * kGroupsPerWave) {
-    const int64_t u = r0 + g;
-    int64_t beg = 0, end = 0, out = 0;
-    if (u < n) {
-      beg = row_ptr[u];
-      end = row_ptr[u + 1];
-      out = dag_ptr[u];
-    }
-    const int64_t len64 = end - beg;
-    const int32_t len = len64 > kShortRow ? kShortRow + 1 : (int32_t)len64;
-    const int32_t widest = group_max(len);
-    if (widest <= kShortRow) {
-      const int32_t iters = (widest + kGroup - 1) / kGroup;
-      for (int32_t k = 0; k < iters; ++k) {
-        const int32_t j = k * kGroup + gl;
-        const int32_t v = j < len ? col[beg + j] : 0;
-        const bool kk = j < len && keep_edge<Order>(u, len, v, deg);
-        const uint64_t m = ballot(kk) & gmask;
-        if (kk) dag_col[out + rank_below(m)] = v;
-        out += popc(m);
-      }
-      continue;
-    }
-    for (int r = 0; r < kGroupsPerWave && r0 + r < n; ++r) {
-      const int64_t ur = r0 + r;
-      const int64_t rb = read_lane64(beg, r * kGroup), re = read_lane64(end, r * kGroup);
-      if (re - rb > kLongRow) continue;
-      const int32_t du = (int32_t)(re - rb);
-      int64_t o = read_lane64(out, r * kGroup);
-      for (int64_t e = rb + lane; e - lane < re; e += kWave) {
-        const int32_t v = e < re ? col[e] : 0;
-        const bool kk = e < re && keep_edge<Order>(ur, du, v, deg);
-        const uint64_t m = ballot(kk);
-        if (kk) dag_col[o + rank_below(m)] = v;
-        o += popc(m);
-      }
-    }
+  const int64_t num_tiles = info->num_tiles, nnz = info->nnz;
+  const int tid = threadIdx.x;
+  if (num_tiles == 0) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t u = (int64_t)blockIdx.x * kBlock + tid; u <= n; u += stride) dag_ptr[u] = 0;
+    return;
   }
-}
-
-// Pass 2 (long rows): ordered compaction across the workgroup's four waves.
-template <typename OffT, int Order>
-__global__ __launch_bounds__(kBlock) void fill_long_kernel(const OffT* __restrict__ row_ptr,
-                                                           const int32_t* __restrict__ col,
-                                                           const int32_t* __restrict__ deg,
-                                                           const OffT* __restrict__ dag_ptr,
-                                                           int32_t* __restrict__ dag_col,
-                                                           const int32_t* __restrict__ long_rows,
-                                                           const int32_t* __restrict__ long_count,
-                                                           const int64_t* __restrict__ m_out) {
-  if (*m_out < 0) return;
-  __shared__ uint32_t wave_kept[kWavesPerBlock];
-  const int wave = threadIdx.x / kWave;
-  const int32_t count = *long_count;
-  for (int32_t li = blockIdx.x; li < count; li += gridDim.x) {
-    const int64_t u = long_rows[li];
-    const int64_t beg = row_ptr[u], end = row_ptr[u + 1];
-    const int32_t du = (int32_t)(end - beg);
-    int64_t out = dag_ptr[u];
-    for (int64_t e0 = beg; e0 < end; e0 += kBlock) {
-      const int64_t e = e0 + threadIdx.x;
-      const int32_t v = e < end ? col[e] : 0;
-      const bool k = e < end && keep_edge<Order>(u, du, v, deg);
-      const uint64_t m = ballot(k);
-      if (lane_id() == 0) wave_kept[wave] = popc(m);
-      __syncthreads();
-      uint32_t before = 0, all = 0;
-      for (int w = 0; w < kWavesPerBlock; ++w) {
-        if (w < wave) before += wave_kept[w];
-        all += wave_kept[w];
+  for (int64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
+    const int64_t e0 = t * kTile;
+    const int len = (int)(nnz - e0 < kTile ? nnz - e0 : kTile);
+    const int32_t r_lo = row_start[t];
+    const int64_t r_hi = t + 1 < num_tiles ? (int64_t)row_start[t + 1] : n + 1;
+    const int64_t base = tile_off[t];
+    const uint32_t mask = bits[t * kBlock + tid];
+    load_tile(col, e0, len, sval);
+    int32_t kept;
+    const int32_t before = block_exclusive_sum((int32_t)popc(mask), wave_tot, &kept);
+    toff[tid] = before;
+    tmask[tid] = mask;
+    int32_t p = before;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+      if ((mask >> k) & 1u) stage[p++] = sval[padded(tid * kItems + k)];
+    __syncthreads();
+    for (int j = tid; j < kept; j += kBlock) dag_col[base + j] = stage[j];
+    for (int64_t u = r_lo + tid; u < r_hi; u += kBlock) {
+      const int64_t pos = (int64_t)row_ptr[u] - e0;  // in [0, len]
+      int32_t kb = kept;
+      if (pos >= 0 && pos < len) {
+        const int q = (int)pos >> 4;
+        kb = toff[q] + (int32_t)__popc(tmask[q] & ((1u << (pos & 15)) - 1u));
       }
-      if (k) dag_col[out + before + rank_below(m)] = v;
-      out += all;
-      __syncthreads();
+      dag_ptr[u] = (OffT)(base + kb);
     }
+    __syncthreads();
   }
 }
 
@@ -253,23 +257,37 @@ __global__ void zero_on_error_kernel(OffT* p, int64_t len, const int64_t* m_out)
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
 }
 
+// Tiles the workspace provides for: a symmetric CSR whose DAG fits `cap` edges
+// has nnz <= 2 cap, and a simple graph has nnz <= n (n - 1).
+int64_t tiles_for(int64_t n, int64_t cap) {
+  const int64_t by_cap = (2 * cap + kTile - 1) / kTile;
+  const int64_t by_n = (n * (n - 1) + kTile - 1) / kTile;  // n < 2^31: no overflow
+  return std::min(by_cap, by_n);
+}
+
 struct OrientLayout {
   int32_t* deg;
-  int64_t* outdeg;
-  int32_t* long_rows;
-  int32_t* long_count;
+  int32_t* row_start;
+  TileInfo* info;
+  uint16_t* bits;
+  int32_t* tile_cnt;
+  int64_t* tile_off;
   int64_t* partial;
+  int64_t tiles_max;
   size_t bytes;
 };
 
-OrientLayout carve_orient(void* ws, int64_t n) {
+OrientLayout carve_orient(void* ws, int64_t n, int64_t cap) {
   Carver c(ws);
   OrientLayout L;
+  L.tiles_max = tiles_for(n, cap);
   L.deg = c.take<int32_t>(n);
-  L.outdeg = c.take<int64_t>(n);
-  L.long_rows = c.take<int32_t>(n);
-  L.long_count = c.take<int32_t>(1);
-  L.partial = c.take<int64_t>(scan_partial_len(n + 1));
+  L.row_start = c.take<int32_t>(L.tiles_max + 1);
+  L.info = c.take<TileInfo>(1);
+  L.bits = c.take<uint16_t>(L.tiles_max * kBlock);
+  L.tile_cnt = c.take<int32_t>(L.tiles_max);
+  L.tile_off = c.take<int64_t>(L.tiles_max);
+  L.partial = c.take<int64_t>(scan_partial_len(L.tiles_max));
   L.bytes = c.used();
   return L;
 }
@@ -278,29 +296,19 @@ template <typename OffT, int Order>
 tc_status orient_impl(int64_t n, const OffT* row_ptr, const int32_t* col, OffT* dag_ptr,
                       int32_t* dag_col, int64_t cap, int64_t* m_out, const OrientLayout& L,
                       hipStream_t s) {
-  const int grid_rows = grid_for(n, kWavesPerBlock * kGroupsPerWave, 16384);
-  // at most n / kLongRow rows can be long
-  const int grid_long = (int)std::max<int64_t>(
-      1, std::min<int64_t>(2 * device_cu_count(), (n + kLongRow - 1) / kLongRow));
-  clear_counter_kernel<<<1, 1, 0, s>>>(L.long_count);
-  if (n > 0) {
-    if (Order == TC_ORDER_DEGREE)
-      degree_kernel<OffT><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, row_ptr, L.deg);
-    count_rows_kernel<OffT, Order><<<grid_rows, kBlock, 0, s>>>(n, row_ptr, col, L.deg, L.outdeg,
-                                                                L.long_rows, L.long_count);
-    count_long_kernel<OffT, Order><<<grid_long, kBlock, 0, s>>>(row_ptr, col, L.deg, L.outdeg,
-                                                                L.long_rows, L.long_count);
-  }
-  hipError_t e = scan_exclusive<OpSum>(n + 1, DegLoad{L.outdeg, n}, OffStore<OffT>{dag_ptr},
-                                       L.partial, s);
-  if (e != hipSuccess) return check_hip(e, "orient offset scan");
-  finalize_kernel<<<1, 1, 0, s>>>(L.partial + scan_num_tiles(n + 1), cap, m_out);
-  if (n > 0) {
-    fill_rows_kernel<OffT, Order><<<grid_rows, kBlock, 0, s>>>(n, row_ptr, col, L.deg, dag_ptr,
-                                                               dag_col, m_out);
-    fill_long_kernel<OffT, Order><<<grid_long, kBlock, 0, s>>>(
-        row_ptr, col, L.deg, dag_ptr, dag_col, L.long_rows, L.long_count, m_out);
-  }
+  const int grid_tiles = (int)std::max<int64_t>(
+      1, std::min<int64_t>(L.tiles_max, (int64_t)kTileBlocksPerCu * device_cu_count()));
+  rows_kernel<OffT, Order><<<grid_for(n + 1, 256, 8192), 256, 0, s>>>(n, row_ptr, L.deg,
+                                                                       L.row_start, L.tiles_max,
+                                                                       L.info);
+  flags_kernel<OffT, Order><<<grid_tiles, kBlock, 0, s>>>(n, row_ptr, col, L.deg, L.row_start,
+                                                          L.info, L.bits, L.tile_cnt);
+  hipError_t e = scan_exclusive<OpSum>(L.tiles_max, TileCountLoad{L.tile_cnt, L.info},
+                                       TileOffStore{L.tile_off}, L.partial, s);
+  if (e != hipSuccess) return check_hip(e, "orient tile scan");
+  finalize_kernel<<<1, 1, 0, s>>>(L.partial + scan_num_tiles(L.tiles_max), L.info, cap, m_out);
+  write_kernel<OffT><<<grid_tiles, kBlock, 0, s>>>(n, row_ptr, col, L.row_start, L.info, L.bits,
+                                                   L.tile_off, m_out, dag_ptr, dag_col);
   zero_on_error_kernel<OffT><<<grid_for(n + 1, 256, 4096), 256, 0, s>>>(dag_ptr, n + 1, m_out);
   return check_hip(hipGetLastError(), "tc_orient launch");
 }
@@ -316,15 +324,19 @@ extern "C" tc_status tc_orient(const tc_csr* sym, int32_t order, void* dag_row_p
   const int64_t n = sym->n;
   if (n < 0 || dag_col_capacity < 0) return fail(TC_ERR_INVALID_ARG, "negative size");
   if (n > INT32_MAX) return fail(TC_ERR_UNSUPPORTED, "n=%lld needs ids beyond int32", (long long)n);
+  if (dag_col_capacity > ((int64_t)1 << 40))
+    return fail(TC_ERR_UNSUPPORTED, "dag_col_capacity=%lld is beyond 2^40",
+                (long long)dag_col_capacity);
   if (sym->offset_bytes != 4 && sym->offset_bytes != 8)
     return fail(TC_ERR_INVALID_ARG, "offset_bytes must be 4 or 8, got %d", sym->offset_bytes);
   if (order != TC_ORDER_DEGREE && order != TC_ORDER_ID)
     return fail(TC_ERR_INVALID_ARG, "unknown order %d", order);
   tc_status st;
-  if (workspace_query(ws, ws_bytes, carve_orient(nullptr, n).bytes, &st)) return st;
+  if (workspace_query(ws, ws_bytes, carve_orient(nullptr, n, dag_col_capacity).bytes, &st))
+    return st;
   if (!sym->row_ptr || !dag_row_ptr || !m_out || (dag_col_capacity > 0 && !dag_col))
     return fail(TC_ERR_INVALID_ARG, "null device pointer");
-  const OrientLayout L = carve_orient(ws, n);
+  const OrientLayout L = carve_orient(ws, n, dag_col_capacity);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (sym->offset_bytes == 4) {
     auto rp = static_cast<const int32_t*>(sym->row_ptr);

@@ -45,7 +45,10 @@ class Pipeline:
         self.total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.per_vertex = torch.zeros(max(n, 1), dtype=torch.int64, device=dev)
         self.ws_build = _bytes(_lib.tc_build_csr_workspace(n, num_pairs, offset_bytes), dev)
-        self.ws_orient = _bytes(_lib.tc_orient_workspace(n), dev)
+        self.ws_orient = _bytes(_lib.tc_orient_workspace(n, self.dag_col.numel()), dev)
+        self.triples = None
+        self.ws_list = None
+        self.list_count = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_count = _bytes(max(_lib.tc_count_workspace(n),
                                    _lib.tc_count_per_vertex_workspace(n)), dev)
 
@@ -68,6 +71,26 @@ class Pipeline:
         pv = self.per_vertex[: self.n]
         _lib.tc_count_per_vertex(self.n, self.dag_ptr, self.dag_col, pv, self.total,
                                  self.ws_count, tune=tune, stream=stream)
+
+    def list_triangles(self, capacity: int, stream=None, tune=None) -> None:
+        """Enqueue tc_list_triangles on the current DAG into a (capacity, 3) buffer that is
+        kept across calls (grown when a larger capacity is asked for)."""
+        capacity = int(capacity)
+        if self.triples is None or self.triples.shape[0] < capacity:
+            self.triples = torch.empty((max(capacity, 1), 3), dtype=torch.int32,
+                                       device=self.device)
+        if self.ws_list is None:
+            self.ws_list = _bytes(_lib.tc_list_triangles_workspace(self.n), self.device)
+        _lib.tc_list_triangles(self.n, self.dag_ptr, self.dag_col, self.triples[:capacity],
+                               self.list_count, self.ws_list, tune=tune, stream=stream)
+
+    def listing(self) -> torch.Tensor:
+        """Synchronise and return the rows written by list_triangles (a view)."""
+        torch.cuda.synchronize(self.device)
+        c = int(self.list_count.item())
+        if c < 0:
+            raise TcError(-c, "reported by tc_list_triangles on the device")
+        return self.triples[:c]
 
     def enqueue(self, src, dst, *, per_vertex: bool = False, stream=None) -> None:
         self.build(src, dst, stream)

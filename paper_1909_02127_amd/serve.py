@@ -50,9 +50,11 @@ class Request:
 def footprint_bytes(n: int, num_pairs: int) -> int:
     """Device bytes a request holds while in flight (its share of a batch): the
     pairs (8 B each), the build keys (2 x 16 B per pair), the symmetric and
-    oriented CSR (12 B per pair, 16 B per vertex for int64 offsets), per-vertex
-    counts and scratch (about 24 B per vertex)."""
-    return 8 * num_pairs + 32 * num_pairs + 12 * num_pairs + 16 * (n + 1) + 24 * n + 1024
+    oriented CSR (12 B per pair, 16 B per vertex for int64 offsets), the orientation's
+    per-tile state (under 1 B per pair), per-vertex counts and scratch (about 24 B per
+    vertex)."""
+    return 8 * num_pairs + 32 * num_pairs + 12 * num_pairs + num_pairs + 16 * (n + 1) + 24 * n \
+        + 1024
 
 
 @dataclass
@@ -253,7 +255,8 @@ class DeviceExecutor:
             dag_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
             dag_col = torch.empty(max(p, 1), dtype=torch.int32, device=dev)
             m = torch.empty(1, dtype=torch.int64, device=dev)
-            ws_o = torch.empty(max(L.tc_orient_workspace(n), 1), dtype=torch.uint8, device=dev)
+            ws_o = torch.empty(max(L.tc_orient_workspace(n, dag_col.numel()), 1), dtype=torch.uint8,
+                               device=dev)
             L.tc_orient(n, row_ptr, col, L.TC_ORDER_DEGREE, dag_ptr, dag_col, m, ws_o,
                         stream=stream)
             totals = torch.empty(max(G, 1), dtype=torch.int64, device=dev)

@@ -24,6 +24,7 @@ def declared_constants():
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ["tc_build_csr", "tc_orient", "tc_count", "tc_count_per_vertex",
+                 "tc_count_batched", "tc_list_triangles",
                  "tc_status_string", "tc_last_error", "tc_version"]:
         assert name in fns
 
@@ -53,7 +54,7 @@ def test_host_side_argument_errors_need_no_gpu():
     """Workspace queries and argument validation run on the host only."""
     from paper_1909_02127_amd import _lib
     assert _lib.tc_build_csr_workspace(1024, 8192) > 2 * 2 * 8192 * 8
-    assert _lib.tc_orient_workspace(1024) > 0
+    assert _lib.tc_orient_workspace(1024, 8192) > _lib.tc_orient_workspace(1024, 0) > 0
     assert _lib.tc_count_workspace(1024) > 0
     with pytest.raises(_lib.TcError) as e:
         _lib.tc_build_csr_workspace(-1, 10)
@@ -67,8 +68,15 @@ def test_host_side_argument_errors_need_no_gpu():
     with pytest.raises(_lib.TcError) as e:
         _lib.tc_build_csr_workspace(10, (1 << 30) + 1, offset_bytes=4)
     assert e.value.status == _lib.TC_ERR_UNSUPPORTED
+    assert _lib.tc_list_triangles_workspace(1024) > _lib.tc_list_triangles_workspace(0) > 0
     csr = _lib.tc_csr(10, 4, None, None)
     size = ctypes.c_size_t(0)
+    st = _lib.LIB.tc_list_triangles(ctypes.byref(csr), None, -1, None, None, None,
+                                    ctypes.byref(size), None)
+    assert st == _lib.TC_ERR_INVALID_ARG and "capacity" in _lib.LIB.tc_last_error().decode()
+    st = _lib.LIB.tc_orient(ctypes.byref(csr), 0, None, None, (1 << 40) + 1, None, None,
+                            ctypes.byref(size), None)
+    assert st == _lib.TC_ERR_UNSUPPORTED
     st = _lib.LIB.tc_orient(ctypes.byref(csr), 7, None, None, 0, None, None, ctypes.byref(size), None)
     assert st == _lib.TC_ERR_INVALID_ARG
     assert "order" in _lib.LIB.tc_last_error().decode()
