@@ -594,6 +594,21 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   for (int c = 0; c < kNumClasses - 1; ++c) n_large += st->class_count[c];
   const int32_t n_small = st->class_count[kNumClasses - 1];
   uint64_t hits = 0;
+  // Batched mode: this wave's hits of the graph it is working on, added to the
+  // graph's total when the wave moves to another graph (consecutive sources are
+  // mostly of one graph; one atomic per source would pile up on a few totals).
+  int32_t pend_g = -1;
+  uint64_t pend_h = 0;
+  auto credit = [&](int32_t u, uint64_t h) {
+    if (!args.totals || !h) return;
+    const int32_t g = args.gid[u];
+    if (g != pend_g) {
+      if (pend_h && lane == 0) atomicAdd((unsigned long long*)&args.totals[pend_g], (unsigned long long)pend_h);
+      pend_g = g;
+      pend_h = 0;
+    }
+    if (g >= 0) pend_h += h;
+  };
 
   // A workgroup's first source is static (its id); later ones come from the
   // cursor, offset past that first round, so small launches need few atomics.
@@ -603,10 +618,7 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
     const uint64_t h = process_source<kWavesPerBlock, K, Wide, OffT>(
         u, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, args.list);
     hits += h;
-    if (args.totals && h && lane == 0) {
-      const int32_t g = args.gid[u];
-      if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
-    }
+    credit(u, h);
     if (args.src_cnt && h && lane == 0)
       atomicAdd((unsigned long long*)&args.src_cnt[u], (unsigned long long)h);
     if (threadIdx.x == 0) big.meta[2] = (int32_t)gridDim.x + atomicAdd(&st->large_cursor, 1);
@@ -634,10 +646,7 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
                                                           kSmallMax, args.max_kicks,
                                                           args.force_sorted, args.list);
       hits += h;
-      if (args.totals && h && lane == 0) {
-        const int32_t g = args.gid[u];
-        if (g >= 0) atomicAdd((unsigned long long*)&args.totals[g], (unsigned long long)h);
-      }
+      credit(u, h);
       if (args.src_cnt && h && lane == 0)
         atomicAdd((unsigned long long*)&args.src_cnt[u], (unsigned long long)h);
     }
@@ -649,6 +658,8 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
       first += waves;
     }
   }
+  if (pend_h && lane == 0)
+    atomicAdd((unsigned long long*)&args.totals[pend_g], (unsigned long long)pend_h);
   if (lane == 0 && hits) atomicAdd((unsigned long long*)total, (unsigned long long)hits);
 }
 
