@@ -2,9 +2,9 @@
 //
 // Values come from a Load functor (int64 result for index i) and prefixes go to
 // a Store functor, so callers scan derived quantities (flags, degrees, digit
-// counts) without materialising them.  Tiles of kScanTile elements are walked
-// as kScanItems coalesced rounds of kScanBlock threads.  The grand total lands
-// in partial[num_tiles] for later kernels to read on the device.
+// counts) without materialising them.  A tile of kScanTile elements is four
+// wave-owned runs of kScanItems coalesced 64-wide rounds.  The grand total
+// lands in partial[num_tiles] for later kernels to read on the device.
 #pragma once
 
 #include "tc_device.h"
@@ -39,86 +39,109 @@ __device__ __forceinline__ int64_t wave_inclusive(int64_t x) {
   return x;
 }
 
-// Exclusive scan of one value per thread across the block; *block_total gets the
-// combination of all kScanBlock values.  Contains barriers: all threads must call.
+// Combination of one value per lane across the wave (every lane gets it).
 template <class Op>
-__device__ __forceinline__ int64_t block_exclusive(int64_t x, int64_t* block_total) {
-  __shared__ int64_t wave_tot[kScanBlock / kWave];
-  const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
-  int64_t inc = wave_inclusive<Op>(x);
-  if (lane == kWave - 1) wave_tot[wave] = inc;
-  __syncthreads();
-  int64_t before = Op::identity();
-  int64_t all = Op::identity();
+__device__ __forceinline__ int64_t wave_reduce(int64_t x) {
 #pragma unroll
-  for (int w = 0; w < kScanBlock / kWave; ++w) {
-    if (w < wave) before = Op::apply(before, wave_tot[w]);
-    all = Op::apply(all, wave_tot[w]);
-  }
-  __syncthreads();
-  int64_t exc = __shfl_up(inc, 1, kWave);
-  if (lane == 0) exc = Op::identity();
-  *block_total = all;
-  return Op::apply(before, exc);
+  for (int off = kWave / 2; off > 0; off >>= 1) x = Op::apply(x, __shfl_xor(x, off, kWave));
+  return x;
 }
 
+// Each wave of a tile owns kScanItems consecutive rounds of 64 elements, so a
+// tile needs one workgroup barrier (to combine the four wave totals).
 template <class Op, class Load>
 __global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(int64_t len, Load load,
                                                                   int64_t* partial) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  __shared__ int64_t wave_tot[kScanBlock / kWave];
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)wave * kScanItems * kWave;
   int64_t acc = Op::identity();
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    int64_t i = base + (int64_t)r * kScanBlock + threadIdx.x;
+    const int64_t i = base + (int64_t)r * kWave + lane;
     if (i < len) acc = Op::apply(acc, load(i));
   }
-  int64_t total;
-  (void)block_exclusive<Op>(acc, &total);
-  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+  acc = wave_reduce<Op>(acc);
+  if (lane == 0) wave_tot[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t total = Op::identity();
+    for (int w = 0; w < kScanBlock / kWave; ++w) total = Op::apply(total, wave_tot[w]);
+    partial[blockIdx.x] = total;
+  }
 }
+
+// The tile totals, scanned in place by one workgroup: each round covers 1024
+// threads x kPartialItems consecutive totals (a serial scan per thread, then
+// one scan of the thread sums).  partial[num] receives the grand total.
+constexpr int kPartialItems = 8;
 
 template <class Op>
 __global__ __launch_bounds__(1024) void scan_partials_kernel(int64_t num, int64_t* partial) {
   __shared__ int64_t wave_tot[1024 / kWave];
-  __shared__ int64_t carry_s;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
-  if (threadIdx.x == 0) carry_s = Op::identity();
-  __syncthreads();
-  for (int64_t base = 0; base < num; base += 1024) {
-    int64_t i = base + threadIdx.x;
-    int64_t x = i < num ? partial[i] : Op::identity();
-    int64_t inc = wave_inclusive<Op>(x);
+  int64_t carry = Op::identity();
+  for (int64_t base = 0; base < num; base += 1024 * kPartialItems) {
+    const int64_t first = base + (int64_t)threadIdx.x * kPartialItems;
+    int64_t x[kPartialItems];
+    int64_t mine = Op::identity();
+#pragma unroll
+    for (int k = 0; k < kPartialItems; ++k) {
+      x[k] = first + k < num ? partial[first + k] : Op::identity();
+      mine = Op::apply(mine, x[k]);
+    }
+    const int64_t inc = wave_inclusive<Op>(mine);
     if (lane == kWave - 1) wave_tot[wave] = inc;
     __syncthreads();
-    int64_t before = carry_s, all = carry_s;
+    int64_t before = carry, all = carry;
     for (int w = 0; w < 1024 / kWave; ++w) {
       if (w < wave) before = Op::apply(before, wave_tot[w]);
       all = Op::apply(all, wave_tot[w]);
     }
     int64_t exc = __shfl_up(inc, 1, kWave);
     if (lane == 0) exc = Op::identity();
-    if (i < num) partial[i] = Op::apply(before, exc);
-    __syncthreads();
-    if (threadIdx.x == 0) carry_s = all;
+    int64_t run = Op::apply(before, exc);
+#pragma unroll
+    for (int k = 0; k < kPartialItems; ++k) {
+      if (first + k < num) partial[first + k] = run;
+      run = Op::apply(run, x[k]);
+    }
+    carry = all;
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[num] = carry_s;
+  if (threadIdx.x == 0) partial[num] = carry;
 }
 
 template <class Op, class Load, class Store>
 __global__ __launch_bounds__(kScanBlock) void scan_down_kernel(int64_t len, Load load, Store store,
                                                                 const int64_t* partial) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  int64_t carry = partial[blockIdx.x];
+  __shared__ int64_t wave_tot[kScanBlock / kWave];
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)wave * kScanItems * kWave;
+  int64_t x[kScanItems];
+  int64_t acc = Op::identity();
+#pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    int64_t i = base + (int64_t)r * kScanBlock + threadIdx.x;
-    int64_t x = i < len ? load(i) : Op::identity();
-    int64_t total;
-    int64_t exc = block_exclusive<Op>(x, &total);
+    const int64_t i = base + (int64_t)r * kWave + lane;
+    x[r] = i < len ? load(i) : Op::identity();
+    acc = Op::apply(acc, x[r]);
+  }
+  acc = wave_reduce<Op>(acc);
+  if (lane == 0) wave_tot[wave] = acc;
+  __syncthreads();
+  int64_t carry = partial[blockIdx.x];
+  for (int w = 0; w < wave; ++w) carry = Op::apply(carry, wave_tot[w]);
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t i = base + (int64_t)r * kWave + lane;
+    const int64_t inc = wave_inclusive<Op>(x[r]);
+    int64_t exc = __shfl_up(inc, 1, kWave);
+    if (lane == 0) exc = Op::identity();
     if (i < len) store(i, Op::apply(carry, exc));
-    carry = Op::apply(carry, total);
+    carry = Op::apply(carry, __shfl(inc, kWave - 1, kWave));
   }
 }
 
