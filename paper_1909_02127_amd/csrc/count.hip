@@ -234,38 +234,65 @@ struct Slice {
   int stash_n;
 };
 
-template <bool PV, int Mode, bool Wide>
-__device__ __forceinline__ bool probe(const Table& t, const Slice& sl, int32_t w) {
-  if (Mode == kModeSorted) {
-    int lo = 0, len = sl.keys;
-    while (len > 0) {
-      const int half = len >> 1;
-      if (t.slot[lo + half] < w) {
-        lo += half + 1;
-        len -= half + 1;
-      } else {
-        len = half;
-      }
+// Binary search of the sorted slice (the fallback mode): whether w is a key.
+template <bool PV>
+__device__ __forceinline__ bool probe_sorted(const Table& t, const Slice& sl, int32_t w) {
+  int lo = 0, len = sl.keys;
+  while (len > 0) {
+    const int half = len >> 1;
+    if (t.slot[lo + half] < w) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
     }
-    const bool hit = lo < sl.keys && t.slot[lo] == w;
-    if (PV && hit) atomicAdd(&t.cnt[lo], 1u);
-    return hit;
   }
+  const bool hit = lo < sl.keys && t.slot[lo] == w;
+  if (PV && hit) atomicAdd(&t.cnt[lo], 1u);
+  return hit;
+}
+
+// Whether w is a key, counting the hit on its slot (per-vertex mode).
+template <int Mode, bool Wide>
+__device__ __forceinline__ bool probe_counted(const Table& t, const Slice& sl, int32_t w) {
+  if (Mode == kModeSorted) return probe_sorted<true>(t, sl, w);
   const uint32_t x = hash_input<Wide>(w);
   const uint32_t s1 = hash_a_of(x, sl.shift);
   const uint32_t s2 = (uint32_t)sl.side + hash_b_of(x, sl.shift);
   const int32_t a = t.slot[s1];
   const int32_t b = t.slot[s2];
   bool hit = (a == w) | (b == w);
-  if (PV && hit) atomicAdd(&t.cnt[a == w ? s1 : s2], 1u);
+  if (hit) atomicAdd(&t.cnt[a == w ? s1 : s2], 1u);
   if (Mode == kModeStash) {
     for (int i = 0; i < sl.stash_n; ++i) {
       const bool h = t.stash[i] == w;
-      if (PV && h) atomicAdd(&t.stash_cnt[i], 1u);
+      if (h) atomicAdd(&t.stash_cnt[i], 1u);
       hit |= h;
     }
   }
   return hit;
+}
+
+// The wave's hits as a mask.  Without per-slot counters the two slot compares
+// are balloted directly (no per-lane boolean is materialised).
+template <bool PV, int Mode, bool Wide>
+__device__ __forceinline__ uint64_t probe_ballot(const Table& t, const Slice& sl, int32_t w) {
+  if (PV) return ballot(probe_counted<Mode, Wide>(t, sl, w));
+  if (Mode == kModeSorted) return ballot(probe_sorted<false>(t, sl, w));
+  const uint32_t x = hash_input<Wide>(w);
+  const int32_t a = t.slot[hash_a_of(x, sl.shift)];
+  const int32_t b = t.slot[(uint32_t)sl.side + hash_b_of(x, sl.shift)];
+  uint64_t m = ballot(a == w) | ballot(b == w);
+  if (Mode == kModeStash) {
+    for (int i = 0; i < sl.stash_n; ++i) m |= ballot(t.stash[i] == w);
+  }
+  return m;
+}
+
+// Element i of a list by a 32-bit unsigned byte offset from its (uniform) start,
+// which lets the load take the scalar-base + vector-offset form.
+__device__ __forceinline__ int32_t list_at(const int32_t* __restrict__ lst, uint32_t i) {
+  return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(lst) + i * 4u);
 }
 
 // Listing output of one source u: its rows start at `base`; a group-shared LDS
@@ -315,24 +342,24 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
     for (int k = 0; k < kUnroll; ++k) w[k] = p[k * kWave];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
-      const uint64_t b = ballot(probe<PV, Mode, Wide>(t, sl, w[k]));
+      const uint64_t b = probe_ballot<PV, Mode, Wide>(t, sl, w[k]);
       hv += popc(b);
       if (K == kKindList) emit(lc, b, v, w[k]);
     }
   }
   if (base < len) {
-    const int last = len - 1;
+    const uint32_t last = (uint32_t)(len - 1);
     int32_t w[kUnroll];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
-      const int i = base + k * kWave + lane;
-      const int32_t x = lst[i < last ? i : last];
+      const uint32_t i = (uint32_t)(base + k * kWave + lane);
+      const int32_t x = list_at(lst, i < last ? i : last);
       w[k] = i <= last ? x : kNoKey;
     }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       if (base + k * kWave < len) {
-        const uint64_t b = ballot(probe<PV, Mode, Wide>(t, sl, w[k]));
+        const uint64_t b = probe_ballot<PV, Mode, Wide>(t, sl, w[k]);
         hv += popc(b);
         if (K == kKindList) emit(lc, b, v, w[k]);
       }
@@ -390,10 +417,15 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       if (base + k * kWave < total) {
-        const bool hit = probe<PV, Mode, Wide>(t, sl, w[k]);
-        const uint64_t b = ballot(hit);
+        uint64_t b;
+        if (PV) {
+          const bool hit = probe_counted<Mode, Wide>(t, sl, w[k]);
+          b = ballot(hit);
+          if (hit) atomicAdd(&ws.shits[seg[k]], 1u);
+        } else {
+          b = probe_ballot<PV, Mode, Wide>(t, sl, w[k]);
+        }
         hv += popc(b);
-        if (PV && hit) atomicAdd(&ws.shits[seg[k]], 1u);
         if (K == kKindList) emit(lc, b, mid[k], w[k]);
       }
     }

@@ -14,7 +14,7 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot((int)p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Number of set bits of `mask` at lanes below the calling lane.
 __device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
