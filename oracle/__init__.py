@@ -54,6 +54,8 @@ def _load():
         lib.oracle_count.argtypes = [i64, p, p, p, i32]
         lib.oracle_vertex_triangles.restype = i64
         lib.oracle_vertex_triangles.argtypes = [i64, i64, p, p, i32]
+        lib.oracle_edge_support.restype = i64
+        lib.oracle_edge_support.argtypes = [i64, p, p, p]
         lib.oracle_list.restype = i64
         lib.oracle_list.argtypes = [i64, p, p, p, i64]
         lib.oracle_max_threads.restype = i32
@@ -138,6 +140,17 @@ def list_triangles(dag_ptr: np.ndarray, dag_col: np.ndarray) -> np.ndarray:
     if got != total:
         raise OracleError("oracle_list changed its answer")
     return out[:total].copy()
+
+
+def edge_support(dag_ptr: np.ndarray, dag_col: np.ndarray) -> tuple[int, np.ndarray]:
+    """(T, sup) where sup[e] (uint32, one per oriented edge) counts the triangles on edge e."""
+    lib = _load()
+    dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
+    dag_col = _i32(dag_col)
+    n = dag_ptr.size - 1
+    sup = np.zeros(max(int(dag_ptr[-1]), 1), dtype=np.uint32)
+    total = int(lib.oracle_edge_support(n, _ptr(dag_ptr), _ptr(dag_col), _ptr(sup)))
+    return total, sup[: int(dag_ptr[-1])].copy()
 
 
 def max_threads() -> int:

@@ -30,6 +30,10 @@
  *    matching is every match; Alg. 1 collects the complete matches in M).  Each
  *    triangle is one match under the orientation, written as the triple
  *    (u, v, w) = (u1, u2, u3) of the query path with its non-tree edge.
+ *  - oracle_edge_support: for every edge, the number of matches (triangles)
+ *    that use it, i.e. how many times it appears as a query edge among the
+ *    matches of M.  Each match u -> v -> w, u -> w adds one to each of its
+ *    three edges.
  *
  * Every function is pinned by the CPU test suite against brute force over
  * vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms and invariants.
@@ -264,6 +268,42 @@ int64_t oracle_list(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col, i
             out[3 * found + 1] = (int32_t)v;
             out[3 * found + 2] = a;
           }
+          ++found;
+          ++i;
+          ++j;
+        }
+      }
+    }
+  }
+  return found;
+}
+
+/*
+ * Support of every oriented edge: sup[e] (e an index into dag_col) = number of
+ * triangles containing that edge.  Every triangle found by merging N+(u) and
+ * N+(v) for the edge e = (u, v) adds one to e, to (u, w) and to (v, w), whose
+ * indices are the merge positions.  sup: uint32[dag_ptr[n]], overwritten.
+ * Single-threaded.  Returns T.
+ */
+int64_t oracle_edge_support(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col,
+                            uint32_t* sup) {
+  memset(sup, 0, sizeof(uint32_t) * (size_t)dag_ptr[n]);
+  int64_t found = 0;
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
+      int64_t v = dag_col[e];
+      int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];
+      int64_t j = dag_ptr[v], jend = dag_ptr[v + 1];
+      while (i < iend && j < jend) {
+        int32_t a = dag_col[i], b = dag_col[j];
+        if (a < b) {
+          ++i;
+        } else if (b < a) {
+          ++j;
+        } else {
+          sup[e] += 1;  /* (u, v) */
+          sup[i] += 1;  /* (u, w) */
+          sup[j] += 1;  /* (v, w) */
           ++found;
           ++i;
           ++j;

@@ -285,3 +285,79 @@ def test_list_counts_agree_with_trace(seed):
     assert len(lst) == tt
     np.testing.assert_array_equal(np.bincount(lst.ravel(), minlength=n), tper)
     _check_listing_shape(dp, dc, lst)
+
+
+# -- per-edge support -----------------------------------------------------------------------
+
+
+def _support(n, s, d, order=oracle.ORDER_DEGREE):
+    rp, col = oracle.clean(n, s, d)
+    dp, dc = oracle.orient(rp, col, order)
+    T, sup = oracle.edge_support(dp, dc)
+    return dp, dc, T, sup
+
+
+def _support_by_definition(n, s, d, dp, dc):
+    """Support of each oriented edge {a, b}: common neighbours of a and b in the edge set."""
+    nb = [set() for _ in range(n)]
+    for a, b in pins.edge_set(s, d):
+        nb[a].add(b)
+        nb[b].add(a)
+    return np.array([len(nb[u] & nb[int(v)]) for u in range(n) for v in dc[dp[u]:dp[u + 1]]],
+                    dtype=np.uint32)
+
+
+@pytest.mark.parametrize("seed", range(50))
+def test_support_brute_force_random_tiny(seed):
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(1, 30))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.1, 0.3, 0.6, 1.0])), seed)
+    bt, _ = pins.brute_force(n, s, d)
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        dp, dc, T, sup = _support(n, s, d, order)
+        assert T == bt and int(sup.sum()) == 3 * bt
+        np.testing.assert_array_equal(sup, _support_by_definition(n, s, d, dp, dc))
+
+
+def test_support_closed_forms():
+    # K_n: every edge lies in n - 2 triangles
+    for n in (3, 5, 9):
+        _, s, d = pins.complete(n)
+        _, _, T, sup = _support(n, s, d)
+        assert np.all(sup == n - 2) and sup.size == n * (n - 1) // 2
+    # wheel with r >= 4 rim vertices: rim edges in 1 triangle, spokes in 2
+    r = 7
+    n, s, d = pins.wheel(r)
+    dp, dc, T, sup = _support(n, s, d)
+    for u in range(n):
+        for k, v in enumerate(dc[dp[u]:dp[u + 1]]):
+            assert sup[dp[u] + k] == (2 if 0 in (u, int(v)) else 1)
+    # friendship F_k: every edge in exactly one triangle; triangle-free graphs: all zero
+    n, s, d = pins.friendship(5)
+    assert np.all(_support(n, s, d)[3] == 1)
+    for n, s, d in (pins.cycle(8), pins.petersen(), pins.complete_bipartite(3, 4)):
+        assert not _support(n, s, d)[3].any()
+
+
+@pytest.mark.parametrize("fx", goldens.all_fixtures(), ids=lambda f: f.name)
+def test_support_golden_fixtures(fx):
+    """Support of each fixture edge = fixture triangles (hand-derived) containing both ends."""
+    dp, dc, T, sup = _support(fx.n, fx.src, fx.dst)
+    assert T == fx.triangles
+    for u in range(fx.n):
+        for k, v in enumerate(dc[dp[u]:dp[u + 1]]):
+            want = sum(1 for t in fx.triangle_sets if u in t and int(v) in t)
+            assert sup[dp[u] + k] == want
+
+
+def test_support_config1_against_matrix_product():
+    """G(1024, 8192): support of edge {a, b} = (A^2)[a, b], the common-neighbour count."""
+    s, d, n = graphgen.erdos_renyi(1024, 8192, 1)
+    a = np.zeros((n, n))
+    a[s.numpy(), d.numpy()] = 1
+    a[d.numpy(), s.numpy()] = 1
+    np.fill_diagonal(a, 0)
+    a2 = a @ a
+    dp, dc, T, sup = _support(n, s.numpy(), d.numpy())
+    rows = np.repeat(np.arange(n), np.diff(dp))
+    np.testing.assert_array_equal(sup, a2[rows, dc].astype(np.uint32))
