@@ -21,6 +21,8 @@
  *                        union, in one launch sequence.
  *   tc_list_triangles    the match set M itself: every triangle as one row
  *                        (u, v, w) of the oriented graph.
+ *   tc_edge_support      for every edge, the number of matches (triangles)
+ *                        that use it.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -232,6 +234,29 @@ tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, const int64_t*
 tc_status tc_list_triangles(const tc_csr* dag, int32_t* triples, int64_t capacity,
                             int64_t* count_out, const tc_tune* tune, void* ws, size_t* ws_bytes,
                             void* stream);
+
+/*
+ * tc_edge_support - per-edge support: for every oriented edge e, the number of
+ * triangles (matches of the triangle query, Sec. II-A and Alg. 1) that contain
+ * it.  A match u -> v -> w closed by (u, w) uses the three edges (u, v), (v, w)
+ * and (u, w); each gets one.  Summed over the edges this is 3T.
+ *
+ *   dag       oriented CSR (as written by tc_orient)
+ *   support   device uint32[capacity] (written): support[e] for e in [0, m),
+ *             aligned with dag->col (entry e is the edge (u, dag->col[e]))
+ *   capacity  entries available in support; m = dag row_ptr[n] are needed
+ *   m_out     device int64[1] (written): m, or -TC_ERR_CAPACITY when m >
+ *             capacity (then support is not written)
+ *   total     device uint64[1] (written) or NULL: T
+ *   tune      launch parameters or NULL (as for tc_count)
+ *   ws, ws_bytes  workspace; O(n) bytes.
+ * One launch of the count enumeration: each hit adds one to (v, w) with a
+ * global atomic; the hits of each (u, v) list and of each slot w of the source's
+ * LDS table are added once per source.
+ */
+tc_status tc_edge_support(const tc_csr* dag, uint32_t* support, int64_t capacity, int64_t* m_out,
+                          uint64_t* total, const tc_tune* tune, void* ws, size_t* ws_bytes,
+                          void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* tc_status_string(tc_status status);

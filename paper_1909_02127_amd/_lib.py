@@ -79,6 +79,8 @@ def _load() -> ctypes.CDLL:
     lib.tc_count_per_vertex.argtypes = [csr, p, p, tune, p, sz, p]
     lib.tc_count_batched.restype = i32
     lib.tc_count_batched.argtypes = [csr, i64, p, p, p, p, tune, p, sz, p]
+    lib.tc_edge_support.restype = i32
+    lib.tc_edge_support.argtypes = [csr, p, i64, p, p, tune, p, sz, p]
     lib.tc_list_triangles.restype = i32
     lib.tc_list_triangles.argtypes = [csr, p, i64, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
@@ -210,6 +212,23 @@ def tc_count_batched(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_batched, ws, ctypes.byref(csr), g, _ptr(vtx_off), _ptr(totals),
              _ptr(per_vertex), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_edge_support_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_edge_support, ctypes.byref(csr), None, 0, None, None, None)
+
+
+def tc_edge_support(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                    support: torch.Tensor, m_out: torch.Tensor, ws: torch.Tensor, *,
+                    total: torch.Tensor | None = None, tune=None, stream=None) -> None:
+    """support (int32 or uint32 storage, capacity entries) receives the triangles on each
+    oriented edge; m_out (int64[1]) receives m or -TC_ERR_CAPACITY."""
+    if support.element_size() != 4 or m_out.dtype != torch.int64 or m_out.numel() != 1:
+        raise ValueError("support must hold 4-byte counts and m_out must be int64[1]")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_edge_support, ws, ctypes.byref(csr), _ptr(support), support.numel(),
+             _ptr(m_out), _ptr(total), _tune_ref(tune), stream=stream)
 
 
 def tc_list_triangles_workspace(n: int) -> int:

@@ -61,6 +61,11 @@ constexpr int kNumClasses = 8;  // 0..6: workgroup classes by size (largest firs
 constexpr int kKindTotal = 0;      // the total (and optionally per-graph / per-source sums)
 constexpr int kKindPerVertex = 1;  // plus t(v) for every vertex
 constexpr int kKindList = 2;       // every triangle as a (u, v, w) row
+constexpr int kKindSupport = 3;    // triangles on every oriented edge
+// Kinds that count hits per LDS slot (the (u, w) pairs of a source).
+__host__ __device__ constexpr bool counted(int kind) {
+  return kind == kKindPerVertex || kind == kKindSupport;
+}
 
 // Probe modes, fixed per table slice after it is built.
 constexpr int kModeCuckoo = 0;  // every key sits in one of its two cuckoo slots
@@ -298,12 +303,16 @@ __device__ __forceinline__ int32_t list_at(const int32_t* __restrict__ lst, uint
 // Listing output of one source u: its rows start at `base`; a group-shared LDS
 // cursor hands out row slots as hits arrive (rows of one source are
 // contiguous, in no particular order).
+// Support mode reuses it for the edge counters: sup[e] for e an index into the
+// column array, and ubeg = the first edge of u.
 struct ListCtx {
   int32_t* out;     // int32[3 * cap]
   int64_t base;
   int64_t cap;
   int32_t* cursor;  // LDS
   int32_t u;
+  uint32_t* sup;
+  int64_t ubeg;
 };
 
 // Writes the wedges u -> v -> w of the lanes set in `hits` as rows (u, v, w).
@@ -330,8 +339,8 @@ __device__ __forceinline__ void emit(const ListCtx& c, uint64_t hits, int32_t v,
 template <int K, int Mode, bool Wide>
 __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, int len,
                                               const Table& t, const Slice& sl, int32_t v,
-                                              const ListCtx& lc) {
-  constexpr bool PV = K == kKindPerVertex;
+                                              const ListCtx& lc, int64_t jb) {
+  constexpr bool CNT = counted(K);
   const int lane = lane_id();
   uint32_t hv = 0;
   int base = 0;
@@ -342,9 +351,11 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
     for (int k = 0; k < kUnroll; ++k) w[k] = p[k * kWave];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
-      const uint64_t b = probe_ballot<PV, Mode, Wide>(t, sl, w[k]);
+      const uint64_t b = probe_ballot<CNT, Mode, Wide>(t, sl, w[k]);
       hv += popc(b);
       if (K == kKindList) emit(lc, b, v, w[k]);
+      if (K == kKindSupport && ((b >> lane) & 1u))
+        atomicAdd(&lc.sup[jb + base + k * kWave + lane], 1u);  // the edge (v, w)
     }
   }
   if (base < len) {
@@ -359,9 +370,11 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       if (base + k * kWave < len) {
-        const uint64_t b = probe_ballot<PV, Mode, Wide>(t, sl, w[k]);
+        const uint64_t b = probe_ballot<CNT, Mode, Wide>(t, sl, w[k]);
         hv += popc(b);
         if (K == kKindList) emit(lc, b, v, w[k]);
+        if (K == kKindSupport && ((b >> lane) & 1u))
+          atomicAdd(&lc.sup[jb + base + k * kWave + lane], 1u);  // the edge (v, w)
       }
     }
   }
@@ -379,13 +392,15 @@ template <int K, int Mode, bool Wide, typename OffT>
 __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
                                                const int32_t* __restrict__ col, const Table& t,
                                                const Slice& sl, const WaveScratch& ws,
-                                               uint64_t* __restrict__ tv, const ListCtx& lc) {
+                                               uint64_t* __restrict__ tv, const ListCtx& lc,
+                                               int64_t uv_edge) {
   constexpr bool PV = K == kKindPerVertex;
+  constexpr bool CNT = counted(K);
   const int lane = lane_id();
   const int32_t incl = wave_inclusive_sum32(len);
   const int32_t start = incl - len;
   const int32_t total = read_lane(incl, kWave - 1);
-  if (PV) ws.shits[lane] = 0;
+  if (CNT) ws.shits[lane] = 0;
   int32_t carry = -1;
   uint32_t hv = 0;
   for (int32_t base = 0; base < total; base += kWin * kWave) {
@@ -403,6 +418,7 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
     wave_sync();
     if (marks) ws.mark[start - base] = -1;
     int32_t w[kWin], mid[kWin];
+    int64_t at[kWin];
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       const int32_t pos = base + k * kWave + lane;
@@ -411,6 +427,7 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
       const int32_t off = pos - __shfl(start, sk, kWave);
       const int32_t slen = __shfl(len, sk, kWave);
       const OffT sb = __shfl(vb, sk, kWave);
+      at[k] = (int64_t)sb + off;
       // pos < total implies 0 <= off < slen; the check also keeps every read in bounds
       w[k] = (pos < total && (uint32_t)off < (uint32_t)slen) ? col[sb + off] : kNoKey;
     }
@@ -418,22 +435,24 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
     for (int k = 0; k < kWin; ++k) {
       if (base + k * kWave < total) {
         uint64_t b;
-        if (PV) {
+        if (CNT) {
           const bool hit = probe_counted<Mode, Wide>(t, sl, w[k]);
           b = ballot(hit);
           if (hit) atomicAdd(&ws.shits[seg[k]], 1u);
+          if (K == kKindSupport && hit) atomicAdd(&lc.sup[at[k]], 1u);  // the edge (v, w)
         } else {
-          b = probe_ballot<PV, Mode, Wide>(t, sl, w[k]);
+          b = probe_ballot<false, Mode, Wide>(t, sl, w[k]);
         }
         hv += popc(b);
         if (K == kKindList) emit(lc, b, mid[k], w[k]);
       }
     }
   }
-  if (PV) {
+  if (CNT) {
     wave_sync();
     const uint32_t c = ws.shits[lane];
-    if (c) atomicAdd((unsigned long long*)&tv[v], (unsigned long long)c);
+    if (PV && c) atomicAdd((unsigned long long*)&tv[v], (unsigned long long)c);
+    if (K == kKindSupport && c) atomicAdd(&lc.sup[uv_edge], c);  // the edge (u, v)
   }
   return hv;
 }
@@ -477,27 +496,47 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
         je = read_lane64((int64_t)ve, j);
       }
       const int32_t vj = read_lane(v, j);
-      const uint32_t hv = scan_list<K, Mode, Wide>(col + jb, (int)(je - jb), t, sl, vj, lc);
+      const uint32_t hv = scan_list<K, Mode, Wide>(col + jb, (int)(je - jb), t, sl, vj, lc, jb);
       src_hits += hv;
       if (PV && hv && lane == 0) atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
+      if (K == kKindSupport && hv && lane == 0)  // the edge (u, v)
+        atomicAdd(&lc.sup[lc.ubeg + i0 + (int64_t)Waves * j + gwave], hv);
     }
     if (walk_short) {
       const bool is_short = len > 0 && len < kShortMax;
       src_hits += scan_short<K, Mode, Wide, OffT>(v, vb, is_short ? (int32_t)len : 0, col, t, sl,
-                                                  ws, tv, lc);
+                                                  ws, tv, lc, lc.ubeg + i);
     }
   }
   return src_hits;
 }
 
-// Process one source u with a group of Waves waves sharing table `t`.
-// Returns this wave's hit count (uniform across the wave).
-// Where the listing pass writes: rows of source u start at off[u].
+// Where the listing pass writes (rows of source u start at off[u]), and the
+// edge counters of the support pass.
 struct ListArgs {
   int32_t* out;
   const int64_t* off;
   int64_t cap;
+  uint32_t* sup;
 };
+
+// Count of key w in the slice's table (the per-slot counters).
+template <bool Wide>
+__device__ __forceinline__ uint32_t slot_count(const Table& t, const Slice& sl, int mode,
+                                               int p, int32_t w) {
+  if (mode == kModeSorted) return t.cnt[p];
+  const uint32_t x = hash_input<Wide>(w);
+  const uint32_t s1 = hash_a_of(x, sl.shift);
+  const uint32_t s2 = (uint32_t)sl.side + hash_b_of(x, sl.shift);
+  if (t.slot[s1] == w) return t.cnt[s1];
+  if (t.slot[s2] == w) return t.cnt[s2];
+  for (int i = 0; i < sl.stash_n; ++i)
+    if (t.stash[i] == w) return t.stash_cnt[i];
+  return 0;
+}
+
+// Process one source u with a group of Waves waves sharing table `t`.
+// Returns this wave's hit count (uniform across the wave).
 
 template <int Waves, int K, bool Wide, typename OffT>
 __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
@@ -505,13 +544,14 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
                                    const Table& t, const WaveScratch& ws, int max_keys,
                                    int max_kicks, bool force_sorted, const ListArgs& la) {
   constexpr bool PV = K == kKindPerVertex;
+  constexpr bool CNT = counted(K);
   const int lane = lane_id();
   const int gr = group_rank<Waves>();
   const int64_t beg = row_ptr[u];
   const int64_t d = (int64_t)row_ptr[u + 1] - beg;
   const int32_t* nbrs = col + beg;
   uint64_t wave_hits = 0;
-  ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u};
+  ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u, la.sup, beg};
   if (K == kKindList) {
     lc.base = la.off[u];
     if (gr == 0) t.meta[3] = 0;  // ordered before any hit by the slice's first barrier
@@ -524,7 +564,7 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
     sl.shift = 32 - b;
     for (int s = gr; s < 2 * sl.side; s += Waves * kWave) {
       t.slot[s] = kEmpty;
-      if (PV) t.cnt[s] = 0;
+      if (CNT) t.cnt[s] = 0;
     }
     if (gr < kStash) t.stash_cnt[gr] = 0;
     if (gr < 2) t.meta[gr] = 0;
@@ -563,6 +603,14 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
     else
       src_hits = scan_middles<Waves, K, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
     wave_hits += src_hits;
+    if (K == kKindSupport) {
+      // the edges (u, w): hits counted on w's slot
+      group_sync<Waves>();
+      for (int p = gr; p < sl.keys; p += Waves * kWave) {
+        const uint32_t c = slot_count<Wide>(t, sl, mode, p, nbrs[c0 + p]);
+        if (c) atomicAdd(&la.sup[beg + c0 + p], c);
+      }
+    }
     if (PV) {
       if (src_hits && lane == 0) atomicAdd((unsigned long long*)&tv[u], (unsigned long long)src_hits);
       group_sync<Waves>();
@@ -608,9 +656,9 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
                                                        CountState* __restrict__ st,
                                                        uint64_t* __restrict__ total,
                                                        uint64_t* __restrict__ tv, CountArgs args) {
-  constexpr bool PV = K == kKindPerVertex;
+  constexpr bool PV = counted(K);  // table layout with per-slot counters
   __shared__ __align__(16) char smem[smem_total(PV)];
-  if (K == kKindList && *args.list_status < 0) return;
+  if ((K == kKindList || K == kKindSupport) && *args.list_status < 0) return;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   WaveScratch ws;
@@ -783,7 +831,7 @@ CountArgs base_args(const Tune& tune) {
   args.totals = nullptr;
   args.src_cnt = nullptr;
   args.list_status = nullptr;
-  args.list = ListArgs{nullptr, nullptr, 0};
+  args.list = ListArgs{nullptr, nullptr, 0, nullptr};
   args.force_sorted = tune.force_sorted;
   // Test hook: TC_TEST_MAX_KICKS caps cuckoo evictions so that tests can drive
   // keys into the stash (and past it, into the sorted fallback).
@@ -941,14 +989,72 @@ tc_status list_impl(int64_t n, const OffT* row_ptr, const int32_t* col, int32_t*
     reset_cursors_kernel<<<1, 1, 0, s>>>(L.c.st, tot);
     CountArgs a2 = base_args(tune);
     a2.list_status = count_out;
-    a2.list = ListArgs{out, L.src_off, cap};
+    a2.list = ListArgs{out, L.src_off, cap, nullptr};
     launch_count<kKindList, OffT>(n, row_ptr, col, L.c, tot, nullptr, a2, tune, s);
   }
   return check_hip(hipGetLastError(), "tc_list_triangles launch");
 }
 
+// ---- per-edge support ------------------------------------------------------
+
+// m_out = m = row_ptr[n], or -TC_ERR_CAPACITY when it exceeds cap; sup[0, m) = 0.
+template <typename OffT>
+__global__ void support_init_kernel(const OffT* __restrict__ row_ptr, int64_t n, int64_t cap,
+                                    uint32_t* __restrict__ sup, int64_t* __restrict__ m_out) {
+  const int64_t m = (int64_t)row_ptr[n];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *m_out = m > cap ? -(int64_t)TC_ERR_CAPACITY : m;
+  if (m > cap) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) sup[i] = 0;
+}
+
+// One count launch with the support kind: every hit adds one to its edge (v, w),
+// each (u, v) list adds its hits to (u, v), and each source adds the hits
+// counted on w's slot to (u, w).
+template <typename OffT>
+tc_status support_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint32_t* sup,
+                       int64_t cap, int64_t* m_out, uint64_t* total, const Tune& tune,
+                       const CountLayout& L, hipStream_t s) {
+  uint64_t* tot = total ? total : L.total_scratch;
+  init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
+  support_init_kernel<OffT><<<grid_for(cap, 256, 8192), 256, 0, s>>>(row_ptr, n, cap, sup, m_out);
+  if (n > 0) {
+    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st, tune.small_max);
+    bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
+        n, row_ptr, L.st, L.list, tune.small_max);
+    CountArgs args = base_args(tune);
+    args.list_status = m_out;
+    args.list = ListArgs{nullptr, nullptr, 0, sup};
+    launch_count<kKindSupport, OffT>(n, row_ptr, col, L, tot, nullptr, args, tune, s);
+  }
+  return check_hip(hipGetLastError(), "tc_edge_support launch");
+}
+
 }  // namespace
 }  // namespace tc
+
+extern "C" tc_status tc_edge_support(const tc_csr* dag, uint32_t* support, int64_t capacity,
+                                     int64_t* m_out, uint64_t* total, const tc_tune* tune,
+                                     void* ws, size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  tc_status st = check_dag(dag);
+  if (st != TC_OK) return st;
+  Tune t;
+  if ((st = read_tune(tune, &t)) != TC_OK) return st;
+  if (capacity < 0) return fail(TC_ERR_INVALID_ARG, "negative capacity");
+  if (workspace_query(ws, ws_bytes, carve_count(nullptr, dag->n, false).bytes, &st)) return st;
+  if (!dag->row_ptr || !m_out || (capacity > 0 && !support))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const CountLayout L = carve_count(ws, dag->n, false);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dag->offset_bytes == 4)
+    st = support_impl<int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col, support,
+                               capacity, m_out, total, t, L, s);
+  else
+    st = support_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, support,
+                               capacity, m_out, total, t, L, s);
+  return st == TC_OK ? ok() : st;
+}
 
 extern "C" tc_status tc_list_triangles(const tc_csr* dag, int32_t* triples, int64_t capacity,
                                        int64_t* count_out, const tc_tune* tune, void* ws,

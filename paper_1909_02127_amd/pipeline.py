@@ -48,6 +48,9 @@ class Pipeline:
         self.ws_orient = _bytes(_lib.tc_orient_workspace(n, self.dag_col.numel()), dev)
         self.triples = None
         self.ws_list = None
+        self.support = None
+        self.ws_support = None
+        self.support_m = torch.zeros(1, dtype=torch.int64, device=dev)
         self.list_count = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_count = _bytes(max(_lib.tc_count_workspace(n),
                                    _lib.tc_count_per_vertex_workspace(n)), dev)
@@ -83,6 +86,23 @@ class Pipeline:
             self.ws_list = _bytes(_lib.tc_list_triangles_workspace(self.n), self.device)
         _lib.tc_list_triangles(self.n, self.dag_ptr, self.dag_col, self.triples[:capacity],
                                self.list_count, self.ws_list, tune=tune, stream=stream)
+
+    def edge_support(self, stream=None, tune=None) -> None:
+        """Enqueue tc_edge_support on the current DAG (one uint32 count per DAG edge)."""
+        if self.support is None:
+            self.support = torch.empty(self.dag_col.numel(), dtype=torch.int32, device=self.device)
+            self.ws_support = _bytes(_lib.tc_edge_support_workspace(self.n), self.device)
+        _lib.tc_edge_support(self.n, self.dag_ptr, self.dag_col, self.support, self.support_m,
+                             self.ws_support, total=self.total, tune=tune, stream=stream)
+
+    def supports(self) -> torch.Tensor:
+        """Synchronise and return the per-edge supports written by edge_support (int32 view
+        of the uint32 counts, aligned with dag_col)."""
+        torch.cuda.synchronize(self.device)
+        m = int(self.support_m.item())
+        if m < 0:
+            raise TcError(-m, "reported by tc_edge_support on the device")
+        return self.support[:m]
 
     def listing(self) -> torch.Tensor:
         """Synchronise and return the rows written by list_triangles (a view)."""
