@@ -54,6 +54,8 @@ def _load():
         lib.oracle_count.argtypes = [i64, p, p, p, i32]
         lib.oracle_vertex_triangles.restype = i64
         lib.oracle_vertex_triangles.argtypes = [i64, i64, p, p, i32]
+        lib.oracle_kcore.restype = i64
+        lib.oracle_kcore.argtypes = [i64, p, p, i32, p]
         lib.oracle_edge_support.restype = i64
         lib.oracle_edge_support.argtypes = [i64, p, p, p]
         lib.oracle_list.restype = i64
@@ -140,6 +142,18 @@ def list_triangles(dag_ptr: np.ndarray, dag_col: np.ndarray) -> np.ndarray:
     if got != total:
         raise OracleError("oracle_list changed its answer")
     return out[:total].copy()
+
+
+def kcore(row_ptr: np.ndarray, col: np.ndarray, k: int = 2) -> np.ndarray:
+    """uint8[n]: 1 for the vertices of the k-core of a symmetric CSR."""
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = _i32(col)
+    n = row_ptr.size - 1
+    keep = np.zeros(max(n, 1), dtype=np.uint8)
+    if lib.oracle_kcore(n, _ptr(row_ptr), _ptr(col), int(k), _ptr(keep)) < 0:
+        raise OracleError("oracle_kcore failed")
+    return keep[:n].copy()
 
 
 def edge_support(dag_ptr: np.ndarray, dag_col: np.ndarray) -> tuple[int, np.ndarray]:

@@ -30,6 +30,10 @@
  *    matching is every match; Alg. 1 collects the complete matches in M).  Each
  *    triangle is one match under the orientation, written as the triple
  *    (u, v, w) = (u1, u2, u3) of the query path with its non-tree edge.
+ *  - oracle_kcore: the NE (neighbourhood-encoding) candidate filter of Alg. 1
+ *    and Sec. III-C, read as: a data vertex can stand for a query node of
+ *    degree k only if it keeps at least k neighbours that are candidates too,
+ *    applied until nothing changes (the k-core).  For the triangle k = 2.
  *  - oracle_edge_support: for every edge, the number of matches (triangles)
  *    that use it, i.e. how many times it appears as a query edge among the
  *    matches of M.  Each match u -> v -> w, u -> w adds one to each of its
@@ -312,4 +316,33 @@ int64_t oracle_edge_support(int64_t n, const int64_t* dag_ptr, const int32_t* da
     }
   }
   return found;
+}
+
+/*
+ * k-core membership of a symmetric CSR: keep[v] = 1 iff v belongs to the
+ * largest subgraph in which every vertex has at least k neighbours.  Peels with
+ * a queue: a vertex whose count of surviving neighbours drops below k is removed
+ * and its neighbours' counts drop by one.  Returns the number kept.
+ */
+int64_t oracle_kcore(int64_t n, const int64_t* row_ptr, const int32_t* col, int32_t k,
+                     uint8_t* keep) {
+  int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* queue = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!cnt || !queue) { free(cnt); free(queue); return -1; }
+  int64_t head = 0, tail = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    cnt[v] = row_ptr[v + 1] - row_ptr[v];
+    keep[v] = 1;
+    if (cnt[v] < k) { keep[v] = 0; queue[tail++] = v; }
+  }
+  while (head < tail) {
+    int64_t v = queue[head++];
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      int64_t w = col[e];
+      if (keep[w] && --cnt[w] < k) { keep[w] = 0; queue[tail++] = w; }
+    }
+  }
+  free(cnt);
+  free(queue);
+  return n - tail;
 }

@@ -361,3 +361,53 @@ def test_support_config1_against_matrix_product():
     dp, dc, T, sup = _support(n, s.numpy(), d.numpy())
     rows = np.repeat(np.arange(n), np.diff(dp))
     np.testing.assert_array_equal(sup, a2[rows, dc].astype(np.uint32))
+
+
+# -- the NE filter (k-core) ---------------------------------------------------------------
+
+
+def _kcore_by_definition(n, s, d, k):
+    """Repeatedly drop every vertex with fewer than k remaining neighbours (synchronous rounds)."""
+    nb = [set() for _ in range(n)]
+    for a, b in pins.edge_set(s, d):
+        nb[a].add(b)
+        nb[b].add(a)
+    alive = set(range(n))
+    while True:
+        drop = {v for v in alive if len(nb[v] & alive) < k}
+        if not drop:
+            return np.array([1 if v in alive else 0 for v in range(n)], dtype=np.uint8)
+        alive -= drop
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_kcore_by_definition_random_tiny(seed):
+    rng = np.random.default_rng(6000 + seed)
+    n = int(rng.integers(1, 40))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.03, 0.06, 0.1, 0.2, 0.5])), seed)
+    rp, col = oracle.clean(n, s, d)
+    for k in (1, 2, 3):
+        np.testing.assert_array_equal(oracle.kcore(rp, col, k), _kcore_by_definition(n, s, d, k))
+
+
+def test_kcore_closed_forms_and_count_preservation():
+    def core(n, s, d, k=2):
+        rp, col = oracle.clean(n, np.asarray(s), np.asarray(d))
+        return oracle.kcore(rp, col, k)
+    assert core(*pins.cycle(9)).all()              # 2-regular: all stay
+    assert core(*pins.complete(6)).all()
+    assert not core(*pins.star(7)).any()           # a tree peels away completely
+    assert not core(8, list(range(7)), list(range(1, 8))).any()  # a path
+    assert core(*pins.friendship(4)).all()         # centre degree 8, others degree 2
+    # a triangle with a pendant path 2-3-4-5: only the triangle survives
+    keep = core(6, [0, 1, 2, 2, 3, 4], [1, 2, 0, 3, 4, 5])
+    np.testing.assert_array_equal(keep, [1, 1, 1, 0, 0, 0])
+    # every triangle vertex survives the 2-core, so the count on the core is the count
+    for seed in range(10):
+        n, s, d = pins.random_simple(30, 0.08, seed)
+        keep = core(n, s, d)
+        e = [(a, b) for a, b in zip(s, d) if keep[a] and keep[b]]
+        sub_s = [a for a, _ in e]
+        sub_d = [b for _, b in e]
+        assert oracle.triangles(n, np.array(sub_s, dtype=np.int32), np.array(sub_d, dtype=np.int32)) \
+            == pins.brute_force(n, s, d)[0]
