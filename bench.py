@@ -33,6 +33,9 @@ WORKLOADS = {
     "serve-poisson": dict(kind="serve", pool=256, seed=5, large_scale=22, large_frac=0.02),
     # triangle listing (every triangle as a (u, v, w) row) on the scale-20 graph
     "list-rmat-s20-ef16": dict(kind="list", scale=20, ef=16, seed=20, offset_bytes=4),
+    # the paper's own pipeline (NE filter + materialised two-iteration advance) against the
+    # fused count, in id order and degree order, on the scale-20 graph
+    "ablation-rmat-s20-ef16": dict(kind="ablation", scale=20, ef=16, seed=20, offset_bytes=4),
     # per-edge support (triangles on every edge) on the scale-20 graph
     "support-rmat-s20-ef16": dict(kind="support", scale=20, ef=16, seed=20, offset_bytes=4),
 }
@@ -531,6 +534,74 @@ def support_main(args, spec):
     print(json.dumps(out), flush=True)
 
 
+def ablation_main(args, spec):
+    """Time the fused count and the paper's materialised two-iteration advance (with and
+    without the NE filter) in both orders on one graph; all counts must agree."""
+    import torch
+    import paper_1909_02127_amd as tc
+    from paper_1909_02127_amd import _lib
+
+    dev = torch.device("cuda:0")
+    s, d, n = make_graph(dict(spec, kind="rmat"), dev)
+    ob = spec["offset_bytes"]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = []
+    counts = set()
+    reps = max(1, min(args.steps, 5))
+    for order, name in ((tc.TC_ORDER_DEGREE, "degree"), (tc.TC_ORDER_ID, "id")):
+        pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, order=order, device=dev)
+        pipe.build(s, d)
+        t_orient = timed(pipe.orient, reps)
+        t_fused = timed(pipe.count, reps)
+        res = pipe.result()
+        counts.add(res.total)
+        keep = torch.zeros(n, dtype=torch.uint8, device=dev)
+        nstats = torch.zeros(3, dtype=torch.int64, device=dev)
+        ws_ne = torch.empty(_lib.tc_ne_filter_workspace(n, 64), dtype=torch.uint8, device=dev)
+        t_ne = timed(lambda: _lib.tc_ne_filter(n, pipe.row_ptr, pipe.col, keep, nstats, ws_ne), reps)
+        cap = pipe.dag_col.numel()
+        ws_b = torch.empty(_lib.tc_count_bfs_workspace(n, cap), dtype=torch.uint8, device=dev)
+        bstats = torch.zeros(4, dtype=torch.int64, device=dev)
+        for mask_name, mask in (("none", None), ("ne", keep)):
+            t_bfs = timed(lambda: _lib.tc_count_bfs(n, pipe.dag_ptr, pipe.dag_col, bstats, ws_b,
+                                                    frontier_capacity=cap, keep=mask), reps)
+            st = bstats.cpu().tolist()
+            counts.add(st[2])
+            rows.append({"order": name, "ne_filter": mask_name, "ms_orient": t_orient,
+                         "ms_fused_count": t_fused, "ms_ne_filter": t_ne if mask is not None else 0.0,
+                         "ms_bfs_count": t_bfs, "frontier": st[0], "candidate_wedges": st[1],
+                         "matches": st[2], "status": st[3],
+                         "ne_kept": int(nstats[0].item()), "ne_rounds": int(nstats[1].item())})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        del pipe
+    best_bfs = min(r["ms_bfs_count"] for r in rows)
+    fused = min(r["ms_fused_count"] for r in rows if r["order"] == "degree")
+    out = {
+        "metric": "fused count speed-up over the materialised two-iteration advance",
+        "value": best_bfs / fused, "unit": "x",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": fused,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "offset_bytes": ob,
+                   "parallelism": "single-gpu"},
+        "counts_agree": len(counts) == 1, "triangles": counts.pop() if len(counts) == 1 else None,
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def _with_tune(runner, tune):
     runner.tune = tune
     return runner
@@ -563,6 +634,8 @@ def main():
         return list_main(args, spec)
     if spec["kind"] == "support":
         return support_main(args, spec)
+    if spec["kind"] == "ablation":
+        return ablation_main(args, spec)
     s, d, n = make_graph(spec, dev)
     ob = spec["offset_bytes"]
     pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, order=tc.TC_ORDER_DEGREE, device=dev)

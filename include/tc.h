@@ -23,6 +23,9 @@
  *                        (u, v, w) of the oriented graph.
  *   tc_edge_support      for every edge, the number of matches (triangles)
  *                        that use it.
+ *   tc_ne_filter,        the paper's own pipeline, kept for comparison: the NE
+ *   tc_count_bfs         candidate filter and the two-iteration advance with
+ *                        its partial and complete matches written out.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -257,6 +260,54 @@ tc_status tc_list_triangles(const tc_csr* dag, int32_t* triples, int64_t capacit
 tc_status tc_edge_support(const tc_csr* dag, uint32_t* support, int64_t capacity, int64_t* m_out,
                           uint64_t* total, const tc_tune* tune, void* ws, size_t* ws_bytes,
                           void* stream);
+
+/*
+ * tc_ne_filter - the candidate filter of Alg. 1: a data vertex can stand for a
+ * query node only if its neighbourhood encoding (NE = degree, Sec. III-C)
+ * covers the node's; every node of the triangle query has degree 2.  Iterated:
+ * a vertex is dropped while it keeps fewer than min_degree candidate
+ * neighbours, which converges to the min_degree-core.  Any number of rounds
+ * keeps every triangle (its vertices always keep two candidate neighbours).
+ *
+ *   sym          symmetric CSR (as written by tc_build_csr)
+ *   min_degree   the query node degree (2 for the triangle), >= 0
+ *   max_rounds   rounds launched, in [0, 4096]; a round after one that removed
+ *                nothing does no work
+ *   keep         device uint8[n] (written): 1 for the remaining candidates
+ *   stats_out    device int64[3] (written): candidates kept, rounds that removed
+ *                something, 1 if the last round removed nothing (converged)
+ *   ws, ws_bytes workspace; 4 (max_rounds + 1) bytes.
+ */
+tc_status tc_ne_filter(const tc_csr* sym, int32_t min_degree, int32_t max_rounds, uint8_t* keep,
+                       int64_t* stats_out, void* ws, size_t* ws_bytes, void* stream);
+
+/*
+ * tc_count_bfs - Alg. 1's verification as two BFS iterations with their
+ * results written out (the comparison point for the fused tc_count).
+ * Iteration 1 advances every candidate source u to v in N+(u) and compacts the
+ * partial matches (u, v) that pass the 2-/1-look-ahead of Sec. III-C (d+(u) >=
+ * 2, d+(v) >= 1) and the candidate mask; iteration 2 advances each to every w
+ * in N+(v) that is a candidate and keeps it when the non-tree query edge (u, w)
+ * exists ("Store_none_tree_connection"), i.e. w is in N+(u).
+ *
+ *   dag                oriented CSR (as written by tc_orient, either order)
+ *   keep               device uint8[n] or NULL: candidate vertices
+ *   frontier_capacity  partial matches the workspace holds; m = dag row_ptr[n]
+ *                      always suffices
+ *   matches            device int32[3 * match_capacity] or NULL: complete
+ *                      matches as rows (u, v, w), in no particular order
+ *   match_capacity     rows available in matches
+ *   stats_out          device int64[4] (written): partial matches after
+ *                      iteration 1, candidate wedges of iteration 2, complete
+ *                      matches, status: 0, or TC_ERR_CAPACITY when the frontier
+ *                      did not fit (then only the first entry is valid) or the
+ *                      matches did not fit the rows (then the rows are partial)
+ *   total              device uint64[1] or NULL (written): complete matches
+ *   ws, ws_bytes       workspace; about 16 B per frontier_capacity entry.
+ */
+tc_status tc_count_bfs(const tc_csr* dag, const uint8_t* keep, int64_t frontier_capacity,
+                       int32_t* matches, int64_t match_capacity, int64_t* stats_out,
+                       uint64_t* total, void* ws, size_t* ws_bytes, void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* tc_status_string(tc_status status);

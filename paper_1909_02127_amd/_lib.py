@@ -79,6 +79,10 @@ def _load() -> ctypes.CDLL:
     lib.tc_count_per_vertex.argtypes = [csr, p, p, tune, p, sz, p]
     lib.tc_count_batched.restype = i32
     lib.tc_count_batched.argtypes = [csr, i64, p, p, p, p, tune, p, sz, p]
+    lib.tc_ne_filter.restype = i32
+    lib.tc_ne_filter.argtypes = [csr, i32, i32, p, p, p, sz, p]
+    lib.tc_count_bfs.restype = i32
+    lib.tc_count_bfs.argtypes = [csr, p, i64, p, i64, p, p, p, sz, p]
     lib.tc_edge_support.restype = i32
     lib.tc_edge_support.argtypes = [csr, p, i64, p, p, tune, p, sz, p]
     lib.tc_list_triangles.restype = i32
@@ -212,6 +216,47 @@ def tc_count_batched(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_batched, ws, ctypes.byref(csr), g, _ptr(vtx_off), _ptr(totals),
              _ptr(per_vertex), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_ne_filter_workspace(n: int, max_rounds: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_ne_filter, ctypes.byref(csr), 2, max_rounds, None, None)
+
+
+def tc_ne_filter(n: int, row_ptr: torch.Tensor, col: torch.Tensor, keep: torch.Tensor,
+                 stats: torch.Tensor, ws: torch.Tensor, *, min_degree: int = 2,
+                 max_rounds: int = 64, stream=None) -> None:
+    """keep (uint8[n]) receives the candidates left by max_rounds rounds of the NE filter;
+    stats (int64[3]) = kept, rounds that removed something, converged."""
+    if keep.dtype != torch.uint8 or keep.numel() < n or stats.dtype != torch.int64 \
+            or stats.numel() < 3:
+        raise ValueError("keep must be uint8[n] and stats int64[3]")
+    csr = make_csr(n, row_ptr, col)
+    _ws_call(LIB.tc_ne_filter, ws, ctypes.byref(csr), min_degree, max_rounds, _ptr(keep),
+             _ptr(stats), stream=stream)
+
+
+def tc_count_bfs_workspace(n: int, frontier_capacity: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_count_bfs, ctypes.byref(csr), None, frontier_capacity, None, 0,
+                     None, None)
+
+
+def tc_count_bfs(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor, stats: torch.Tensor,
+                 ws: torch.Tensor, *, frontier_capacity: int, keep: torch.Tensor | None = None,
+                 matches: torch.Tensor | None = None, total: torch.Tensor | None = None,
+                 stream=None) -> None:
+    """The two-iteration advance; stats (int64[4]) = frontier, candidate wedges, matches,
+    status; matches (int32[capacity, 3]) optional."""
+    if stats.dtype != torch.int64 or stats.numel() < 4:
+        raise ValueError("stats must be int64[4]")
+    if matches is not None and (matches.dtype != torch.int32 or matches.dim() != 2
+                                or matches.shape[1] != 3):
+        raise ValueError("matches must be int32 of shape (capacity, 3)")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count_bfs, ws, ctypes.byref(csr), _ptr(keep), frontier_capacity,
+             _ptr(matches), 0 if matches is None else matches.shape[0], _ptr(stats), _ptr(total),
+             stream=stream)
 
 
 def tc_edge_support_workspace(n: int) -> int:

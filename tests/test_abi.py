@@ -24,7 +24,8 @@ def declared_constants():
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ["tc_build_csr", "tc_orient", "tc_count", "tc_count_per_vertex",
-                 "tc_count_batched", "tc_list_triangles", "tc_edge_support",
+                 "tc_count_batched", "tc_list_triangles", "tc_edge_support", "tc_ne_filter",
+                 "tc_count_bfs",
                  "tc_status_string", "tc_last_error", "tc_version"]:
         assert name in fns
 
@@ -70,6 +71,11 @@ def test_host_side_argument_errors_need_no_gpu():
     assert e.value.status == _lib.TC_ERR_UNSUPPORTED
     assert _lib.tc_list_triangles_workspace(1024) > _lib.tc_list_triangles_workspace(0) > 0
     assert _lib.tc_edge_support_workspace(1024) > 0
+    assert _lib.tc_ne_filter_workspace(1024, 64) > 0
+    assert _lib.tc_count_bfs_workspace(1024, 1 << 20) > 16 * (1 << 20)
+    with pytest.raises(_lib.TcError) as e:
+        _lib.tc_ne_filter_workspace(10, 5000)
+    assert e.value.status == _lib.TC_ERR_INVALID_ARG
     csr = _lib.tc_csr(10, 4, None, None)
     size = ctypes.c_size_t(0)
     st = _lib.LIB.tc_list_triangles(ctypes.byref(csr), None, -1, None, None, None,
