@@ -71,6 +71,8 @@ __host__ __device__ constexpr bool counted(int kind) {
 constexpr int kModeCuckoo = 0;  // every key sits in one of its two cuckoo slots
 constexpr int kModeStash = 1;   // plus up to kStash keys in the stash
 constexpr int kModeSorted = 2;  // stash overflowed: binary search the keys, sorted in the slots
+constexpr int kModeGlobal = 3;  // N+(u) too long for a few slices: binary search it in memory
+constexpr int64_t kGlobalMin = 4 * 816;  // d+(u) above which a source takes kModeGlobal
 
 __host__ __device__ constexpr int small_bytes_per_wave(bool pv) {
   return (2 * kSmallSide) * 4 * (pv ? 2 : 1) + kStash * 8 + 16;
@@ -237,6 +239,7 @@ struct Slice {
   int shift;  // 32 - log2(side)
   int keys;   // keys in this slice
   int stash_n;
+  const int32_t* gkeys;  // kModeGlobal: the sorted row N+(u) in memory
 };
 
 // Binary search of the sorted slice (the fallback mode): whether w is a key.
@@ -313,6 +316,7 @@ struct ListCtx {
   int32_t u;
   uint32_t* sup;
   int64_t ubeg;
+  uint64_t* tv;  // per-vertex counts (kModeGlobal adds t(w) per hit)
 };
 
 // Writes the wedges u -> v -> w of the lanes set in `hits` as rows (u, v, w).
@@ -333,6 +337,39 @@ __device__ __forceinline__ void emit(const ListCtx& c, uint64_t hits, int32_t v,
   }
 }
 
+// Position of w in the sorted keys[0, n) in memory, or -1.
+__device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ keys, int32_t n,
+                                               int32_t w) {
+  int32_t lo = 0, len = n;
+  while (len > 0) {
+    const int32_t half = len >> 1;
+    if (keys[lo + half] < w) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo < n && keys[lo] == w ? lo : -1;
+}
+
+// The wave's hits among the wedges u -> v -> w[lane], with the per-hit work of
+// each kind: LDS slot counters, or (kModeGlobal, which has no table) the
+// per-vertex count t(w) and the support of (u, w) directly.
+template <int K, int Mode, bool Wide>
+__device__ __forceinline__ uint64_t probe_mask(const Table& t, const Slice& sl, int32_t w,
+                                               const ListCtx& lc) {
+  if (Mode == kModeGlobal) {
+    const int32_t pos = find_sorted(sl.gkeys, sl.keys, w);
+    if (K == kKindPerVertex && pos >= 0)
+      atomicAdd((unsigned long long*)&lc.tv[w], 1ull);
+    if (K == kKindSupport && pos >= 0) atomicAdd(&lc.sup[lc.ubeg + pos], 1u);
+    return ballot(pos >= 0);
+  }
+  if (counted(K)) return ballot(probe_counted<Mode, Wide>(t, sl, w));
+  return probe_ballot<false, Mode, Wide>(t, sl, w);
+}
+
 // Hits among the `len` ids of one out-neighbour list `lst` (len >= 1).  Four
 // 64-wide loads are issued before any probe so each wave keeps several memory
 // requests in flight; the tail clamps its indices to stay inside the list.
@@ -351,7 +388,7 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
     for (int k = 0; k < kUnroll; ++k) w[k] = p[k * kWave];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
-      const uint64_t b = probe_ballot<CNT, Mode, Wide>(t, sl, w[k]);
+      const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
       hv += popc(b);
       if (K == kKindList) emit(lc, b, v, w[k]);
       if (K == kKindSupport && ((b >> lane) & 1u))
@@ -370,7 +407,7 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       if (base + k * kWave < len) {
-        const uint64_t b = probe_ballot<CNT, Mode, Wide>(t, sl, w[k]);
+        const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
         hv += popc(b);
         if (K == kKindList) emit(lc, b, v, w[k]);
         if (K == kKindSupport && ((b >> lane) & 1u))
@@ -434,15 +471,10 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       if (base + k * kWave < total) {
-        uint64_t b;
-        if (CNT) {
-          const bool hit = probe_counted<Mode, Wide>(t, sl, w[k]);
-          b = ballot(hit);
-          if (hit) atomicAdd(&ws.shits[seg[k]], 1u);
-          if (K == kKindSupport && hit) atomicAdd(&lc.sup[at[k]], 1u);  // the edge (v, w)
-        } else {
-          b = probe_ballot<false, Mode, Wide>(t, sl, w[k]);
-        }
+        const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
+        const bool hit = (b >> lane) & 1u;
+        if (CNT && hit) atomicAdd(&ws.shits[seg[k]], 1u);
+        if (K == kKindSupport && hit) atomicAdd(&lc.sup[at[k]], 1u);  // the edge (v, w)
         hv += popc(b);
         if (K == kKindList) emit(lc, b, mid[k], w[k]);
       }
@@ -551,10 +583,27 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
   const int64_t d = (int64_t)row_ptr[u + 1] - beg;
   const int32_t* nbrs = col + beg;
   uint64_t wave_hits = 0;
-  ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u, la.sup, beg};
+  ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u, la.sup, beg, tv};
   if (K == kKindList) {
     lc.base = la.off[u];
-    if (gr == 0) t.meta[3] = 0;  // ordered before any hit by the slice's first barrier
+    if (gr == 0) t.meta[3] = 0;  // ordered before any hit by the next barrier
+  }
+  if (Waves > 1 && d > kGlobalMin) {
+    // Too many slices: every slice would stream all of the N+(v) again.  Binary
+    // search the sorted row in memory instead (no table, counts added per hit).
+    if (K == kKindList) group_sync<Waves>();
+    Slice sl;
+    sl.keys = (int)d;
+    sl.side = 0;
+    sl.shift = 0;
+    sl.stash_n = 0;
+    sl.gkeys = nbrs;
+    const uint64_t src_hits =
+        scan_middles<Waves, K, kModeGlobal, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
+    if (PV && src_hits && lane == 0)
+      atomicAdd((unsigned long long*)&tv[u], (unsigned long long)src_hits);
+    group_sync<Waves>();
+    return src_hits;
   }
   for (int64_t c0 = 0; c0 < d; c0 += max_keys) {
     Slice sl;
