@@ -37,14 +37,26 @@ int id_bits(int64_t n) {
   return b;
 }
 
-__global__ __launch_bounds__(256) void make_keys_kernel(int64_t n, int64_t num_pairs,
-                                                        const int32_t* __restrict__ src,
-                                                        const int32_t* __restrict__ dst, int cb,
-                                                        uint64_t* __restrict__ keys,
-                                                        int32_t* __restrict__ err) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// One workgroup per radix tile: its kRadixTile / 2 pairs give the tile's keys,
+// whose first-pass digits (key & mask0) are counted into the first pass's tile
+// histogram (digit-major).
+__global__ __launch_bounds__(kRadixBlock) void make_keys_kernel(int64_t n, int64_t num_pairs,
+                                                                const int32_t* __restrict__ src,
+                                                                const int32_t* __restrict__ dst,
+                                                                int cb, uint32_t mask0,
+                                                                uint64_t* __restrict__ keys,
+                                                                uint32_t* __restrict__ hist,
+                                                                int64_t num_tiles,
+                                                                int32_t* __restrict__ err) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
   bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < num_pairs; i += stride) {
+  const int64_t first = (int64_t)blockIdx.x * (kRadixTile / 2);
+#pragma unroll 4
+  for (int r = 0; r < kRadixItems / 2; ++r) {
+    const int64_t i = first + (int64_t)r * kRadixBlock + threadIdx.x;
+    if (i >= num_pairs) break;
     int64_t a = src[i], b = dst[i];
     uint64_t k0 = kSentinel, k1 = kSentinel;
     if (a < 0 || a >= n || b < 0 || b >= n) {
@@ -55,8 +67,12 @@ __global__ __launch_bounds__(256) void make_keys_kernel(int64_t n, int64_t num_p
     }
     keys[2 * i] = k0;
     keys[2 * i + 1] = k1;
+    atomicAdd(&h[(uint32_t)k0 & mask0], 1u);
+    atomicAdd(&h[(uint32_t)k1 & mask0], 1u);
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(err, 1);
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t* __restrict__ keys,
@@ -288,16 +304,19 @@ tc_status build_impl(int64_t n, int64_t num_pairs, const int32_t* src, const int
 
   clear_i32_kernel<<<1, 1, 0, s>>>(L.err);
   if (num_pairs > 0) {
-    make_keys_kernel<<<grid_for(num_pairs, 256, 8192), 256, 0, s>>>(n, num_pairs, src, dst, cb,
-                                                                     L.keys_a, L.err);
+    const uint32_t mask0 = (1u << (key_bits < 8 ? key_bits : 8)) - 1u;
+    make_keys_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(n, num_pairs, src, dst, cb, mask0,
+                                                            L.keys_a, L.hist, tiles, L.err);
   }
   uint64_t* in = L.keys_a;
   uint64_t* out = L.keys_b;
   if (nk > 0) {
     for (int shift = 0; shift < key_bits; shift += 8) {
       const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
-      radix_hist_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(in, nk, shift, (1u << bits) - 1u,
-                                                               L.hist, tiles);
+      // the first pass's tile histograms come from make_keys
+      if (shift > 0)
+        radix_hist_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(in, nk, shift, (1u << bits) - 1u,
+                                                                 L.hist, tiles);
       hipError_t e = scan_exclusive<OpSum>(256 * tiles, HistLoad{L.hist}, HistStore{L.hist},
                                            L.partial_a, s);
       if (e != hipSuccess) return check_hip(e, "radix digit scan");
