@@ -54,6 +54,8 @@ def _load():
         lib.oracle_count.argtypes = [i64, p, p, p, i32]
         lib.oracle_vertex_triangles.restype = i64
         lib.oracle_vertex_triangles.argtypes = [i64, i64, p, p, i32]
+        lib.oracle_count_k4.restype = ctypes.c_uint64
+        lib.oracle_count_k4.argtypes = [i64, p, p]
         lib.oracle_kcore.restype = i64
         lib.oracle_kcore.argtypes = [i64, p, p, i32, p]
         lib.oracle_edge_support.restype = i64
@@ -142,6 +144,24 @@ def list_triangles(dag_ptr: np.ndarray, dag_col: np.ndarray) -> np.ndarray:
     if got != total:
         raise OracleError("oracle_list changed its answer")
     return out[:total].copy()
+
+
+def count_k4(dag_ptr: np.ndarray, dag_col: np.ndarray) -> int:
+    """Number of 4-cliques of an oriented graph (each found once)."""
+    lib = _load()
+    dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
+    dag_col = _i32(dag_col)
+    r = int(lib.oracle_count_k4(dag_ptr.size - 1, _ptr(dag_ptr), _ptr(dag_col)))
+    if r == (1 << 64) - 1:
+        raise OracleError("oracle_count_k4: allocation failed")
+    return r
+
+
+def k4(n: int, src, dst, *, order: int = ORDER_DEGREE) -> int:
+    """4-cliques from raw pairs: clean -> orient -> count."""
+    row_ptr, col = clean(n, src, dst)
+    dag_ptr, dag_col = orient(row_ptr, col, order)
+    return count_k4(dag_ptr, dag_col)
 
 
 def kcore(row_ptr: np.ndarray, col: np.ndarray, k: int = 2) -> np.ndarray:

@@ -50,6 +50,23 @@ def brute_force_sets(n: int, src, dst) -> list[tuple[int, int, int]]:
     return out
 
 
+def brute_force_k4(n: int, src, dst) -> int:
+    """4-cliques by checking every 4-subset of the vertices."""
+    import itertools
+    e = edge_set(src, dst)
+    nb = [set() for _ in range(n)]
+    for a, b in (tuple(x) for x in e):
+        nb[a].add(b)
+        nb[b].add(a)
+    count = 0
+    for a, b in (tuple(sorted(x)) for x in e):
+        common = sorted(w for w in nb[a] & nb[b] if w > b)
+        for c, d in itertools.combinations(common, 2):
+            if d in nb[c]:
+                count += 1
+    return count
+
+
 def trace_cube(n: int, src, dst) -> tuple[int, np.ndarray]:
     """T = trace(A^3)/6 and t = diag(A^3)/2 for the 0/1 symmetric adjacency A."""
     A = np.zeros((n, n), dtype=np.float64)

@@ -411,3 +411,63 @@ def test_kcore_closed_forms_and_count_preservation():
         sub_d = [b for _, b in e]
         assert oracle.triangles(n, np.array(sub_s, dtype=np.int32), np.array(sub_d, dtype=np.int32)) \
             == pins.brute_force(n, s, d)[0]
+
+
+# -- 4-cliques ---------------------------------------------------------------------------------
+
+
+def _k4_subsets(n, s, d):
+    """Reference by enumeration of all 4-subsets (tiny n only)."""
+    import itertools
+    e = pins.edge_set(s, d)
+    return sum(1 for q in itertools.combinations(range(n), 4)
+               if all(frozenset(p) in e for p in itertools.combinations(q, 2)))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_k4_brute_force_random_tiny(seed):
+    rng = np.random.default_rng(8000 + seed)
+    n = int(rng.integers(1, 22))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.2, 0.4, 0.6, 0.8, 1.0])), seed)
+    want = _k4_subsets(n, s, d)
+    assert pins.brute_force_k4(n, s, d) == want
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        assert oracle.k4(n, s, d, order=order) == want
+
+
+def test_k4_closed_forms():
+    from math import comb
+    for n in (3, 4, 5, 8, 13):
+        _, s, d = pins.complete(n)
+        assert oracle.k4(n, s, d) == comb(n, 4)
+    # complete tripartite graphs have no K4; complete 4-partite K_{a,b,c,d} has a*b*c*d
+    n, s, d = pins.complete_tripartite(3, 4, 5)
+    assert oracle.k4(n, s, d) == 0
+    parts = [2, 3, 2, 4]
+    off = np.cumsum([0] + parts)
+    s4, d4 = [], []
+    for p in range(4):
+        for q in range(p + 1, 4):
+            for i in range(off[p], off[p + 1]):
+                for j in range(off[q], off[q + 1]):
+                    s4.append(i)
+                    d4.append(j)
+    assert oracle.k4(int(off[-1]), s4, d4) == 2 * 3 * 2 * 4
+    # wheels: W_3 = K4 has one, larger wheels none; friendship graphs none
+    n, s, d = pins.wheel(3)
+    assert oracle.k4(n, s, d) == 1
+    for r in (4, 5, 9):
+        n, s, d = pins.wheel(r)
+        assert oracle.k4(n, s, d) == 0
+    n, s, d = pins.friendship(5)
+    assert oracle.k4(n, s, d) == 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_k4_small_rmat_against_edge_enumeration(seed):
+    """R-MAT scale 9: against the independent edge-and-common-neighbour enumeration."""
+    s, d, n = graphgen.rmat(9, 8, 300 + seed)
+    want = pins.brute_force_k4(n, s.numpy(), d.numpy())
+    assert want > 0
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        assert oracle.k4(n, s.numpy(), d.numpy(), order=order) == want
