@@ -23,6 +23,7 @@
  *                        (u, v, w) of the oriented graph.
  *   tc_edge_support      for every edge, the number of matches (triangles)
  *                        that use it.
+ *   tc_count_k4          the 4-clique query (the next clique after the triangle).
  *   tc_ne_filter,        the paper's own pipeline, kept for comparison: the NE
  *   tc_count_bfs         candidate filter and the two-iteration advance with
  *                        its partial and complete matches written out.
@@ -308,6 +309,20 @@ tc_status tc_ne_filter(const tc_csr* sym, int32_t min_degree, int32_t max_rounds
 tc_status tc_count_bfs(const tc_csr* dag, const uint8_t* keep, int64_t frontier_capacity,
                        int32_t* matches, int64_t match_capacity, int64_t* stats_out,
                        uint64_t* total, void* ws, size_t* ws_bytes, void* stream);
+
+/*
+ * tc_count_k4 - number of 4-cliques: the matches of the 4-clique query (Sec.
+ * II-A's subgraph matching with Q = K4; one node per BFS iteration of Alg. 1
+ * under the unique mapping order, so each 4-clique is found once, as
+ * u -> v -> w -> x with all six edges present).  Look-ahead (Sec. III-C):
+ * d+(u) >= 3, d+(v) >= 2, d+(w) >= 1.
+ *
+ *   dag      oriented CSR (as written by tc_orient, either order)
+ *   total    device uint64[1] (written)
+ *   ws, ws_bytes  workspace; 256 bytes.
+ */
+tc_status tc_count_k4(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_bytes,
+                      void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* tc_status_string(tc_status status);

@@ -79,6 +79,8 @@ def _load() -> ctypes.CDLL:
     lib.tc_count_per_vertex.argtypes = [csr, p, p, tune, p, sz, p]
     lib.tc_count_batched.restype = i32
     lib.tc_count_batched.argtypes = [csr, i64, p, p, p, p, tune, p, sz, p]
+    lib.tc_count_k4.restype = i32
+    lib.tc_count_k4.argtypes = [csr, p, p, sz, p]
     lib.tc_ne_filter.restype = i32
     lib.tc_ne_filter.argtypes = [csr, i32, i32, p, p, p, sz, p]
     lib.tc_count_bfs.restype = i32
@@ -216,6 +218,20 @@ def tc_count_batched(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_batched, ws, ctypes.byref(csr), g, _ptr(vtx_off), _ptr(totals),
              _ptr(per_vertex), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_count_k4_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_count_k4, ctypes.byref(csr), None)
+
+
+def tc_count_k4(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor, total: torch.Tensor,
+                ws: torch.Tensor, *, stream=None) -> None:
+    """4-cliques of the oriented graph into total (int64[1], read as uint64)."""
+    if total.dtype != torch.int64 or total.numel() != 1:
+        raise ValueError("total must be int64[1]")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count_k4, ws, ctypes.byref(csr), _ptr(total), stream=stream)
 
 
 def tc_ne_filter_workspace(n: int, max_rounds: int) -> int:

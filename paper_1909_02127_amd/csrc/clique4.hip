@@ -1,0 +1,209 @@
+// clique4.hip - tc_count_k4: the 4-clique query, the next clique after the
+// triangle in the paper's subgraph-matching view (Sec. II-A; Alg. 1 matches a
+// query by advancing one query node per iteration under the unique mapping
+// order).  On the oriented graph every 4-clique appears once as u -> v -> w -> x
+// with all six edges present: v in N+(u), w in S = N+(u) & N+(v), x in
+// N+(w) & S.  Look-ahead (Sec. III-C): a source needs d+(u) >= 3, a second node
+// d+(v) >= 2, a third node d+(w) >= 1.
+//
+// A workgroup takes runs of kGrab sources from a global cursor, one source at a
+// time; N+(u) (sorted) sits in LDS when it has at most kLdsKeys ids.  Its four waves take the v round robin.  For each
+// (u, v) a wave streams N+(v), finds each w in N+(u) by binary search, marks
+// w's position in a per-wave bitmap over N+(u) and keeps the positions in a
+// per-wave list; then for each kept w it streams N+(w) and counts the x whose
+// position in N+(u) is marked.  Longer sources keep N+(u) in memory: w and x
+// are then tested by binary search in the sorted rows of u and v, and the
+// kept w go through a bounded list in chunks.
+#include "tc_device.h"
+#include "tc_host.h"
+
+#include <algorithm>
+
+namespace tc {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kLdsKeys = 2048;           // N+(u) ids held in LDS
+constexpr int kMarkWords = kLdsKeys / 32;
+constexpr int kListCap = 1024;           // kept w per chunk in the in-memory path
+constexpr int kGrab = 8;                 // sources per claim from the global cursor
+
+struct K4State {
+  int32_t cursor;
+  int32_t pad[3];
+};
+
+__global__ void k4_init_kernel(K4State* st, uint64_t* total) {
+  st->cursor = 0;
+  *total = 0;
+}
+
+// Position of w in the sorted keys[0, n), or -1 (keys in LDS or memory).
+__device__ __forceinline__ int32_t find_pos(const int32_t* keys, int32_t n, int32_t w) {
+  int32_t lo = 0, len = n;
+  while (len > 0) {
+    const int32_t half = len >> 1;
+    if (keys[lo + half] < w) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo < n && keys[lo] == w ? lo : -1;
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    K4State* __restrict__ st,
+                                                    uint64_t* __restrict__ total) {
+  __shared__ int32_t tkeys[kLdsKeys];
+  __shared__ uint32_t marks[kWavesPerBlock][kMarkWords];
+  __shared__ int32_t list[kWavesPerBlock][kListCap > kLdsKeys ? kListCap : kLdsKeys];
+  __shared__ int32_t next_s;
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  uint32_t* mk = marks[wave];
+  int32_t* lst = list[wave];
+  for (int w = lane; w < kMarkWords; w += kWave) mk[w] = 0;
+  uint64_t found = 0;
+  if (threadIdx.x == 0) next_s = atomicAdd(&st->cursor, 1);
+  __syncthreads();
+  int64_t u0 = (int64_t)next_s * kGrab;
+  __syncthreads();
+  while (u0 < n) {
+    for (int64_t u = u0; u < u0 + kGrab && u < n; ++u) {
+      const int64_t ub = row_ptr[u];
+      const int32_t du = (int32_t)((int64_t)row_ptr[u + 1] - ub);
+      const bool in_lds = du <= kLdsKeys;
+      if (du >= 3) {
+        if (in_lds)
+          for (int i = threadIdx.x; i < du; i += kBlock) tkeys[i] = col[ub + i];
+        __syncthreads();
+        const int32_t* urow = col + ub;
+        for (int32_t iv = wave; iv < du; iv += kWavesPerBlock) {
+          const int32_t v = in_lds ? tkeys[iv] : urow[iv];
+          const int64_t vb = row_ptr[v];
+          const int32_t dv = (int32_t)((int64_t)row_ptr[v + 1] - vb);
+          if (dv < 2) continue;
+          // stream N+(v): keep the w that are also in N+(u)
+          int32_t ns = 0;
+          for (int32_t base = 0; base < dv; base += kWave) {
+            const int32_t j = base + lane;
+            int32_t pos = -1;
+            int32_t w = 0;
+            if (j < dv) {
+              w = col[vb + j];
+              pos = in_lds ? find_pos(tkeys, du, w) : find_pos(urow, du, w);
+            }
+            const uint64_t hit = ballot(pos >= 0);
+            if (pos >= 0) {
+              if (in_lds) {
+                atomicOr(&mk[pos >> 5], 1u << (pos & 31));
+                lst[ns + rank_below(hit)] = pos;
+              } else {
+                lst[ns + rank_below(hit)] = w;
+              }
+            }
+            ns += popc(hit);
+            // the in-memory path flushes a full chunk (the next 64 could overflow it)
+            const bool flush = !in_lds && (ns > kListCap - kWave || base + kWave >= dv);
+            if (!in_lds && !flush) continue;
+            if (!in_lds) {
+              wave_sync();
+              for (int32_t a = 0; a < ns; ++a) {
+                const int32_t ww = lst[a];
+                const int64_t wb = row_ptr[ww];
+                const int32_t dw = (int32_t)((int64_t)row_ptr[ww + 1] - wb);
+                for (int32_t xb = 0; xb < dw; xb += kWave) {
+                  bool ok = false;
+                  if (xb + lane < dw) {
+                    const int32_t x = col[wb + xb + lane];
+                    ok = find_pos(urow, du, x) >= 0 && find_pos(col + vb, dv, x) >= 0;
+                  }
+                  found += popc(ballot(ok));
+                }
+              }
+              wave_sync();
+              ns = 0;
+            }
+          }
+          if (!in_lds || ns < 2) {
+            if (in_lds) {
+              wave_sync();
+              for (int32_t a = lane; a < ns; a += kWave) mk[lst[a] >> 5] = 0;
+              wave_sync();
+            }
+            continue;
+          }
+          wave_sync();
+          // for each kept w: the x in N+(w) whose position in N+(u) is marked
+          for (int32_t a = 0; a < ns; ++a) {
+            const int32_t ww = tkeys[lst[a]];
+            const int64_t wb = row_ptr[ww];
+            const int32_t dw = (int32_t)((int64_t)row_ptr[ww + 1] - wb);
+            for (int32_t xb = 0; xb < dw; xb += kWave) {
+              bool ok = false;
+              if (xb + lane < dw) {
+                const int32_t p = find_pos(tkeys, du, col[wb + xb + lane]);
+                ok = p >= 0 && ((mk[p >> 5] >> (p & 31)) & 1u);
+              }
+              found += popc(ballot(ok));
+            }
+          }
+          wave_sync();
+          for (int32_t a = lane; a < ns; a += kWave) mk[lst[a] >> 5] = 0;
+          wave_sync();
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) next_s = atomicAdd(&st->cursor, 1);
+    __syncthreads();
+    u0 = (int64_t)next_s * kGrab;
+    __syncthreads();
+  }
+  if (lane == 0 && found) atomicAdd((unsigned long long*)total, (unsigned long long)found);
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_count_k4(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_bytes,
+                                 void* stream) {
+  using namespace tc;
+  if (!dag) return fail(TC_ERR_INVALID_ARG, "dag is NULL");
+  const int64_t n = dag->n;
+  if (n < 0) return fail(TC_ERR_INVALID_ARG, "negative n");
+  if (n > INT32_MAX) return fail(TC_ERR_UNSUPPORTED, "n=%lld needs ids beyond int32", (long long)n);
+  if (dag->offset_bytes != 4 && dag->offset_bytes != 8)
+    return fail(TC_ERR_INVALID_ARG, "offset_bytes must be 4 or 8, got %d", dag->offset_bytes);
+  Carver c0(nullptr);
+  (void)c0.take<K4State>(1);
+  tc_status st;
+  if (workspace_query(ws, ws_bytes, c0.used(), &st)) return st;
+  if (!dag->row_ptr || !total) return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  Carver c(ws);
+  K4State* state = c.take<K4State>(1);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k4_init_kernel<<<1, 1, 0, s>>>(state, total);
+  if (n > 0) {
+    int per_cu = 0;
+    if (dag->offset_bytes == 4)
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k4_kernel<int32_t>, kBlock, 0);
+    else
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k4_kernel<int64_t>, kBlock, 0);
+    const int grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * device_cu_count(), n));
+    if (dag->offset_bytes == 4)
+      k4_kernel<int32_t><<<grid, kBlock, 0, s>>>(n, static_cast<const int32_t*>(dag->row_ptr),
+                                                 dag->col, state, total);
+    else
+      k4_kernel<int64_t><<<grid, kBlock, 0, s>>>(n, static_cast<const int64_t*>(dag->row_ptr),
+                                                 dag->col, state, total);
+  }
+  st = check_hip(hipGetLastError(), "tc_count_k4 launch");
+  return st == TC_OK ? ok() : st;
+}

@@ -25,7 +25,7 @@ def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ["tc_build_csr", "tc_orient", "tc_count", "tc_count_per_vertex",
                  "tc_count_batched", "tc_list_triangles", "tc_edge_support", "tc_ne_filter",
-                 "tc_count_bfs",
+                 "tc_count_bfs", "tc_count_k4",
                  "tc_status_string", "tc_last_error", "tc_version"]:
         assert name in fns
 
