@@ -38,7 +38,8 @@ constexpr int kTileBlocksPerCu = 4;     // LDS: about 35 KB per workgroup
 
 // LDS index of tile entry i, padded so that a thread's kItems consecutive
 // entries fall into distinct banks across a wave.
-__device__ __forceinline__ int padded(int i) { return i + (i >> 4); }
+__device__ __forceinline__ int padded(int i) { return i + i / kItems; }
+static_assert(kItems <= 16, "keep bits are stored 16 per thread");
 
 struct TileInfo {
   int64_t nnz;        // row_ptr[n]
@@ -70,10 +71,12 @@ __global__ __launch_bounds__(256) void rows_kernel(int64_t n, const OffT* __rest
   }
 }
 
+// rank(u) < rank(v), with du = deg[u] already at hand (degree order only).
 template <int Order>
-__device__ __forceinline__ bool keep_edge(int32_t u, int32_t v, const int32_t* __restrict__ deg) {
+__device__ __forceinline__ bool keep_edge(int32_t u, int32_t du, int32_t v,
+                                          const int32_t* __restrict__ deg) {
   if (Order == TC_ORDER_ID) return u < v;
-  const int32_t du = deg[u], dv = deg[v];
+  const int32_t dv = deg[v];
   return du < dv || (du == dv && u < v);
 }
 
@@ -162,14 +165,19 @@ __global__ __launch_bounds__(kBlock) void flags_kernel(
     // entries before the tile's first marker belong to the row before r_lo
     int32_t cur = block_exclusive_max(agg, wave_tot);
     cur = cur > r_lo - 1 ? cur : r_lo - 1;
+    // the row's degree is loaded once per row start, not once per entry
+    int32_t du = (Order == TC_ORDER_DEGREE && cur >= 0) ? deg[cur] : 0;
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const int i = tid * kItems + k;
       const int32_t mk = smark[padded(i)];
-      cur = cur > mk ? cur : mk;
+      if (mk > cur) {
+        cur = mk;
+        if (Order == TC_ORDER_DEGREE) du = deg[cur];
+      }
       const int32_t v = sval[padded(i)];
-      if (i < len && cur >= 0 && keep_edge<Order>(cur, v, deg)) mask |= 1u << k;
+      if (i < len && cur >= 0 && keep_edge<Order>(cur, du, v, deg)) mask |= 1u << k;
     }
     bits[t * kBlock + tid] = (uint16_t)mask;
     int32_t kept;
@@ -241,8 +249,8 @@ __global__ __launch_bounds__(kBlock) void write_kernel(
       const int64_t pos = (int64_t)row_ptr[u] - e0;  // in [0, len]
       int32_t kb = kept;
       if (pos >= 0 && pos < len) {
-        const int q = (int)pos >> 4;
-        kb = toff[q] + (int32_t)__popc(tmask[q] & ((1u << (pos & 15)) - 1u));
+        const int q = (int)pos / kItems;
+        kb = toff[q] + (int32_t)__popc(tmask[q] & ((1u << ((int)pos % kItems)) - 1u));
       }
       dag_ptr[u] = (OffT)(base + kb);
     }
