@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the FETCH_SIZE / WRITE_SIZE counter runs under the two dirs as the "
                          "count kernel's traffic record in profiles/ and exit (no GPU use)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="write the rocprofv3 --pmc runs under the dirs (any counters) as a text "
+                         "table of per-dispatch means for the library kernels in profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="with --summarize-*: the command that produced the data (repeatable)")
     return ap.parse_args()
@@ -133,6 +136,41 @@ def summarize_trace(args) -> str:
                      f"{float(r['MinNs']) / 1e3:11.2f} {float(r['MaxNs']) / 1e3:11.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f}  {name}")
     out = os.path.join(ROOT, "profiles", f"count_kernel_{args.workload}_kernel_trace.txt")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
+
+
+def summarize_counters(args) -> str:
+    """profiles/count_kernel_<workload>_counters.txt: per-dispatch means of every collected
+    counter for the library kernels, with the ratios read off them."""
+    import collections
+    vals = collections.defaultdict(list)
+    for directory in args.summarize_counters:
+        for r in _csv_rows(directory, "counter_collection.csv"):
+            name = _short_kernel_name(r["Kernel_Name"])
+            if name.startswith("tc::"):
+                vals[(name, r["Counter_Name"])].append(float(r["Counter_Value"]))
+    kernels = sorted({k for k, _ in vals})
+    lines = [f"# rocprofv3 counters: workload {args.workload}, per-dispatch means, library kernels",
+             "# commands (repository root on the MI355X, after: cd /tmp && export TMPDIR=/tmp):"]
+    lines += [f"#   {c}" for c in args.profile_command]
+    for k in kernels:
+        cs = {c: sum(v) / len(v) for (kk, c), v in vals.items() if kk == k}
+        lines.append(f"{k}  ({len(next(v for (kk, _), v in vals.items() if kk == k))} dispatches)")
+        for c in sorted(cs):
+            lines.append(f"    {c:28s} {cs[c]:20.1f}")
+        if "SQ_LDS_BANK_CONFLICT" in cs and cs.get("SQ_INSTS_LDS"):
+            lines.append(f"    {'bank-conflict cycles / LDS instr':28s} "
+                         f"{cs['SQ_LDS_BANK_CONFLICT'] / cs['SQ_INSTS_LDS']:20.3f}")
+        if "SQ_LEVEL_WAVES" in cs and cs.get("SQ_BUSY_CYCLES"):
+            lines.append(f"    {'waves in flight (mean)':28s} "
+                         f"{cs['SQ_LEVEL_WAVES'] / cs['SQ_BUSY_CYCLES']:20.1f}")
+        if "TCC_HIT_sum" in cs and "TCC_MISS_sum" in cs:
+            tot = cs["TCC_HIT_sum"] + cs["TCC_MISS_sum"]
+            if tot:
+                lines.append(f"    {'L2 hit rate':28s} {cs['TCC_HIT_sum'] / tot:20.3f}")
+    out = os.path.join(ROOT, "profiles", f"count_kernel_{args.workload}_counters.txt")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     return out
@@ -652,11 +690,13 @@ def _with_tune(runner, tune):
 
 def main():
     args = parse()
-    if args.summarize_trace or args.summarize_pmc:
+    if args.summarize_trace or args.summarize_pmc or args.summarize_counters:
         if args.summarize_trace:
             print(summarize_trace(args))
         if args.summarize_pmc:
             print(summarize_pmc(args))
+        if args.summarize_counters:
+            print(summarize_counters(args))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
