@@ -260,32 +260,39 @@ __device__ __forceinline__ bool probe_sorted(const Table& t, const Slice& sl, in
   return hit;
 }
 
-// Whether w is a key, counting the hit on its slot (per-vertex mode).
+// The wave's hits as a mask, counting each hit on its slot (per-slot counter
+// kinds).  The two slot compares are balloted directly and the same compare
+// results select the lanes that add to a counter, so no per-lane boolean is
+// rebuilt from the mask.
 template <int Mode, bool Wide>
-__device__ __forceinline__ bool probe_counted(const Table& t, const Slice& sl, int32_t w) {
-  if (Mode == kModeSorted) return probe_sorted<true>(t, sl, w);
+__device__ __forceinline__ uint64_t probe_counted(const Table& t, const Slice& sl, int32_t w) {
+  if (Mode == kModeSorted) return ballot(probe_sorted<true>(t, sl, w));
+  // byte offsets of the two slots, shared by the key and the counter arrays
   const uint32_t x = hash_input<Wide>(w);
-  const uint32_t s1 = hash_a_of(x, sl.shift);
-  const uint32_t s2 = (uint32_t)sl.side + hash_b_of(x, sl.shift);
-  const int32_t a = t.slot[s1];
-  const int32_t b = t.slot[s2];
-  bool hit = (a == w) | (b == w);
-  if (hit) atomicAdd(&t.cnt[a == w ? s1 : s2], 1u);
+  const uint32_t oa = hash_a_of(x, sl.shift) * 4u;
+  const uint32_t ob = (uint32_t)sl.side * 4u + hash_b_of(x, sl.shift) * 4u;
+  const int32_t a = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(t.slot) + oa);
+  const int32_t b = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(t.slot) + ob);
+  const bool ha = a == w;
+  const bool hb = b == w;
+  uint64_t m = ballot(ha) | ballot(hb);
+  if (ha | hb)
+    atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.cnt) + (ha ? oa : ob)), 1u);
   if (Mode == kModeStash) {
     for (int i = 0; i < sl.stash_n; ++i) {
       const bool h = t.stash[i] == w;
+      m |= ballot(h);
       if (h) atomicAdd(&t.stash_cnt[i], 1u);
-      hit |= h;
     }
   }
-  return hit;
+  return m;
 }
 
 // The wave's hits as a mask.  Without per-slot counters the two slot compares
 // are balloted directly (no per-lane boolean is materialised).
 template <bool PV, int Mode, bool Wide>
 __device__ __forceinline__ uint64_t probe_ballot(const Table& t, const Slice& sl, int32_t w) {
-  if (PV) return ballot(probe_counted<Mode, Wide>(t, sl, w));
+  if (PV) return probe_counted<Mode, Wide>(t, sl, w);
   if (Mode == kModeSorted) return ballot(probe_sorted<false>(t, sl, w));
   const uint32_t x = hash_input<Wide>(w);
   const int32_t a = t.slot[hash_a_of(x, sl.shift)];
@@ -366,7 +373,7 @@ __device__ __forceinline__ uint64_t probe_mask(const Table& t, const Slice& sl, 
     if (K == kKindSupport && pos >= 0) atomicAdd(&lc.sup[lc.ubeg + pos], 1u);
     return ballot(pos >= 0);
   }
-  if (counted(K)) return ballot(probe_counted<Mode, Wide>(t, sl, w));
+  if (counted(K)) return probe_counted<Mode, Wide>(t, sl, w);
   return probe_ballot<false, Mode, Wide>(t, sl, w);
 }
 
