@@ -8,14 +8,16 @@
 //   1. make_keys: each pair {a,b}, a != b, emits the packed keys (a<<cb | b) and
 //      (b<<cb | a), cb = bits of an id; self-loops and bad pairs emit a sentinel
 //      that sorts last; an out-of-range id raises a device error flag.
-//   2. LSD radix sort of the 2*num_pairs keys over their 2*cb significant bits,
-//      8 bits per pass: per-tile digit histograms, one scan over the
-//      digit-major histogram table, and a stable scatter that sorts each tile by
-//      digit in LDS (in-tile ranks from 8 wave ballots per key, each wave on its
-//      own quarter of the tile) and then writes every digit's run to
-//      consecutive addresses.
-//   3. One scan over "first of its run" flags drops duplicates and sentinels,
-//      writes col, and records the first position of every non-empty row.
+//   2. LSD radix sort of the 2*num_pairs keys over their 2*cb significant bits
+//      in ceil(2*cb / 8) passes of at most 8 bits: per-tile digit histograms,
+//      one scan over the digit-major histogram table, and a stable scatter that
+//      sorts each tile by digit in LDS (in-tile ranks from one wave ballot per
+//      digit bit, each wave on its own quarter of the tile) and then writes
+//      every digit's run to consecutive addresses.
+//   3. Dedup: a key is kept when it is no sentinel and differs from the key
+//      before it.  One pass counts the kept keys of every tile (ballots), the
+//      tile counts are scanned, and a second pass writes col at the kept keys'
+//      ranks and records the first position of every non-empty row.
 //   4. A suffix-minimum scan turns the row starts into row_ptr (empty rows take
 //      the next row's start), in int32 or int64 offsets.
 //   5. A finalize step reports 2m, or -status with an all-zero row_ptr.
@@ -29,12 +31,30 @@ namespace {
 constexpr int kRadixBlock = 256;
 constexpr int kRadixItems = 16;
 constexpr int64_t kRadixTile = (int64_t)kRadixBlock * kRadixItems;
+constexpr int kMaxDigitBits = 8;
+constexpr int kMaxDigits = 1 << kMaxDigitBits;
+static_assert(kMaxDigits == kRadixBlock, "one digit per thread in the scatter");
 constexpr uint64_t kSentinel = ~0ull;
 
 int id_bits(int64_t n) {
   int b = 1;
   while (b < 31 && ((int64_t)1 << b) < n) ++b;
   return b;
+}
+
+// The radix passes over key_bits bits: as few as digits of at most
+// kMaxDigitBits allow, with the bits spread evenly (earlier passes take the
+// remainder).
+struct RadixPlan {
+  int passes;
+  int key_bits;
+  int bits_of(int p) const { return key_bits / passes + (p < key_bits % passes ? 1 : 0); }
+  int max_bits() const { return bits_of(0); }
+};
+
+RadixPlan radix_plan(int64_t n) {
+  const int key_bits = 2 * id_bits(n);
+  return RadixPlan{(key_bits + kMaxDigitBits - 1) / kMaxDigitBits, key_bits};
 }
 
 // One workgroup per radix tile: its kRadixTile / 2 pairs give the tile's keys,
@@ -48,15 +68,15 @@ __global__ __launch_bounds__(kRadixBlock) void make_keys_kernel(int64_t n, int64
                                                                 uint32_t* __restrict__ hist,
                                                                 int64_t num_tiles,
                                                                 int32_t* __restrict__ err) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[kMaxDigits];
+  const int digits = (int)mask0 + 1;
+  for (int d = threadIdx.x; d < digits; d += kRadixBlock) h[d] = 0;
   __syncthreads();
   bool bad = false;
   const int64_t first = (int64_t)blockIdx.x * (kRadixTile / 2);
+  const int64_t last = first + kRadixTile / 2 < num_pairs ? first + kRadixTile / 2 : num_pairs;
 #pragma unroll 4
-  for (int r = 0; r < kRadixItems / 2; ++r) {
-    const int64_t i = first + (int64_t)r * kRadixBlock + threadIdx.x;
-    if (i >= num_pairs) break;
+  for (int64_t i = first + threadIdx.x; i < last; i += kRadixBlock) {
     int64_t a = src[i], b = dst[i];
     uint64_t k0 = kSentinel, k1 = kSentinel;
     if (a < 0 || a >= n || b < 0 || b >= n) {
@@ -72,7 +92,8 @@ __global__ __launch_bounds__(kRadixBlock) void make_keys_kernel(int64_t n, int64
   }
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(err, 1);
   __syncthreads();
-  hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < digits; d += kRadixBlock)
+    hist[(int64_t)d * num_tiles + blockIdx.x] = h[d];
 }
 
 __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t* __restrict__ keys,
@@ -80,22 +101,24 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
                                                                  uint32_t mask,
                                                                  uint32_t* __restrict__ hist,
                                                                  int64_t num_tiles) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[kMaxDigits];
+  const int digits = (int)mask + 1;
+  for (int d = threadIdx.x; d < digits; d += kRadixBlock) h[d] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-#pragma unroll 4
-  for (int r = 0; r < kRadixItems; ++r) {
-    int64_t i = base + (int64_t)r * kRadixBlock + threadIdx.x;
-    if (i < nk) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
-  }
+  const int64_t end = base + kRadixTile < nk ? base + kRadixTile : nk;
+#pragma unroll 8
+  for (int64_t i = base + threadIdx.x; i < end; i += kRadixBlock)
+    atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
   __syncthreads();
-  hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < digits; d += kRadixBlock)
+    hist[(int64_t)d * num_tiles + blockIdx.x] = h[d];
 }
 
 // Stable scatter of one tile: keys of equal digit keep their input order.  Each
 // wave ranks its own contiguous quarter of the tile, 64 keys per round (peers of
-// equal digit from 8 ballots, a per-wave running count per digit), so the only
+// equal digit from one ballot per digit bit, a per-wave running count per
+// digit), so the only
 // workgroup barriers are the few between the phases.  The tile is then sorted by
 // digit in LDS and written so that each digit's run lands at consecutive global
 // addresses (coalesced stores).
@@ -115,7 +138,8 @@ __global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
   const uint32_t mask = (1u << bits) - 1u;
   const int64_t tile = (int64_t)blockIdx.x * kRadixTile;
   const int valid_n = (int)(nk - tile < kRadixTile ? nk - tile : kRadixTile);
-  gbase[t] = offsets[(int64_t)t * num_tiles + blockIdx.x];
+  // the histogram table holds rows for the pass's digits only
+  if (t < (1 << bits)) gbase[t] = offsets[(int64_t)t * num_tiles + blockIdx.x];
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
   __syncthreads();
@@ -193,31 +217,93 @@ struct HistStore {
   __device__ void operator()(int64_t i, int64_t p) const { hist[i] = (uint32_t)p; }
 };
 
-struct RunFlag {
-  const uint64_t* keys;
-  __device__ __forceinline__ bool operator()(int64_t i) const {
-    const uint64_t k = keys[i];
-    return k != kSentinel && (i == 0 || keys[i - 1] != k);
+// Dedup over the sorted keys, one wave per kDedupRun consecutive keys: a key is
+// kept when it is no sentinel and differs from the key before it.
+constexpr int kDedupBlock = 256;
+constexpr int kDedupItems = 16;
+constexpr int kDedupRun = kDedupItems * kWave;
+constexpr int64_t kDedupTile = (int64_t)kDedupBlock * kDedupItems;
+
+// Loads the wave's run and returns the kept-key mask of every round.
+__device__ __forceinline__ void dedup_load(const uint64_t* __restrict__ keys, int64_t nk,
+                                           int64_t base, uint64_t (&k)[kDedupItems],
+                                           uint64_t (&keep)[kDedupItems]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < kDedupItems; ++r) {
+    const int64_t i = base + (int64_t)r * kWave + lane;
+    k[r] = i < nk ? keys[i] : kSentinel;
   }
-};
-struct DedupLoad {
-  RunFlag flag;
-  __device__ int64_t operator()(int64_t i) const { return flag(i) ? 1 : 0; }
-};
-struct DedupStore {
-  RunFlag flag;
-  int cb;
-  int32_t* col;
-  int64_t cap;
-  int64_t* start;
-  __device__ void operator()(int64_t i, int64_t pos) const {
-    if (!flag(i)) return;
-    const uint64_t k = flag.keys[i];
-    const uint64_t row = k >> cb;
-    if (pos < cap) col[pos] = (int32_t)(k & ((1ull << cb) - 1ull));
-    if (i == 0 || (flag.keys[i - 1] >> cb) != row) start[row] = pos;
+  // the key before lane 0 of the first round (none for the first key)
+  uint64_t prev = base > 0 && base <= nk ? keys[base - 1] : kSentinel;
+  const bool first_key = base == 0;
+#pragma unroll
+  for (int r = 0; r < kDedupItems; ++r) {
+    uint64_t p = __shfl_up(k[r], 1, kWave);
+    if (lane == 0) p = prev;
+    const bool head = r == 0 && lane == 0 && first_key;
+    keep[r] = ballot(k[r] != kSentinel && (head || p != k[r]));
+    prev = __shfl(k[r], kWave - 1, kWave);
   }
-};
+}
+
+__global__ __launch_bounds__(kDedupBlock) void dedup_count_kernel(const uint64_t* __restrict__ keys,
+                                                                  int64_t nk,
+                                                                  int64_t* __restrict__ partial) {
+  __shared__ uint32_t wave_cnt[kDedupBlock / kWave];
+  const int wave = threadIdx.x / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kDedupTile + (int64_t)wave * kDedupRun;
+  uint64_t k[kDedupItems], keep[kDedupItems];
+  dedup_load(keys, nk, base, k, keep);
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < kDedupItems; ++r) c += popc(keep[r]);
+  if (lane_id() == 0) wave_cnt[wave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kDedupBlock / kWave; ++w) tot += wave_cnt[w];
+    partial[blockIdx.x] = tot;
+  }
+}
+
+// partial[] holds the exclusive scan of the tile counts.  Kept keys go to col at
+// their rank (while it is below cap), and the first kept key of each row gives
+// start[row].
+__global__ __launch_bounds__(kDedupBlock) void dedup_write_kernel(
+    const uint64_t* __restrict__ keys, int64_t nk, int cb, const int64_t* __restrict__ partial,
+    int32_t* __restrict__ col, int64_t cap, int64_t* __restrict__ start) {
+  __shared__ uint32_t wave_cnt[kDedupBlock / kWave];
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kDedupTile + (int64_t)wave * kDedupRun;
+  uint64_t k[kDedupItems], keep[kDedupItems];
+  dedup_load(keys, nk, base, k, keep);
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < kDedupItems; ++r) c += popc(keep[r]);
+  if (lane == 0) wave_cnt[wave] = c;
+  __syncthreads();
+  int64_t pos = partial[blockIdx.x];
+  for (int w = 0; w < wave; ++w) pos += wave_cnt[w];
+  // the row of the key before the wave's run (a kept key whose row differs
+  // from its predecessor's starts that row)
+  uint64_t prev_row = base > 0 && base <= nk ? keys[base - 1] >> cb : ~0ull;
+  const uint64_t id_mask = (1ull << cb) - 1ull;
+#pragma unroll
+  for (int r = 0; r < kDedupItems; ++r) {
+    const uint64_t row = k[r] >> cb;
+    uint64_t p = __shfl_up(row, 1, kWave);
+    if (lane == 0) p = prev_row;
+    if ((keep[r] >> lane) & 1u) {
+      const int64_t at = pos + rank_below(keep[r]);
+      if (at < cap) col[at] = (int32_t)(k[r] & id_mask);
+      if (p != row) start[row] = at;
+    }
+    pos += popc(keep[r]);
+    prev_row = __shfl(row, kWave - 1, kWave);
+  }
+}
 
 __global__ void fill_i64_kernel(int64_t* p, int64_t len, int64_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -278,15 +364,16 @@ struct BuildLayout {
 BuildLayout carve_build(void* ws, int64_t n, int64_t num_pairs) {
   const int64_t nk = 2 * num_pairs;
   const int64_t tiles = (nk + kRadixTile - 1) / kRadixTile;
-  int64_t pa = scan_partial_len(256 * tiles);
+  const int64_t digits = (int64_t)1 << radix_plan(n).max_bits();
+  int64_t pa = scan_partial_len(digits * tiles);
   if (scan_partial_len(n + 1) > pa) pa = scan_partial_len(n + 1);
   Carver c(ws);
   BuildLayout L;
   L.keys_a = c.take<uint64_t>(nk);
   L.keys_b = c.take<uint64_t>(nk);
-  L.hist = c.take<uint32_t>(256 * tiles);
+  L.hist = c.take<uint32_t>(digits * tiles);
   L.partial_a = c.take<int64_t>(pa);
-  L.partial_b = c.take<int64_t>(scan_partial_len(nk));
+  L.partial_b = c.take<int64_t>((nk + kDedupTile - 1) / kDedupTile + 1);
   L.start = c.take<int64_t>(n + 1);
   L.err = c.take<int32_t>(1);
   L.bytes = c.used();
@@ -299,43 +386,49 @@ tc_status build_impl(int64_t n, int64_t num_pairs, const int32_t* src, const int
                      const BuildLayout& L, hipStream_t s) {
   const int64_t nk = 2 * num_pairs;
   const int cb = id_bits(n);
-  const int key_bits = 2 * cb;
+  const RadixPlan plan = radix_plan(n);
   const int64_t tiles = (nk + kRadixTile - 1) / kRadixTile;
 
   clear_i32_kernel<<<1, 1, 0, s>>>(L.err);
   if (num_pairs > 0) {
-    const uint32_t mask0 = (1u << (key_bits < 8 ? key_bits : 8)) - 1u;
+    const uint32_t mask0 = (1u << plan.bits_of(0)) - 1u;
     make_keys_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(n, num_pairs, src, dst, cb, mask0,
                                                             L.keys_a, L.hist, tiles, L.err);
   }
   uint64_t* in = L.keys_a;
   uint64_t* out = L.keys_b;
   if (nk > 0) {
-    for (int shift = 0; shift < key_bits; shift += 8) {
-      const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
+    int shift = 0;
+    for (int pass = 0; pass < plan.passes; ++pass) {
+      const int bits = plan.bits_of(pass);
+      const int64_t digits = (int64_t)1 << bits;
       // the first pass's tile histograms come from make_keys
-      if (shift > 0)
+      if (pass > 0)
         radix_hist_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(in, nk, shift, (1u << bits) - 1u,
                                                                  L.hist, tiles);
-      hipError_t e = scan_exclusive<OpSum>(256 * tiles, HistLoad{L.hist}, HistStore{L.hist},
+      hipError_t e = scan_exclusive<OpSum>(digits * tiles, HistLoad{L.hist}, HistStore{L.hist},
                                            L.partial_a, s);
       if (e != hipSuccess) return check_hip(e, "radix digit scan");
       radix_scatter_kernel<<<(unsigned)tiles, kRadixBlock, 0, s>>>(in, out, nk, shift, bits,
                                                                   L.hist, tiles);
+      shift += bits;
       uint64_t* t = in;
       in = out;
       out = t;
     }
   }
   fill_i64_kernel<<<grid_for(n + 1, 256, 4096), 256, 0, s>>>(L.start, n + 1, INT64_MAX);
-  RunFlag flag{in};
-  hipError_t e = scan_exclusive<OpSum>(nk, DedupLoad{flag}, DedupStore{flag, cb, col, cap, L.start},
-                                       L.partial_b, s);
-  if (e != hipSuccess) return check_hip(e, "dedup scan");
-  const int64_t* dedup_total = L.partial_b + scan_num_tiles(nk);
+  const int64_t dtiles = (nk + kDedupTile - 1) / kDedupTile;
+  if (dtiles > 0)
+    dedup_count_kernel<<<(unsigned)dtiles, kDedupBlock, 0, s>>>(in, nk, L.partial_b);
+  scan_partials_kernel<OpSum><<<1, 1024, 0, s>>>(dtiles, L.partial_b);
+  if (dtiles > 0)
+    dedup_write_kernel<<<(unsigned)dtiles, kDedupBlock, 0, s>>>(in, nk, cb, L.partial_b, col, cap,
+                                                                L.start);
+  const int64_t* dedup_total = L.partial_b + dtiles;
   set_total_kernel<<<1, 1, 0, s>>>(L.start, n, dedup_total);
-  e = scan_exclusive<OpMin>(n + 1, SuffixLoad{L.start, n}, SuffixStore<OffT>{L.start, n, row_ptr},
-                            L.partial_a, s);
+  hipError_t e = scan_exclusive<OpMin>(n + 1, SuffixLoad{L.start, n},
+                                       SuffixStore<OffT>{L.start, n, row_ptr}, L.partial_a, s);
   if (e != hipSuccess) return check_hip(e, "row offset scan");
   finalize_kernel<<<1, 1, 0, s>>>(L.err, dedup_total, cap, nnz_out);
   zero_on_error_kernel<OffT><<<grid_for(n + 1, 256, 4096), 256, 0, s>>>(row_ptr, n + 1, nnz_out);

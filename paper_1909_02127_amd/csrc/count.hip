@@ -384,7 +384,6 @@ template <int K, int Mode, bool Wide>
 __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, int len,
                                               const Table& t, const Slice& sl, int32_t v,
                                               const ListCtx& lc, int64_t jb) {
-  constexpr bool CNT = counted(K);
   const int lane = lane_id();
   uint32_t hv = 0;
   int base = 0;
