@@ -34,7 +34,8 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kItems = 16;              // entries per thread and tile
 constexpr int kTile = kBlock * kItems;  // entries per tile
 constexpr int kPadded = kTile + kTile / kItems;
-constexpr int kTileBlocksPerCu = 4;     // LDS: about 35 KB per workgroup
+constexpr int kTileBlocksPerCu = 4;     // write_kernel LDS: about 35 KB per workgroup
+constexpr int kFlagBlocksPerCu = 6;     // flags_kernel LDS: about 22 KB per workgroup
 
 // LDS index of tile entry i, padded so that a thread's kItems consecutive
 // entries fall into distinct banks across a wave.
@@ -69,15 +70,6 @@ __global__ __launch_bounds__(256) void rows_kernel(int64_t n, const OffT* __rest
       info->over = tiles > tiles_max;
     }
   }
-}
-
-// rank(u) < rank(v), with du = deg[u] already at hand (degree order only).
-template <int Order>
-__device__ __forceinline__ bool keep_edge(int32_t u, int32_t du, int32_t v,
-                                          const int32_t* __restrict__ deg) {
-  if (Order == TC_ORDER_ID) return u < v;
-  const int32_t dv = deg[v];
-  return du < dv || (du == dv && u < v);
 }
 
 // Block-wide exclusive max-scan of one int32 per thread (-1 before the first).
@@ -118,66 +110,110 @@ __device__ __forceinline__ int32_t block_exclusive_sum(int32_t x, int32_t* wave_
   return before + inc - x;
 }
 
-// The tile's entries into LDS with coalesced reads (entry i at padded(i)).
+// The tile's entries into LDS with coalesced reads (entry i at padded(i)).  The
+// reads are clamped to the tile's last entry (len >= 1) rather than guarded, so
+// all of them are in flight at once.
 __device__ __forceinline__ void load_tile(const int32_t* __restrict__ col, int64_t e0, int len,
                                           int32_t* sval) {
+  int32_t v[kItems];
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int i = k * kBlock + (int)threadIdx.x;
-    sval[padded(i)] = i < len ? col[e0 + i] : 0;
+    v[k] = col[e0 + (i < len ? i : len - 1)];
+  }
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int i = k * kBlock + (int)threadIdx.x;
+    sval[padded(i)] = i < len ? v[k] : 0;
   }
 }
 
 // Pass 1: the keep bit of every entry (kItems bits per thread, in entry order)
-// and the kept count of every tile.
+// and the kept count of every tile.  The entries and their degrees are loaded
+// in the coalesced layout (entry k * kBlock + tid in thread tid), all loads in
+// flight together; the row of every entry comes from a max-scan over the row
+// start markers in the blocked layout (entries tid * kItems + k), and the keep
+// test runs back in the coalesced layout with the entry's values at hand.
 template <typename OffT, int Order>
 __global__ __launch_bounds__(kBlock) void flags_kernel(
     int64_t n, const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const int32_t* __restrict__ deg, const int32_t* __restrict__ row_start,
     const TileInfo* __restrict__ info, uint16_t* __restrict__ bits, int32_t* __restrict__ tile_cnt) {
-  __shared__ int32_t sval[kPadded];
-  __shared__ int32_t smark[kPadded];
+  __shared__ int32_t srow[kPadded];            // row start markers, then the row of every entry
+  __shared__ uint32_t skeep[kTile / 4];        // keep flag of every entry, one byte each
   __shared__ int32_t wave_tot[kWavesPerBlock];
   if (info->over) return;
   const int64_t num_tiles = info->num_tiles, nnz = info->nnz;
   const int tid = threadIdx.x;
+  uint8_t* keep8 = reinterpret_cast<uint8_t*>(skeep);
   for (int64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
     const int64_t e0 = t * kTile;
-    const int len = (int)(nnz - e0 < kTile ? nnz - e0 : kTile);
+    const int len = (int)(nnz - e0 < kTile ? nnz - e0 : kTile);  // >= 1
     const int32_t r_lo = row_start[t];
     const int64_t r_hi = t + 1 < num_tiles ? (int64_t)row_start[t + 1] : n;
-    load_tile(col, e0, len, sval);
+    int32_t v[kItems], dv[kItems];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) smark[padded(k * kBlock + tid)] = -1;
+    for (int k = 0; k < kItems; ++k) {
+      const int i = k * kBlock + tid;
+      v[k] = col[e0 + (i < len ? i : len - 1)];
+    }
+    if (Order == TC_ORDER_DEGREE) {
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) dv[k] = deg[v[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) srow[padded(k * kBlock + tid)] = -1;
     __syncthreads();
     // each non-empty row starting in the tile marks its first entry
     for (int64_t u = r_lo + tid; u < r_hi; u += kBlock) {
       const int64_t b = (int64_t)row_ptr[u] - e0;
-      if (row_ptr[u + 1] > row_ptr[u] && b >= 0 && b < len) smark[padded((int)b)] = (int32_t)u;
+      if (row_ptr[u + 1] > row_ptr[u] && b >= 0 && b < len) srow[padded((int)b)] = (int32_t)u;
     }
     __syncthreads();
-    int32_t agg = -1;
+    {
+      int32_t mk[kItems];
+      int32_t agg = -1;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const int32_t mk = smark[padded(tid * kItems + k)];
-      agg = agg > mk ? agg : mk;
+      for (int k = 0; k < kItems; ++k) {
+        mk[k] = srow[padded(tid * kItems + k)];
+        agg = agg > mk[k] ? agg : mk[k];
+      }
+      // entries before the tile's first marker belong to the row before r_lo
+      int32_t cur = block_exclusive_max(agg, wave_tot);
+      cur = cur > r_lo - 1 ? cur : r_lo - 1;
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        cur = cur > mk[k] ? cur : mk[k];
+        srow[padded(tid * kItems + k)] = cur;
+      }
     }
-    // entries before the tile's first marker belong to the row before r_lo
-    int32_t cur = block_exclusive_max(agg, wave_tot);
-    cur = cur > r_lo - 1 ? cur : r_lo - 1;
-    // the row's degree is loaded once per row start, not once per entry
-    int32_t du = (Order == TC_ORDER_DEGREE && cur >= 0) ? deg[cur] : 0;
+    __syncthreads();
+    {
+      // rank(u) < rank(v); the row degrees are all loaded before any is used,
+      // and the test has no short-circuit branches
+      int32_t u[kItems], du[kItems];
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) u[k] = srow[padded(k * kBlock + tid)];
+      if (Order == TC_ORDER_DEGREE) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) du[k] = deg[u[k] > 0 ? u[k] : 0];
+      }
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const int i = k * kBlock + tid;
+        bool keep = u[k] < v[k];
+        if (Order == TC_ORDER_DEGREE) keep = (du[k] < dv[k]) | ((du[k] == dv[k]) & keep);
+        keep8[i] = (uint8_t)((i < len) & (u[k] >= 0) & keep);
+      }
+    }
+    __syncthreads();
+    // the thread's kItems consecutive flags as bits
     uint32_t mask = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const int i = tid * kItems + k;
-      const int32_t mk = smark[padded(i)];
-      if (mk > cur) {
-        cur = mk;
-        if (Order == TC_ORDER_DEGREE) du = deg[cur];
-      }
-      const int32_t v = sval[padded(i)];
-      if (i < len && cur >= 0 && keep_edge<Order>(cur, du, v, deg)) mask |= 1u << k;
+    for (int q = 0; q < kItems / 4; ++q) {
+      const uint32_t w = skeep[tid * (kItems / 4) + q];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) mask |= ((w >> (8 * j)) & 1u) << (4 * q + j);
     }
     bits[t * kBlock + tid] = (uint16_t)mask;
     int32_t kept;
@@ -309,7 +345,9 @@ tc_status orient_impl(int64_t n, const OffT* row_ptr, const int32_t* col, OffT* 
   rows_kernel<OffT, Order><<<grid_for(n + 1, 256, 8192), 256, 0, s>>>(n, row_ptr, L.deg,
                                                                        L.row_start, L.tiles_max,
                                                                        L.info);
-  flags_kernel<OffT, Order><<<grid_tiles, kBlock, 0, s>>>(n, row_ptr, col, L.deg, L.row_start,
+  const int grid_flags = (int)std::max<int64_t>(
+      1, std::min<int64_t>(L.tiles_max, (int64_t)kFlagBlocksPerCu * device_cu_count()));
+  flags_kernel<OffT, Order><<<grid_flags, kBlock, 0, s>>>(n, row_ptr, col, L.deg, L.row_start,
                                                           L.info, L.bits, L.tile_cnt);
   hipError_t e = scan_exclusive<OpSum>(L.tiles_max, TileCountLoad{L.tile_cnt, L.info},
                                        TileOffStore{L.tile_off}, L.partial, s);
