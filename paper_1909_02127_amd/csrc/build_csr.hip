@@ -73,11 +73,24 @@ __global__ __launch_bounds__(kRadixBlock) void make_keys_kernel(int64_t n, int64
   for (int d = threadIdx.x; d < digits; d += kRadixBlock) h[d] = 0;
   __syncthreads();
   bool bad = false;
+  // the tile's pairs, all loads in flight together (clamped to the last pair)
+  constexpr int kPairs = kRadixItems / 2;
   const int64_t first = (int64_t)blockIdx.x * (kRadixTile / 2);
-  const int64_t last = first + kRadixTile / 2 < num_pairs ? first + kRadixTile / 2 : num_pairs;
-#pragma unroll 4
-  for (int64_t i = first + threadIdx.x; i < last; i += kRadixBlock) {
-    int64_t a = src[i], b = dst[i];
+  const int valid = (int)(num_pairs - first < kRadixTile / 2 ? num_pairs - first : kRadixTile / 2);
+  int32_t pa[kPairs], pb[kPairs];
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    const int j = r * kRadixBlock + (int)threadIdx.x;
+    const int64_t i = first + (j < valid ? j : valid - 1);
+    pa[r] = src[i];
+    pb[r] = dst[i];
+  }
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    const int j = r * kRadixBlock + (int)threadIdx.x;
+    if (j >= valid) continue;
+    const int64_t i = first + j;
+    const int64_t a = pa[r], b = pb[r];
     uint64_t k0 = kSentinel, k1 = kSentinel;
     if (a < 0 || a >= n || b < 0 || b >= n) {
       bad = true;
@@ -105,11 +118,19 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
   const int digits = (int)mask + 1;
   for (int d = threadIdx.x; d < digits; d += kRadixBlock) h[d] = 0;
   __syncthreads();
+  // the tile's keys, all loads in flight together (clamped to the last key)
   const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  const int64_t end = base + kRadixTile < nk ? base + kRadixTile : nk;
-#pragma unroll 8
-  for (int64_t i = base + threadIdx.x; i < end; i += kRadixBlock)
-    atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+  const int valid = (int)(nk - base < kRadixTile ? nk - base : kRadixTile);
+  uint64_t k[kRadixItems];
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int j = r * kRadixBlock + (int)threadIdx.x;
+    k[r] = keys[base + (j < valid ? j : valid - 1)];
+  }
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r)
+    if (r * kRadixBlock + (int)threadIdx.x < valid)
+      atomicAdd(&h[(uint32_t)(k[r] >> shift) & mask], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < digits; d += kRadixBlock)
     hist[(int64_t)d * num_tiles + blockIdx.x] = h[d];

@@ -122,16 +122,40 @@ struct CountState {
 
 constexpr int kSmallGrab = 16;  // wave-mode sources per run in the dynamic hand-out
 
+constexpr int kBinItems = 16;
+
+// Out-degree of vertex base + r * 256 + tid for r < kBinItems, all loads in
+// flight together (indices clamped to n - 1, n >= 1); -1 past n.
+template <typename OffT>
+__device__ __forceinline__ void bin_degrees(int64_t n, const OffT* __restrict__ row_ptr,
+                                            int64_t base, int64_t (&d)[kBinItems]) {
+  int64_t lo[kBinItems], hi[kBinItems];
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    const int64_t u = base + r * 256 + threadIdx.x;
+    const int64_t c = u < n ? u : n - 1;
+    lo[r] = row_ptr[c];
+    hi[r] = row_ptr[c + 1];
+  }
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r)
+    d[r] = base + r * 256 + threadIdx.x < n ? hi[r] - lo[r] : -1;
+}
+
+// Sources per class: one workgroup per 256 * kBinItems vertices, one global
+// atomic per class and workgroup.
 template <typename OffT>
 __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* __restrict__ row_ptr,
                                                         CountState* __restrict__ st, int small_max) {
   __shared__ int32_t h[kNumClasses];
   if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
   __syncthreads();
+  int64_t d[kBinItems];
+  bin_degrees(n, row_ptr, (int64_t)blockIdx.x * (256 * kBinItems), d);
   int32_t mine[kNumClasses] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-    const int c = source_class((int64_t)(row_ptr[u + 1] - row_ptr[u]), small_max);
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    const int c = d[r] >= 0 ? source_class(d[r], small_max) : -1;
 #pragma unroll
     for (int k = 0; k < kNumClasses; ++k) mine[k] += (c == k);
   }
@@ -144,8 +168,6 @@ __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* _
   if (threadIdx.x < kNumClasses && h[threadIdx.x]) atomicAdd(&st->class_count[threadIdx.x], h[threadIdx.x]);
 }
 
-constexpr int kBinItems = 16;
-
 template <typename OffT>
 __global__ __launch_bounds__(256) void bin_write_kernel(int64_t n, const OffT* __restrict__ row_ptr,
                                                         CountState* __restrict__ st,
@@ -155,12 +177,13 @@ __global__ __launch_bounds__(256) void bin_write_kernel(int64_t n, const OffT* _
   if (threadIdx.x < kNumClasses) lcnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * (256 * kBinItems);
+  int64_t d[kBinItems];
+  bin_degrees(n, row_ptr, base, d);
   int cls[kBinItems];
   int32_t lr[kBinItems];
 #pragma unroll
   for (int r = 0; r < kBinItems; ++r) {
-    const int64_t u = base + r * 256 + threadIdx.x;
-    cls[r] = u < n ? source_class((int64_t)(row_ptr[u + 1] - row_ptr[u]), small_max) : -1;
+    cls[r] = d[r] >= 0 ? source_class(d[r], small_max) : -1;
     lr[r] = cls[r] >= 0 ? atomicAdd(&lcnt[cls[r]], 1) : 0;
   }
   __syncthreads();
@@ -176,6 +199,15 @@ __global__ __launch_bounds__(256) void bin_write_kernel(int64_t n, const OffT* _
   for (int r = 0; r < kBinItems; ++r) {
     if (cls[r] >= 0) list[gbase[cls[r]] + lr[r]] = (int32_t)(base + r * 256 + threadIdx.x);
   }
+}
+
+// The source lists by class (n >= 1): counts, then the lists.
+template <typename OffT>
+void launch_bins(int64_t n, const OffT* row_ptr, CountState* st, int32_t* list, int small_max,
+                 hipStream_t s) {
+  const unsigned grid = (unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems));
+  bin_count_kernel<OffT><<<grid, 256, 0, s>>>(n, row_ptr, st, small_max);
+  bin_write_kernel<OffT><<<grid, 256, 0, s>>>(n, row_ptr, st, list, small_max);
 }
 
 __global__ void init_state_kernel(CountState* st, uint64_t* total) {
@@ -929,9 +961,7 @@ tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_
     args.totals = totals;
   }
   if (n > 0) {
-    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st, tune.small_max);
-    bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
-        n, row_ptr, L.st, L.list, tune.small_max);
+    launch_bins<OffT>(n, row_ptr, L.st, L.list, tune.small_max, s);
     launch_count<K, OffT>(n, row_ptr, col, L, tot, tv, args, tune, s);
   }
   return check_hip(hipGetLastError(), "tc_count launch");
@@ -1030,9 +1060,7 @@ tc_status list_impl(int64_t n, const OffT* row_ptr, const int32_t* col, int32_t*
   init_state_kernel<<<1, 64, 0, s>>>(L.c.st, tot);
   zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(L.src_cnt, n);
   if (n > 0) {
-    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.c.st, tune.small_max);
-    bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
-        n, row_ptr, L.c.st, L.c.list, tune.small_max);
+    launch_bins<OffT>(n, row_ptr, L.c.st, L.c.list, tune.small_max, s);
     CountArgs a1 = base_args(tune);
     a1.src_cnt = L.src_cnt;
     launch_count<kKindTotal, OffT>(n, row_ptr, col, L.c, tot, nullptr, a1, tune, s);
@@ -1074,9 +1102,7 @@ tc_status support_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint3
   init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
   support_init_kernel<OffT><<<grid_for(cap, 256, 8192), 256, 0, s>>>(row_ptr, n, cap, sup, m_out);
   if (n > 0) {
-    bin_count_kernel<OffT><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, row_ptr, L.st, tune.small_max);
-    bin_write_kernel<OffT><<<(unsigned)((n + 256 * kBinItems - 1) / (256 * kBinItems)), 256, 0, s>>>(
-        n, row_ptr, L.st, L.list, tune.small_max);
+    launch_bins<OffT>(n, row_ptr, L.st, L.list, tune.small_max, s);
     CountArgs args = base_args(tune);
     args.list_status = m_out;
     args.list = ListArgs{nullptr, nullptr, 0, sup};
