@@ -293,12 +293,18 @@ __device__ __forceinline__ bool probe_sorted(const Table& t, const Slice& sl, in
 }
 
 // The wave's hits as a mask, counting each hit on its slot (per-slot counter
-// kinds).  The two slot compares are balloted directly and the same compare
-// results select the lanes that add to a counter, so no per-lane boolean is
-// rebuilt from the mask.
-template <int Mode, bool Wide>
-__device__ __forceinline__ uint64_t probe_counted(const Table& t, const Slice& sl, int32_t w) {
-  if (Mode == kModeSorted) return ballot(probe_sorted<true>(t, sl, w));
+// kinds) and, with Seg, on the caller's per-lane LDS counter `seg` too.  The two
+// slot compares are balloted directly and the same compare results select the
+// lanes that add to the counters, so no per-lane boolean is rebuilt from the
+// mask.
+template <int Mode, bool Wide, bool Seg>
+__device__ __forceinline__ uint64_t probe_counted(const Table& t, const Slice& sl, int32_t w,
+                                                  uint32_t* seg) {
+  if (Mode == kModeSorted) {
+    const bool h = probe_sorted<true>(t, sl, w);
+    if (Seg && h) atomicAdd(seg, 1u);
+    return ballot(h);
+  }
   // byte offsets of the two slots, shared by the key and the counter arrays
   const uint32_t x = hash_input<Wide>(w);
   const uint32_t oa = hash_a_of(x, sl.shift) * 4u;
@@ -308,13 +314,18 @@ __device__ __forceinline__ uint64_t probe_counted(const Table& t, const Slice& s
   const bool ha = a == w;
   const bool hb = b == w;
   uint64_t m = ballot(ha) | ballot(hb);
-  if (ha | hb)
+  if (ha | hb) {
     atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.cnt) + (ha ? oa : ob)), 1u);
+    if (Seg) atomicAdd(seg, 1u);
+  }
   if (Mode == kModeStash) {
     for (int i = 0; i < sl.stash_n; ++i) {
       const bool h = t.stash[i] == w;
       m |= ballot(h);
-      if (h) atomicAdd(&t.stash_cnt[i], 1u);
+      if (h) {
+        atomicAdd(&t.stash_cnt[i], 1u);
+        if (Seg) atomicAdd(seg, 1u);
+      }
     }
   }
   return m;
@@ -324,7 +335,7 @@ __device__ __forceinline__ uint64_t probe_counted(const Table& t, const Slice& s
 // are balloted directly (no per-lane boolean is materialised).
 template <bool PV, int Mode, bool Wide>
 __device__ __forceinline__ uint64_t probe_ballot(const Table& t, const Slice& sl, int32_t w) {
-  if (PV) return probe_counted<Mode, Wide>(t, sl, w);
+  if (PV) return probe_counted<Mode, Wide, false>(t, sl, w, nullptr);
   if (Mode == kModeSorted) return ballot(probe_sorted<false>(t, sl, w));
   const uint32_t x = hash_input<Wide>(w);
   const int32_t a = t.slot[hash_a_of(x, sl.shift)];
@@ -394,18 +405,20 @@ __device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ keys,
 
 // The wave's hits among the wedges u -> v -> w[lane], with the per-hit work of
 // each kind: LDS slot counters, or (kModeGlobal, which has no table) the
-// per-vertex count t(w) and the support of (u, w) directly.
-template <int K, int Mode, bool Wide>
+// per-vertex count t(w) and the support of (u, w) directly.  With Seg (counted
+// kinds only) each hit also adds one to the lane's LDS counter `seg`.
+template <int K, int Mode, bool Wide, bool Seg = false>
 __device__ __forceinline__ uint64_t probe_mask(const Table& t, const Slice& sl, int32_t w,
-                                               const ListCtx& lc) {
+                                               const ListCtx& lc, uint32_t* seg = nullptr) {
   if (Mode == kModeGlobal) {
     const int32_t pos = find_sorted(sl.gkeys, sl.keys, w);
     if (K == kKindPerVertex && pos >= 0)
       atomicAdd((unsigned long long*)&lc.tv[w], 1ull);
     if (K == kKindSupport && pos >= 0) atomicAdd(&lc.sup[lc.ubeg + pos], 1u);
+    if (Seg && pos >= 0) atomicAdd(seg, 1u);
     return ballot(pos >= 0);
   }
-  if (counted(K)) return probe_counted<Mode, Wide>(t, sl, w);
+  if (counted(K)) return probe_counted<Mode, Wide, Seg>(t, sl, w, seg);
   return probe_ballot<false, Mode, Wide>(t, sl, w);
 }
 
@@ -509,10 +522,11 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       if (base + k * kWave < total) {
-        const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
-        const bool hit = (b >> lane) & 1u;
-        if (CNT && hit) atomicAdd(&ws.shits[seg[k]], 1u);
-        if (K == kKindSupport && hit) atomicAdd(&lc.sup[at[k]], 1u);  // the edge (v, w)
+        // a hit adds to its segment's counter inside the probe (counted kinds)
+        const uint64_t b = probe_mask<K, Mode, Wide, CNT>(t, sl, w[k], lc,
+                                                          &ws.shits[seg[k] < 0 ? 0 : seg[k]]);
+        if (K == kKindSupport && ((b >> lane) & 1u))
+          atomicAdd(&lc.sup[at[k]], 1u);  // the edge (v, w)
         hv += popc(b);
         if (K == kKindList) emit(lc, b, mid[k], w[k]);
       }
