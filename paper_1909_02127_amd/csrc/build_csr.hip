@@ -98,8 +98,8 @@ __global__ __launch_bounds__(kRadixBlock) void make_keys_kernel(int64_t n, int64
       k0 = ((uint64_t)a << cb) | (uint64_t)b;
       k1 = ((uint64_t)b << cb) | (uint64_t)a;
     }
-    keys[2 * i] = k0;
-    keys[2 * i + 1] = k1;
+    // both keys of the pair in one 16-byte store (keys is 16-byte aligned)
+    reinterpret_cast<ulonglong2*>(keys)[i] = make_ulonglong2(k0, k1);
     atomicAdd(&h[(uint32_t)k0 & mask0], 1u);
     atomicAdd(&h[(uint32_t)k1 & mask0], 1u);
   }
