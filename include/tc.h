@@ -87,7 +87,7 @@ typedef int32_t tc_status;
  */
 typedef struct tc_tune {
   int32_t small_max;     /* sources with 2 <= d+(u) <= small_max are handled by one wave,
-                            larger ones by a workgroup; 0 = default (64), at most 64 */
+                            larger ones by a workgroup; 0 = default (80), at most 96 */
   int32_t probe;         /* TC_PROBE_AUTO or TC_PROBE_SORTED */
   int32_t blocks_per_cu; /* persistent grid = blocks_per_cu x compute units, capped at the
                             occupancy limit; 0 = occupancy limit */

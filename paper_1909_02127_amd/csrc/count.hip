@@ -43,10 +43,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kSmallMax = 64;    // d+(u) <= kSmallMax: one wave per source
+constexpr int kSmallMax = 96;    // largest d+(u) a wave may take alone (tc_tune.small_max cap)
+constexpr int kSmallDefault = 80;  // default wave/workgroup split on d+(u)
 constexpr int kSideMax = 1024;   // slots per cuckoo half (workgroup mode)
 constexpr int kChunk = 816;      // keys per LDS table slice: side_log2(kChunk) <= log2(kSideMax)
-constexpr int kSmallSide = 128;  // slots per cuckoo half for kSmallMax keys
+constexpr int kSmallSide = 128;  // slots per cuckoo half for kSmallMax keys (load <= 0.4)
 constexpr int kStash = 32;
 constexpr int kMaxKicks = 48;
 constexpr int kUnroll = 4;       // 64-wide loads in flight per wave while streaming N+(v)
@@ -259,12 +260,14 @@ __device__ __forceinline__ int group_rank() {
 }
 
 // log2 of the slots per half for `keys` keys: load <= 0.4 over both halves.
-__device__ __forceinline__ int side_log2(int keys) {
+__host__ __device__ constexpr int side_log2(int keys) {
   const int want = keys + (keys >> 2) + 1;
   int b = 4;
   while ((1 << b) < want) ++b;
   return b;
 }
+static_assert((1 << side_log2(kSmallMax)) <= kSmallSide, "wave-mode table too small");
+static_assert((1 << side_log2(kChunk)) <= kSideMax, "workgroup-mode table too small");
 
 struct Slice {
   int side;   // slots per cuckoo half
@@ -888,7 +891,7 @@ struct Tune {
 };
 
 tc_status read_tune(const tc_tune* tune, Tune* out) {
-  out->small_max = kSmallMax;
+  out->small_max = kSmallDefault;
   out->force_sorted = 0;
   out->blocks_per_cu = 0;
   if (!tune) return TC_OK;

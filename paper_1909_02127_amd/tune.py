@@ -19,7 +19,7 @@ from ._lib import TC_PROBE_AUTO, TC_PROBE_SORTED
 
 DEFAULT_CANDIDATES = [
     {"small_max": s, "probe": p, "blocks_per_cu": b}
-    for s in (16, 32, 64)
+    for s in (16, 32, 64, 96)
     for p in (TC_PROBE_AUTO, TC_PROBE_SORTED)
     for b in (0, 4)
 ]

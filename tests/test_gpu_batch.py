@@ -87,7 +87,8 @@ def test_batched_tuning_never_changes_counts(tc):
     want, _ = _oracle_totals(graphs)
     b = PackedBatch(graphs)
     for tune in [None, {"small_max": 1}, {"small_max": 16}, {"probe": tc.TC_PROBE_SORTED},
-                 {"blocks_per_cu": 1}, {"small_max": 64, "probe": 1, "blocks_per_cu": 2}]:
+                 {"blocks_per_cu": 1}, {"small_max": 64, "probe": 1, "blocks_per_cu": 2},
+                 {"small_max": 96}]:
         br = BatchRunner(b, tune=tune)
         br.enqueue()
         assert br.results()[0] == want, tune
@@ -128,4 +129,4 @@ def test_batched_edge_cases(tc):
     assert totals == [4] and grand == 4 + 10
     with pytest.raises(_lib.TcError):
         _lib.tc_count_batched(b.n, br.dag_ptr, br.dag_col, b.vtx_off, br.totals[:1], br.ws_count,
-                              tune={"small_max": 65})
+                              tune={"small_max": 97})

@@ -291,3 +291,33 @@ def test_ids_above_2_24(tc):
         res, pv = _gpu(tc, n, s, d, order=order)
         assert res.total == T
         np.testing.assert_array_equal(pv, t)
+
+
+def test_wave_workgroup_split_thresholds(tc):
+    """Dense graphs put many sources at d+ in (64, 96]: every split between the one-wave
+    and the workgroup path (tc_tune.small_max) gives the oracle's total and t(v)."""
+    from paper_1909_02127_amd import _lib
+    for n, m, seed in [(400, 30000, 7), (1500, 60000, 8)]:
+        s, d, n = graphgen.erdos_renyi(n, m, seed)
+        s, d = s.numpy(), d.numpy()
+        T, t = _oracle(n, s, d)
+        p = tc.Pipeline(n, len(s))
+        p.build(_dev(s), _dev(d))
+        p.orient()
+        dplus = np.diff(p.dag_ptr.cpu().numpy())
+        _say("split thresholds n", n, "sources with 64 < d+ <= 96:", int(((dplus > 64) & (dplus <= 96)).sum()))
+        assert ((dplus > 64) & (dplus <= 96)).sum() > 0
+        total = torch.zeros(1, dtype=torch.int64, device="cuda")
+        pv = torch.zeros(n, dtype=torch.int64, device="cuda")
+        ws = torch.empty(_lib.tc_count_per_vertex_workspace(n), dtype=torch.uint8, device="cuda")
+        for sm in (0, 1, 64, 65, 80, 95, 96):
+            tune = {"small_max": sm}
+            _lib.tc_count_per_vertex(n, p.dag_ptr, p.dag_col, pv, total, ws, tune=tune)
+            torch.cuda.synchronize()
+            assert int(total.item()) == T, sm
+            np.testing.assert_array_equal(pv.cpu().numpy().astype(np.uint64), t)
+            _lib.tc_count(n, p.dag_ptr, p.dag_col, total, ws, tune=tune)
+            torch.cuda.synchronize()
+            assert int(total.item()) == T, sm
+        with pytest.raises(_lib.TcError):
+            _lib.tc_count(n, p.dag_ptr, p.dag_col, total, ws, tune={"small_max": 97})
