@@ -309,9 +309,9 @@ __device__ __forceinline__ uint64_t probe_counted(const Table& t, const Slice& s
     return ballot(h);
   }
   // byte offsets of the two slots, shared by the key and the counter arrays
-  const uint32_t x = hash_input<Wide>(w);
-  const uint32_t oa = hash_a_of(x, sl.shift) * 4u;
-  const uint32_t ob = (uint32_t)sl.side * 4u + hash_b_of(x, sl.shift) * 4u;
+  const uint32_t p = hash_product(hash_input<Wide>(w));
+  const uint32_t oa = slot_a_of(p, sl.shift) * 4u;
+  const uint32_t ob = (uint32_t)sl.side * 4u + slot_b_of(p, sl.shift) * 4u;
   const int32_t a = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(t.slot) + oa);
   const int32_t b = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(t.slot) + ob);
   const bool ha = a == w;
@@ -340,9 +340,9 @@ template <bool PV, int Mode, bool Wide>
 __device__ __forceinline__ uint64_t probe_ballot(const Table& t, const Slice& sl, int32_t w) {
   if (PV) return probe_counted<Mode, Wide, false>(t, sl, w, nullptr);
   if (Mode == kModeSorted) return ballot(probe_sorted<false>(t, sl, w));
-  const uint32_t x = hash_input<Wide>(w);
-  const int32_t a = t.slot[hash_a_of(x, sl.shift)];
-  const int32_t b = t.slot[(uint32_t)sl.side + hash_b_of(x, sl.shift)];
+  const uint32_t p = hash_product(hash_input<Wide>(w));
+  const int32_t a = t.slot[slot_a_of(p, sl.shift)];
+  const int32_t b = t.slot[(uint32_t)sl.side + slot_b_of(p, sl.shift)];
   uint64_t m = ballot(a == w) | ballot(b == w);
   if (Mode == kModeStash) {
     for (int i = 0; i < sl.stash_n; ++i) m |= ballot(t.stash[i] == w);
@@ -612,9 +612,9 @@ template <bool Wide>
 __device__ __forceinline__ uint32_t slot_count(const Table& t, const Slice& sl, int mode,
                                                int p, int32_t w) {
   if (mode == kModeSorted) return t.cnt[p];
-  const uint32_t x = hash_input<Wide>(w);
-  const uint32_t s1 = hash_a_of(x, sl.shift);
-  const uint32_t s2 = (uint32_t)sl.side + hash_b_of(x, sl.shift);
+  const uint32_t hp = hash_product(hash_input<Wide>(w));
+  const uint32_t s1 = slot_a_of(hp, sl.shift);
+  const uint32_t s2 = (uint32_t)sl.side + slot_b_of(hp, sl.shift);
   if (t.slot[s1] == w) return t.cnt[s1];
   if (t.slot[s2] == w) return t.cnt[s2];
   for (int i = 0; i < sl.stash_n; ++i)
