@@ -26,9 +26,11 @@
 // (its four waves take the v's round robin); the rest are handled one wave each.
 // N+(u) longer than kChunk is processed in kChunk-sized slices of the table.
 //
-// Per-vertex counts: t(u) += hits of source u, t(v) += hits of edge (u,v), and
-// t(w) += the hit counter of w's LDS slot, flushed once per source, so global
-// atomics are at most n + 2m rather than one per triangle.
+// Per-vertex counts: t(u) += hits of source u; t(v) += hits of the edge (u,v)
+// and t(w) += hits closed at w both gather in the LDS slot counters of v and w
+// (when the table holds all of N+(u); split sources add t(v) directly) and are
+// flushed once per source, so global atomics are at most n + 2m rather than
+// one per triangle.
 #include "tc_device.h"
 #include "tc_hash.h"
 #include "tc_host.h"
@@ -472,6 +474,48 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
   return hv;
 }
 
+// Adds c to the per-slot counter of key v (counted kinds), for a v that is in
+// the table: a middle of the source, when the table holds all of N+(u).  The
+// (u, v) counts then reach memory with the slot's own flush at the end of the
+// source instead of one global atomic per middle; such an atomic, although
+// nothing waits for its value, holds up the wave's next wait on a list load.
+template <int Mode, bool Wide>
+__device__ __forceinline__ void slot_add(const Table& t, const Slice& sl, int32_t v, uint32_t c) {
+  if (Mode == kModeSorted) {
+    int lo = 0, len = sl.keys;
+    while (len > 0) {
+      const int half = len >> 1;
+      if (t.slot[lo + half] < v) {
+        lo += half + 1;
+        len -= half + 1;
+      } else {
+        len = half;
+      }
+    }
+    atomicAdd(&t.cnt[lo], c);
+    return;
+  }
+  const uint32_t p = hash_product(hash_input<Wide>(v));
+  const uint32_t s1 = slot_a_of(p, sl.shift);
+  if (t.slot[s1] == v) {
+    atomicAdd(&t.cnt[s1], c);
+    return;
+  }
+  const uint32_t s2 = (uint32_t)sl.side + slot_b_of(p, sl.shift);
+  if (t.slot[s2] == v) {
+    atomicAdd(&t.cnt[s2], c);
+    return;
+  }
+  if (Mode == kModeStash) {
+    for (int i = 0; i < sl.stash_n; ++i) {
+      if (t.stash[i] == v) {
+        atomicAdd(&t.stash_cnt[i], c);
+        return;
+      }
+    }
+  }
+}
+
 // The short out-lists of up to 64 middles held one per lane (len = 0 for lanes
 // without one) walked as one concatenation, kWin * 64 wedges per step, so a
 // wave is not spent on a single short list.  Lane l's segment is the last lane
@@ -484,7 +528,7 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
                                                const int32_t* __restrict__ col, const Table& t,
                                                const Slice& sl, const WaveScratch& ws,
                                                uint64_t* __restrict__ tv, const ListCtx& lc,
-                                               int64_t uv_edge) {
+                                               int64_t uv_edge, bool local_v) {
   constexpr bool PV = K == kKindPerVertex;
   constexpr bool CNT = counted(K);
   const int lane = lane_id();
@@ -538,8 +582,12 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
   if (CNT) {
     wave_sync();
     const uint32_t c = ws.shits[lane];
-    if (PV && c) atomicAdd((unsigned long long*)&tv[v], (unsigned long long)c);
-    if (K == kKindSupport && c) atomicAdd(&lc.sup[uv_edge], c);  // the edge (u, v)
+    if (c && local_v) {
+      slot_add<Mode, Wide>(t, sl, v, c);  // t(v), or the edge (u, v)
+    } else if (c) {
+      if (PV) atomicAdd((unsigned long long*)&tv[v], (unsigned long long)c);
+      if (K == kKindSupport) atomicAdd(&lc.sup[uv_edge], c);  // the edge (u, v)
+    }
   }
   return hv;
 }
@@ -556,6 +604,8 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
   constexpr bool PV = K == kKindPerVertex;
   const int lane = lane_id();
   const int gwave = Waves == 1 ? 0 : (int)threadIdx.x / kWave;
+  // every middle is a key of this table (one slice): (u, v) counts go to its slot
+  const bool local_v = Mode != kModeGlobal && (int64_t)sl.keys == d;
   uint64_t src_hits = 0;
   for (int64_t i0 = 0; i0 < d; i0 += (int64_t)Waves * kWave) {
     const int64_t i = i0 + (int64_t)Waves * lane + gwave;
@@ -585,14 +635,20 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
       const int32_t vj = read_lane(v, j);
       const uint32_t hv = scan_list<K, Mode, Wide>(col + jb, (int)(je - jb), t, sl, vj, lc, jb);
       src_hits += hv;
-      if (PV && hv && lane == 0) atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
-      if (K == kKindSupport && hv && lane == 0)  // the edge (u, v)
-        atomicAdd(&lc.sup[lc.ubeg + i0 + (int64_t)Waves * j + gwave], hv);
+      if (counted(K) && hv && lane == 0) {
+        if (local_v) {
+          slot_add<Mode, Wide>(t, sl, vj, hv);  // t(v), or the edge (u, v)
+        } else {
+          if (PV) atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
+          if (K == kKindSupport)  // the edge (u, v)
+            atomicAdd(&lc.sup[lc.ubeg + i0 + (int64_t)Waves * j + gwave], hv);
+        }
+      }
     }
     if (walk_short) {
       const bool is_short = len > 0 && len < kShortMax;
       src_hits += scan_short<K, Mode, Wide, OffT>(v, vb, is_short ? (int32_t)len : 0, col, t, sl,
-                                                  ws, tv, lc, lc.ubeg + i);
+                                                  ws, tv, lc, lc.ubeg + i, local_v);
     }
   }
   return src_hits;
