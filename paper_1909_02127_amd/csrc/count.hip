@@ -522,14 +522,13 @@ __device__ __forceinline__ void slot_add(const Table& t, const Slice& sl, int32_
 // whose list starts at or before its position: each list's first position is
 // marked in LDS and propagated with a wave max-scan.  The marker array holds -1
 // between walks (the writer clears its own entry after the step; a wave's LDS
-// operations complete in program order).  Returns the hits (uniform).
+// operations complete in program order).  Returns the hits (uniform); counted
+// kinds also get each lane's own list's hits in *seg_hits.
 template <int K, int Mode, bool Wide, typename OffT>
 __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
                                                const int32_t* __restrict__ col, const Table& t,
                                                const Slice& sl, const WaveScratch& ws,
-                                               uint64_t* __restrict__ tv, const ListCtx& lc,
-                                               int64_t uv_edge, bool local_v) {
-  constexpr bool PV = K == kKindPerVertex;
+                                               const ListCtx& lc, uint32_t* seg_hits) {
   constexpr bool CNT = counted(K);
   const int lane = lane_id();
   const int32_t incl = wave_inclusive_sum32(len);
@@ -581,13 +580,7 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
   }
   if (CNT) {
     wave_sync();
-    const uint32_t c = ws.shits[lane];
-    if (c && local_v) {
-      slot_add<Mode, Wide>(t, sl, v, c);  // t(v), or the edge (u, v)
-    } else if (c) {
-      if (PV) atomicAdd((unsigned long long*)&tv[v], (unsigned long long)c);
-      if (K == kKindSupport) atomicAdd(&lc.sup[uv_edge], c);  // the edge (u, v)
-    }
+    *seg_hits = ws.shits[lane];
   }
   return hv;
 }
@@ -621,6 +614,7 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
     const uint64_t shorts = Mode == kModeCuckoo ? ballot(len > 0 && len < kShortMax) : 0;
     const bool walk_short = popc(shorts) >= kShortMinLists;
     uint64_t longs = walk_short ? ballot(len >= kShortMax) : ballot(len > 0);
+    uint32_t cv = 0;  // counted kinds: the (u, v) hits of this lane's middle
     while (longs) {
       const int j = __builtin_ctzll(longs);
       longs &= longs - 1;
@@ -635,20 +629,23 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
       const int32_t vj = read_lane(v, j);
       const uint32_t hv = scan_list<K, Mode, Wide>(col + jb, (int)(je - jb), t, sl, vj, lc, jb);
       src_hits += hv;
-      if (counted(K) && hv && lane == 0) {
-        if (local_v) {
-          slot_add<Mode, Wide>(t, sl, vj, hv);  // t(v), or the edge (u, v)
-        } else {
-          if (PV) atomicAdd((unsigned long long*)&tv[vj], (unsigned long long)hv);
-          if (K == kKindSupport)  // the edge (u, v)
-            atomicAdd(&lc.sup[lc.ubeg + i0 + (int64_t)Waves * j + gwave], hv);
-        }
-      }
+      if (counted(K) && lane == j) cv = hv;
     }
     if (walk_short) {
       const bool is_short = len > 0 && len < kShortMax;
+      uint32_t cs = 0;
       src_hits += scan_short<K, Mode, Wide, OffT>(v, vb, is_short ? (int32_t)len : 0, col, t, sl,
-                                                  ws, tv, lc, lc.ubeg + i, local_v);
+                                                  ws, lc, &cs);
+      cv += cs;
+    }
+    // the (u, v) counts of the batch's middles, all lanes at once
+    if (counted(K) && cv) {
+      if (local_v) {
+        slot_add<Mode, Wide>(t, sl, v, cv);  // t(v), or the edge (u, v)
+      } else {
+        if (PV) atomicAdd((unsigned long long*)&tv[v], (unsigned long long)cv);
+        if (K == kKindSupport) atomicAdd(&lc.sup[lc.ubeg + i], cv);  // the edge (u, v)
+      }
     }
   }
   return src_hits;
