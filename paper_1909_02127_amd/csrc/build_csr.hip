@@ -136,6 +136,17 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
     hist[(int64_t)d * num_tiles + blockIdx.x] = h[d];
 }
 
+// The tile a scatter workgroup takes.  Workgroups go to the eight XCDs round
+// robin (workgroup b to XCD b mod 8); this gives every XCD one contiguous range
+// of tiles, taken in order, so the cache line where tile t's run of a digit
+// ends and tile t + 1's begins is usually written through one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t g) {
+  const int64_t per = g / kXcds, rem = g % kXcds;
+  const int64_t x = b % kXcds, i = b / kXcds;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // Stable scatter of one tile: keys of equal digit keep their input order.  Each
 // wave ranks its own contiguous quarter of the tile, 64 keys per round (peers of
 // equal digit from one ballot per digit bit, a per-wave running count per
@@ -157,10 +168,11 @@ __global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
   const int wave = t / kWave;
   const int lane = lane_id();
   const uint32_t mask = (1u << bits) - 1u;
-  const int64_t tile = (int64_t)blockIdx.x * kRadixTile;
+  const int64_t tile_id = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t tile = tile_id * kRadixTile;
   const int valid_n = (int)(nk - tile < kRadixTile ? nk - tile : kRadixTile);
   // the histogram table holds rows for the pass's digits only
-  if (t < (1 << bits)) gbase[t] = offsets[(int64_t)t * num_tiles + blockIdx.x];
+  if (t < (1 << bits)) gbase[t] = offsets[(int64_t)t * num_tiles + tile_id];
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
   __syncthreads();
