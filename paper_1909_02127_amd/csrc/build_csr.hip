@@ -136,17 +136,6 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
     hist[(int64_t)d * num_tiles + blockIdx.x] = h[d];
 }
 
-// The tile a scatter workgroup takes.  Workgroups go to the eight XCDs round
-// robin (workgroup b to XCD b mod 8); this gives every XCD one contiguous range
-// of tiles, taken in order, so the cache line where tile t's run of a digit
-// ends and tile t + 1's begins is usually written through one L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t g) {
-  const int64_t per = g / kXcds, rem = g % kXcds;
-  const int64_t x = b % kXcds, i = b / kXcds;
-  return x * per + (x < rem ? x : rem) + i;
-}
-
 // Stable scatter of one tile: keys of equal digit keep their input order.  Each
 // wave ranks its own contiguous quarter of the tile, 64 keys per round (peers of
 // equal digit from one ballot per digit bit, a per-wave running count per
@@ -285,7 +274,8 @@ __global__ __launch_bounds__(kDedupBlock) void dedup_count_kernel(const uint64_t
                                                                   int64_t* __restrict__ partial) {
   __shared__ uint32_t wave_cnt[kDedupBlock / kWave];
   const int wave = threadIdx.x / kWave;
-  const int64_t base = (int64_t)blockIdx.x * kDedupTile + (int64_t)wave * kDedupRun;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t base = tile * kDedupTile + (int64_t)wave * kDedupRun;
   uint64_t k[kDedupItems], keep[kDedupItems];
   dedup_load(keys, nk, base, k, keep);
   uint32_t c = 0;
@@ -296,7 +286,7 @@ __global__ __launch_bounds__(kDedupBlock) void dedup_count_kernel(const uint64_t
   if (threadIdx.x == 0) {
     uint32_t tot = 0;
     for (int w = 0; w < kDedupBlock / kWave; ++w) tot += wave_cnt[w];
-    partial[blockIdx.x] = tot;
+    partial[tile] = tot;
   }
 }
 
@@ -309,7 +299,8 @@ __global__ __launch_bounds__(kDedupBlock) void dedup_write_kernel(
   __shared__ uint32_t wave_cnt[kDedupBlock / kWave];
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
-  const int64_t base = (int64_t)blockIdx.x * kDedupTile + (int64_t)wave * kDedupRun;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t base = tile * kDedupTile + (int64_t)wave * kDedupRun;
   uint64_t k[kDedupItems], keep[kDedupItems];
   dedup_load(keys, nk, base, k, keep);
   uint32_t c = 0;
@@ -317,7 +308,7 @@ __global__ __launch_bounds__(kDedupBlock) void dedup_write_kernel(
   for (int r = 0; r < kDedupItems; ++r) c += popc(keep[r]);
   if (lane == 0) wave_cnt[wave] = c;
   __syncthreads();
-  int64_t pos = partial[blockIdx.x];
+  int64_t pos = partial[tile];
   for (int w = 0; w < wave; ++w) pos += wave_cnt[w];
   // the row of the key before the wave's run (a kept key whose row differs
   // from its predecessor's starts that row)
