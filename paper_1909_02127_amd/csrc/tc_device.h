@@ -38,22 +38,6 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t g) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
-// A persistent workgroup's walk over `tiles` tiles: first, end (exclusive) and
-// step.  Workgroup b takes every step-th tile of its XCD's range; with fewer
-// workgroups than XCDs it falls back to a plain grid-stride walk.
-struct TileWalk {
-  int64_t first, end, step;
-};
-__device__ __forceinline__ TileWalk xcd_walk(int64_t b, int64_t g, int64_t tiles) {
-  if (g < kXcds) return TileWalk{b, tiles, g};
-  const int64_t x = b % kXcds, i = b / kXcds;
-  const int64_t per = tiles / kXcds, rem = tiles % kXcds;
-  const int64_t start = x * per + (x < rem ? x : rem);
-  const int64_t len = per + (x < rem ? 1 : 0);
-  const int64_t on_xcd = g / kXcds + (x < g % kXcds ? 1 : 0);
-  return TileWalk{start + i, start + len, on_xcd};
-}
-
 // Make this wave's earlier LDS writes visible to its later LDS reads from other lanes.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
