@@ -75,7 +75,8 @@ __global__ __launch_bounds__(kRadixBlock) void make_keys_kernel(int64_t n, int64
   bool bad = false;
   // the tile's pairs, all loads in flight together (clamped to the last pair)
   constexpr int kPairs = kRadixItems / 2;
-  const int64_t first = (int64_t)blockIdx.x * (kRadixTile / 2);
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t first = tile * (kRadixTile / 2);
   const int valid = (int)(num_pairs - first < kRadixTile / 2 ? num_pairs - first : kRadixTile / 2);
   int32_t pa[kPairs], pb[kPairs];
 #pragma unroll
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kRadixBlock) void make_keys_kernel(int64_t n, int64
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(err, 1);
   __syncthreads();
   for (int d = threadIdx.x; d < digits; d += kRadixBlock)
-    hist[(int64_t)d * num_tiles + blockIdx.x] = h[d];
+    hist[(int64_t)d * num_tiles + tile] = h[d];
 }
 
 __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t* __restrict__ keys,
@@ -119,7 +120,8 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
   for (int d = threadIdx.x; d < digits; d += kRadixBlock) h[d] = 0;
   __syncthreads();
   // the tile's keys, all loads in flight together (clamped to the last key)
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t base = tile * kRadixTile;
   const int valid = (int)(nk - base < kRadixTile ? nk - base : kRadixTile);
   uint64_t k[kRadixItems];
 #pragma unroll
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kRadixBlock) void radix_hist_kernel(const uint64_t*
       atomicAdd(&h[(uint32_t)(k[r] >> shift) & mask], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < digits; d += kRadixBlock)
-    hist[(int64_t)d * num_tiles + blockIdx.x] = h[d];
+    hist[(int64_t)d * num_tiles + tile] = h[d];
 }
 
 // Stable scatter of one tile: keys of equal digit keep their input order.  Each
