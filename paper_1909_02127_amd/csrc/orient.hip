@@ -35,7 +35,7 @@ constexpr int kItems = 16;              // entries per thread and tile
 constexpr int kTile = kBlock * kItems;  // entries per tile
 constexpr int kPadded = kTile + kTile / kItems;
 constexpr int kTileBlocksPerCu = 4;     // write_kernel LDS: about 35 KB per workgroup
-constexpr int kFlagBlocksPerCu = 6;     // flags_kernel LDS: about 22 KB per workgroup
+constexpr int kFlagBlocksPerCu = 64;    // flags_kernel grid cap: one tile per workgroup up to 64 per CU
 
 // LDS index of tile entry i, padded so that a thread's kItems consecutive
 // entries fall into distinct banks across a wave.
