@@ -34,7 +34,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kItems = 16;              // entries per thread and tile
 constexpr int kTile = kBlock * kItems;  // entries per tile
 constexpr int kPadded = kTile + kTile / kItems;
-constexpr int kTileBlocksPerCu = 4;     // write_kernel LDS: about 35 KB per workgroup
+constexpr int kTileBlocksPerCu = 64;    // write_kernel grid cap (LDS: about 35 KB per workgroup)
 constexpr int kFlagBlocksPerCu = 64;    // flags_kernel grid cap: one tile per workgroup up to 64 per CU
 
 // LDS index of tile entry i, padded so that a thread's kItems consecutive
