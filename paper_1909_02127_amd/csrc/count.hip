@@ -124,6 +124,7 @@ struct CountState {
 };
 
 constexpr int kSmallGrab = 16;  // wave-mode sources per run in the dynamic hand-out
+static_assert(kSmallGrab <= kWave, "a run's sources are prefetched one per lane");
 
 constexpr int kBinItems = 16;
 
@@ -675,11 +676,13 @@ __device__ __forceinline__ uint32_t slot_count(const Table& t, const Slice& sl, 
   return 0;
 }
 
-// Process one source u with a group of Waves waves sharing table `t`.
-// Returns this wave's hit count (uniform across the wave).
+// Process one source u (its out-list at col[beg, beg + d)) with a group of
+// Waves waves sharing table `t`.  Returns this wave's hit count (uniform across
+// the wave).
 
 template <int Waves, int K, bool Wide, typename OffT>
-__device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
+__device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
+                                   const OffT* __restrict__ row_ptr,
                                    const int32_t* __restrict__ col, uint64_t* __restrict__ tv,
                                    const Table& t, const WaveScratch& ws, int max_keys,
                                    int max_kicks, bool force_sorted, const ListArgs& la) {
@@ -687,8 +690,6 @@ __device__ uint64_t process_source(int64_t u, const OffT* __restrict__ row_ptr,
   constexpr bool CNT = counted(K);
   const int lane = lane_id();
   const int gr = group_rank<Waves>();
-  const int64_t beg = row_ptr[u];
-  const int64_t d = (int64_t)row_ptr[u + 1] - beg;
   const int32_t* nbrs = col + beg;
   uint64_t wave_hits = 0;
   ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u, la.sup, beg, tv};
@@ -852,8 +853,10 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   const Table big = table_at<PV>(smem, kSideMax);
   for (int32_t idx = blockIdx.x; idx < n_large;) {
     const int32_t u = list[idx];
+    const int64_t beg = row_ptr[u];
+    const int64_t d = (int64_t)row_ptr[u + 1] - beg;
     const uint64_t h = process_source<kWavesPerBlock, K, Wide, OffT>(
-        u, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, args.list);
+        u, beg, d, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, args.list);
     hits += h;
     credit(u, h);
     if (args.src_cnt && h && lane == 0)
@@ -877,9 +880,26 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   while (first < n_small) {
     const int32_t last = dynamic ? (first + kSmallGrab < n_small ? first + kSmallGrab : n_small)
                                  : first + 1;
+    // the run's source ids and row bounds, one source per lane, loaded together
+    int32_t ru = 0;
+    OffT rb = 0, re = 0;
+    if (lane < last - first) {
+      ru = list[n_large + first + lane];
+      rb = row_ptr[ru];
+      re = row_ptr[ru + 1];
+    }
     for (int32_t i = first; i < last; ++i) {
-      const int32_t u = list[n_large + i];
-      const uint64_t h = process_source<1, K, Wide, OffT>(u, row_ptr, col, tv, mine, ws,
+      const int src = i - first;
+      const int32_t u = read_lane(ru, src);
+      int64_t beg, d;
+      if (sizeof(OffT) == 4) {
+        beg = read_lane((int32_t)rb, src);
+        d = (int64_t)read_lane((int32_t)re, src) - beg;
+      } else {
+        beg = read_lane64((int64_t)rb, src);
+        d = read_lane64((int64_t)re, src) - beg;
+      }
+      const uint64_t h = process_source<1, K, Wide, OffT>(u, beg, d, row_ptr, col, tv, mine, ws,
                                                           kSmallMax, args.max_kicks,
                                                           args.force_sorted, args.list);
       hits += h;
