@@ -272,6 +272,19 @@ def cpu_baseline(spec, s_host, d_host, n, budget_s: float):
     }
 
 
+def oracle_prefix_baseline(fn, dp, dc, frac: float, value_of, unit: str, what: str) -> dict:
+    """A single-threaded oracle function timed on the sources below frac * n.  Vertex
+    ids are permuted by the generator, so the prefix is a uniform sample of sources."""
+    n = dp.size - 1
+    k = max(1, int(n * frac))
+    t0 = time.perf_counter()
+    r = fn(dp, dc, sources=k)
+    dt = time.perf_counter() - t0
+    return {"value": value_of(r, k) / dt, "unit": unit, "cores": 1, "kind": "oracle",
+            "sample": f"sources below {k} of {n} ({frac:.3g} of the ids): {what} in {dt:.1f}s, "
+                      f"one thread"}
+
+
 def batch_main(args, spec):
     """Batched path vs the plain one-graph-per-launch path on the same packed graphs."""
     import numpy as np
@@ -332,12 +345,43 @@ def batch_main(args, spec):
     wall_plain = (time.perf_counter() - w0) / plain_steps * 1e3
     plain_totals = pr.results()
 
+    # the dominant kernel alone (the batched count launch), timed with HIP events
+    # on the stream it runs on, against its algorithmic bytes over the union DAG
+    for _ in range(2):
+        br.count_only()
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(args.steps):
+        br.count_only()
+    c1.record()
+    torch.cuda.synchronize()
+    ms_count = c0.elapsed_time(c1) / args.steps
+    alg = algorithmic_bytes(br.dag_ptr, br.dag_col, b.n, spec["offset_bytes"], per_vertex=False)
+    achieved = alg["bytes"] / (ms_count / 1e3) / 1e9
+
     rng = np.random.default_rng(0)
     sample = sorted(rng.choice(len(graphs), size=min(16, len(graphs)), replace=False).tolist())
     oracle_ok = all(
         oracle.triangles(graphs[i][2], graphs[i][0].cpu().numpy(), graphs[i][1].cpu().numpy())
         == totals[i] for i in sample)
     G = b.G
+    cb = None
+    if not args.no_cpu_baseline:
+        # the oracle's whole pipeline per graph, graphs in batch order, for a bounded time
+        host = [(g[2], g[0].cpu().numpy(), g[1].cpu().numpy()) for g in graphs]
+        threads = oracle.max_threads()
+        budget = min(args.cpu_budget_s, 20.0)
+        done = 0
+        w1 = time.perf_counter()
+        while done < len(host) and time.perf_counter() - w1 < budget:
+            n_i, s_i, d_i = host[done]
+            oracle.triangles(n_i, s_i, d_i, threads=threads)
+            done += 1
+        dt = time.perf_counter() - w1
+        cb = {"value": done / dt, "unit": "graphs/s", "cores": threads, "kind": "oracle",
+              "sample": f"the first {done} of the {G} graphs in batch order, clean + orient + count "
+                        f"each ({dt:.1f}s; count on {threads} OpenMP threads)"}
     out = {
         "metric": "batched graphs/s (bit-exact vs oracle)",
         "value": G / (ms_batched / 1e3),
@@ -356,8 +400,15 @@ def batch_main(args, spec):
         "triangles": grand,
         "plain_equals_batched": plain_totals == totals,
         "oracle_sample_graphs": len(sample), "oracle_match": oracle_ok,
+        "roofline": {"bound": "hbm", "kernel": "count_kernel (tc_count_batched)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": alg["bytes"], "wedges": alg["wedges"],
+                     "ms_count": ms_count},
         "autotune_table": table,
     }
+    if cb is not None:
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
@@ -494,11 +545,17 @@ def list_main(args, spec):
     ms = e0.elapsed_time(e1) / args.steps
     rows = pipe.listing()
     ok = rows.shape[0] == T
-    if not args.no_check:
+    cb = None
+    if not args.no_check or not args.no_cpu_baseline:
         import oracle
         rp, col = oracle.clean(n, s.cpu().numpy(), d.cpu().numpy())
         dp, dc = oracle.orient(rp, col)
-        ok = ok and oracle.count(dp, dc) == T
+        if not args.no_check:
+            ok = ok and oracle.count(dp, dc) == T
+        if not args.no_cpu_baseline:
+            cb = oracle_prefix_baseline(oracle.list_triangles, dp, dc, 1 / 4,
+                                        lambda r, k: r.shape[0], "triangles/s",
+                                        "every triangle listed")
     alg = algorithmic_bytes(pipe.dag_ptr, pipe.dag_col, n, ob, per_vertex=False)
     # two enumeration passes, 12 B per row written, a count and an offset per vertex
     b = 2 * alg["bytes"] + 12 * T + 16 * n
@@ -517,6 +574,8 @@ def list_main(args, spec):
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b},
     }
+    if cb is not None:
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
@@ -546,12 +605,18 @@ def support_main(args, spec):
     sup = pipe.supports()
     T = res.total
     ok = int(sup.to(torch.int64).sum().item()) == 3 * T
-    if not args.no_check:
+    cb = None
+    if not args.no_check or not args.no_cpu_baseline:
         import oracle
         rp, col = oracle.clean(n, s.cpu().numpy(), d.cpu().numpy())
         dp, dc = oracle.orient(rp, col)
-        _, want = oracle.edge_support(dp, dc)
-        ok = ok and np.array_equal(sup.cpu().numpy().view(np.uint32), want)
+        if not args.no_check:
+            _, want = oracle.edge_support(dp, dc)
+            ok = ok and np.array_equal(sup.cpu().numpy().view(np.uint32), want)
+        if not args.no_cpu_baseline:
+            cb = oracle_prefix_baseline(oracle.edge_support, dp, dc, 1 / 2,
+                                        lambda r, k: int(dp[k]) / 1e9, "GTEPS",
+                                        "the support of every edge")
     alg = algorithmic_bytes(pipe.dag_ptr, pipe.dag_col, n, ob, per_vertex=False)
     # the count's bytes, a 4-byte read-modify-write per triangle on (v, w), and per edge
     # the zeroing store plus the aggregated (u, v) and (u, w) read-modify-writes
@@ -571,6 +636,8 @@ def support_main(args, spec):
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b},
     }
+    if cb is not None:
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
@@ -667,10 +734,35 @@ def k4_main(args, spec):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     k4 = int(total.item())
+    # Algorithmic bytes of one launch: each source with d+ >= 3 reads its row bounds
+    # and N+(u); each of its middles v its row bounds, and N+(v) when d+(v) >= 2;
+    # each kept w (a triangle u -> v -> w with d+(v) >= 2) its row bounds and N+(w).
+    o = spec["offset_bytes"]
+    dplus = (pipe.dag_ptr[1:] - pipe.dag_ptr[:-1]).to(torch.int64)
+    src3 = dplus >= 3
+    rows_u = torch.repeat_interleave(torch.arange(n, device=dev), dplus)
+    mid_ok = src3[rows_u]
+    mids = pipe.dag_col.to(torch.int64)[: rows_u.numel()][mid_ok]
+    b = int((2 * o + 4 * dplus[src3]).sum().item()) + 2 * o * int(mids.numel())
+    b += 4 * int(dplus[mids][dplus[mids] >= 2].sum().item())
+    del rows_u, mid_ok, mids
+    pipe.list_triangles(res.total)
+    tri = pipe.listing().to(torch.int64)
+    keep = src3[tri[:, 0]] & (dplus[tri[:, 1]] >= 2)
+    b += int((2 * o + 4 * dplus[tri[:, 2][keep]]).sum().item())
+    del tri, keep
+    achieved = b / (ms / 1e3) / 1e9
     ok = None
-    if not args.no_check:
+    cb = None
+    if not args.no_check or not args.no_cpu_baseline:
         import oracle
-        ok = oracle.k4(n, s.cpu().numpy(), d.cpu().numpy()) == k4
+        rp, col = oracle.clean(n, s.cpu().numpy(), d.cpu().numpy())
+        dp, dc = oracle.orient(rp, col)
+        if not args.no_check:
+            ok = oracle.count_k4(dp, dc) == k4
+        if not args.no_cpu_baseline:
+            cb = oracle_prefix_baseline(oracle.count_k4, dp, dc, 1 / 2, lambda r, k: r,
+                                        "4-cliques/s", "4-cliques counted")
     out = {
         "metric": "4-cliques/s (exact vs oracle)", "value": k4 / (ms / 1e3), "unit": "4-cliques/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -679,7 +771,12 @@ def k4_main(args, spec):
         "config": {"workload": args.workload, "n": n, "m": res.m, "triangles": res.total,
                    "k4": k4, "order": "degree", "parallelism": "single-gpu"},
         "gteps": res.m / (ms / 1e3) / 1e9, "oracle_match": ok,
+        "roofline": {"bound": "hbm", "kernel": "k4_kernel", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": b},
     }
+    if cb is not None:
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -131,13 +131,21 @@ def count(dag_ptr: np.ndarray, dag_col: np.ndarray, *, per_vertex: bool = False,
     return total
 
 
-def list_triangles(dag_ptr: np.ndarray, dag_col: np.ndarray) -> np.ndarray:
+def _sources(dag_ptr: np.ndarray, sources) -> int:
+    """Sources to enumerate: all n, or the first `sources` ids (a timing sample;
+    the rows of every vertex stay readable)."""
+    n = dag_ptr.size - 1
+    return n if sources is None else max(0, min(int(sources), n))
+
+
+def list_triangles(dag_ptr: np.ndarray, dag_col: np.ndarray, sources=None) -> np.ndarray:
     """The triangles of an oriented graph as an int32 array of shape (T, 3): rows
-    (u, v, w) with v, w in N+(u) and w in N+(v), in lexicographic order."""
+    (u, v, w) with v, w in N+(u) and w in N+(v), in lexicographic order.  With
+    `sources`, only the triangles whose source u (lowest rank) has an id below it."""
     lib = _load()
     dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
     dag_col = _i32(dag_col)
-    n = dag_ptr.size - 1
+    n = _sources(dag_ptr, sources)
     total = int(lib.oracle_list(n, _ptr(dag_ptr), _ptr(dag_col), None, 0))
     out = np.zeros((max(total, 1), 3), dtype=np.int32)
     got = int(lib.oracle_list(n, _ptr(dag_ptr), _ptr(dag_col), _ptr(out), total))
@@ -146,12 +154,13 @@ def list_triangles(dag_ptr: np.ndarray, dag_col: np.ndarray) -> np.ndarray:
     return out[:total].copy()
 
 
-def count_k4(dag_ptr: np.ndarray, dag_col: np.ndarray) -> int:
-    """Number of 4-cliques of an oriented graph (each found once)."""
+def count_k4(dag_ptr: np.ndarray, dag_col: np.ndarray, sources=None) -> int:
+    """Number of 4-cliques of an oriented graph (each found once).  With `sources`,
+    only those whose source (lowest rank) has an id below it."""
     lib = _load()
     dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
     dag_col = _i32(dag_col)
-    r = int(lib.oracle_count_k4(dag_ptr.size - 1, _ptr(dag_ptr), _ptr(dag_col)))
+    r = int(lib.oracle_count_k4(_sources(dag_ptr, sources), _ptr(dag_ptr), _ptr(dag_col)))
     if r == (1 << 64) - 1:
         raise OracleError("oracle_count_k4: allocation failed")
     return r
@@ -176,12 +185,13 @@ def kcore(row_ptr: np.ndarray, col: np.ndarray, k: int = 2) -> np.ndarray:
     return keep[:n].copy()
 
 
-def edge_support(dag_ptr: np.ndarray, dag_col: np.ndarray) -> tuple[int, np.ndarray]:
-    """(T, sup) where sup[e] (uint32, one per oriented edge) counts the triangles on edge e."""
+def edge_support(dag_ptr: np.ndarray, dag_col: np.ndarray, sources=None) -> tuple[int, np.ndarray]:
+    """(T, sup) where sup[e] (uint32, one per oriented edge) counts the triangles on edge e.
+    With `sources`, only the triangles whose source (lowest rank) has an id below it count."""
     lib = _load()
     dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
     dag_col = _i32(dag_col)
-    n = dag_ptr.size - 1
+    n = _sources(dag_ptr, sources)
     sup = np.zeros(max(int(dag_ptr[-1]), 1), dtype=np.uint32)
     total = int(lib.oracle_edge_support(n, _ptr(dag_ptr), _ptr(dag_col), _ptr(sup)))
     return total, sup[: int(dag_ptr[-1])].copy()
