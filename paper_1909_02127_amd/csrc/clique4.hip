@@ -10,7 +10,8 @@
 // time; N+(u) (sorted) sits in LDS when it has at most kLdsKeys ids.  Its four waves take the v round robin.  For each
 // (u, v) a wave streams N+(v), finds each w in N+(u) by binary search, marks
 // w's position in a per-wave bitmap over N+(u) and keeps the positions in a
-// per-wave list; then for each kept w it streams N+(w) and counts the x whose
+// per-wave list; then it walks the N+(w) of 64 kept w at a time as one
+// concatenation (one round trip for their row bounds) and counts the x whose
 // position in N+(u) is marked.  Longer sources keep N+(u) in memory: w and x
 // are then tested by binary search in the sorted rows of u and v, and the
 // kept w go through a bounded list in chunks.
@@ -28,6 +29,7 @@ constexpr int kLdsKeys = 2048;           // N+(u) ids held in LDS
 constexpr int kMarkWords = kLdsKeys / 32;
 constexpr int kListCap = 1024;           // kept w per chunk in the in-memory path
 constexpr int kGrab = 8;                 // sources per claim from the global cursor
+constexpr int32_t kWalkMax = 1 << 24;    // longest N+(w) walked in a concatenation of 64
 
 struct K4State {
   int32_t cursor;
@@ -62,12 +64,15 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
   __shared__ int32_t tkeys[kLdsKeys];
   __shared__ uint32_t marks[kWavesPerBlock][kMarkWords];
   __shared__ int32_t list[kWavesPerBlock][kListCap > kLdsKeys ? kListCap : kLdsKeys];
+  __shared__ int32_t segs[kWavesPerBlock][kWave];
   __shared__ int32_t next_s;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   uint32_t* mk = marks[wave];
   int32_t* lst = list[wave];
+  int32_t* seg = segs[wave];
   for (int w = lane; w < kMarkWords; w += kWave) mk[w] = 0;
+  seg[lane] = -1;
   uint64_t found = 0;
   if (threadIdx.x == 0) next_s = atomicAdd(&st->cursor, 1);
   __syncthreads();
@@ -139,15 +144,55 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             continue;
           }
           wave_sync();
-          // for each kept w: the x in N+(w) whose position in N+(u) is marked
-          for (int32_t a = 0; a < ns; ++a) {
-            const int32_t ww = tkeys[lst[a]];
-            const int64_t wb = row_ptr[ww];
-            const int32_t dw = (int32_t)((int64_t)row_ptr[ww + 1] - wb);
-            for (int32_t xb = 0; xb < dw; xb += kWave) {
+          // The x in N+(w) whose position in N+(u) is marked, for the kept w 64 at a
+          // time: lane a takes w = kept[a0 + a] (one round trip for the row bounds of
+          // all 64), and the wave walks the concatenation of their lists 64 positions
+          // per step.  Each position's list is the last lane whose list starts at or
+          // before it: the starts in the window are marked in LDS and a wave max-scan
+          // carries them forward (the marker array holds -1 between steps).
+          for (int32_t a0 = 0; a0 < ns; a0 += kWave) {
+            int64_t wb = 0;
+            int32_t dw = 0;
+            if (a0 + lane < ns) {
+              const int32_t ww = tkeys[lst[a0 + lane]];
+              wb = row_ptr[ww];
+              dw = (int32_t)((int64_t)row_ptr[ww + 1] - wb);
+            }
+            if (ballot(dw > kWalkMax) != 0) {
+              // a list too long for 32-bit positions in the concatenation: one at a time
+              for (int a = 0; a < kWave && a0 + a < ns; ++a) {
+                const int64_t b1 = read_lane64(wb, a);
+                const int32_t d1 = read_lane(dw, a);
+                for (int32_t xb = 0; xb < d1; xb += kWave) {
+                  bool ok = false;
+                  if (xb + lane < d1) {
+                    const int32_t p = find_pos(tkeys, du, col[b1 + xb + lane]);
+                    ok = p >= 0 && ((mk[p >> 5] >> (p & 31)) & 1u);
+                  }
+                  found += popc(ballot(ok));
+                }
+              }
+              continue;
+            }
+            const int32_t incl = wave_inclusive_sum32(dw);
+            const int32_t start = incl - dw;
+            const int32_t total_x = read_lane(incl, kWave - 1);
+            int32_t carry = -1;
+            for (int32_t base = 0; base < total_x; base += kWave) {
+              const bool marks_here = dw > 0 && start >= base && start < base + kWave;
+              if (marks_here) seg[start - base] = lane;
+              wave_sync();
+              int32_t sk = wave_inclusive_max32(seg[lane]);
+              sk = sk > carry ? sk : carry;
+              carry = read_lane(sk, kWave - 1);
+              wave_sync();
+              if (marks_here) seg[start - base] = -1;
+              const int32_t src = sk < 0 ? 0 : sk;
+              const int32_t off = base + lane - __shfl(start, src, kWave);
+              const int64_t sb = __shfl(wb, src, kWave);
               bool ok = false;
-              if (xb + lane < dw) {
-                const int32_t p = find_pos(tkeys, du, col[wb + xb + lane]);
+              if (base + lane < total_x) {  // then 0 <= off < dw of lane src
+                const int32_t p = find_pos(tkeys, du, col[sb + off]);
                 ok = p >= 0 && ((mk[p >> 5] >> (p & 31)) & 1u);
               }
               found += popc(ballot(ok));
