@@ -63,13 +63,17 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
                                                     uint64_t* __restrict__ total) {
   __shared__ int32_t tkeys[kLdsKeys];
   __shared__ uint32_t marks[kWavesPerBlock][kMarkWords];
-  __shared__ int32_t list[kWavesPerBlock][kListCap > kLdsKeys ? kListCap : kLdsKeys];
+  // per-wave kept list: positions in N+(u) (< kLdsKeys, 16-bit) in the LDS path,
+  // ids of w (32-bit, kListCap per chunk) in the in-memory path; 4 KB either way
+  __shared__ int32_t list[kWavesPerBlock][kListCap];
+  static_assert(kLdsKeys <= 65536 && kLdsKeys * 2 <= kListCap * 4, "kept positions fit the list");
   __shared__ int32_t segs[kWavesPerBlock][kWave];
   __shared__ int32_t next_s;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   uint32_t* mk = marks[wave];
-  int32_t* lst = list[wave];
+  int32_t* lst = list[wave];                                   // in-memory path: ids
+  uint16_t* lpos = reinterpret_cast<uint16_t*>(list[wave]);    // LDS path: positions
   int32_t* seg = segs[wave];
   for (int w = lane; w < kMarkWords; w += kWave) mk[w] = 0;
   seg[lane] = -1;
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             if (pos >= 0) {
               if (in_lds) {
                 atomicOr(&mk[pos >> 5], 1u << (pos & 31));
-                lst[ns + rank_below(hit)] = pos;
+                lpos[ns + rank_below(hit)] = (uint16_t)pos;
               } else {
                 lst[ns + rank_below(hit)] = w;
               }
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
           if (!in_lds || ns < 2) {
             if (in_lds) {
               wave_sync();
-              for (int32_t a = lane; a < ns; a += kWave) mk[lst[a] >> 5] = 0;
+              for (int32_t a = lane; a < ns; a += kWave) mk[lpos[a] >> 5] = 0;
               wave_sync();
             }
             continue;
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             int64_t wb = 0;
             int32_t dw = 0;
             if (a0 + lane < ns) {
-              const int32_t ww = tkeys[lst[a0 + lane]];
+              const int32_t ww = tkeys[lpos[a0 + lane]];
               wb = row_ptr[ww];
               dw = (int32_t)((int64_t)row_ptr[ww + 1] - wb);
             }
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             }
           }
           wave_sync();
-          for (int32_t a = lane; a < ns; a += kWave) mk[lst[a] >> 5] = 0;
+          for (int32_t a = lane; a < ns; a += kWave) mk[lpos[a] >> 5] = 0;
           wave_sync();
         }
       }
