@@ -14,23 +14,26 @@
 // wedge (2-look-ahead) and is never queued; a middle v with d+(v) = 0 adds no
 // work (1-look-ahead).
 //
-// Probe structure: two-choice cuckoo hashing in LDS (two independent
-// multiplicative hashes into two halves of the table, load <= 0.4), so a probe
-// is exactly two LDS reads with no data-dependent loop.  Keys that do not settle
+// Probe structure: two-choice cuckoo hashing in LDS (two bit fields of one
+// multiplicative hash index the two halves of the table, load <= 0.4), so a
+// probe is exactly two LDS reads with no data-dependent loop.  Keys that do not settle
 // within kMaxKicks evictions go to a small stash; if the stash overflows the
 // group falls back to binary search: it refills the (then unused) slot array
 // with N+(u), which is sorted, from global memory.
 //
-// Load balance: sources are binned by d+(u); sources with d+(u) > kSmallMax are
-// handed out largest class first through a global cursor, one workgroup each
-// (its four waves take the v's round robin); the rest are handled one wave each.
+// Load balance: sources are binned by d+(u); sources above the split
+// (tc_tune.small_max, default kSmallDefault, at most kSmallMax) are handed out
+// largest class first through a global cursor, one workgroup each (its four
+// waves take the v's round robin); the rest are handled one wave each, in runs
+// whose source ids and row bounds are loaded together.
 // N+(u) longer than kChunk is processed in kChunk-sized slices of the table.
 //
 // Per-vertex counts: t(u) += hits of source u; t(v) += hits of the edge (u,v)
 // and t(w) += hits closed at w both gather in the LDS slot counters of v and w
 // (when the table holds all of N+(u); split sources add t(v) directly) and are
-// flushed once per source, so global atomics are at most n + 2m rather than
-// one per triangle.
+// flushed once per source; each lane keeps its middle's (u,v) count in a
+// register until the batch of 64 middles is done.  Global atomics are at most
+// n + 2m rather than one per triangle.
 #include "tc_device.h"
 #include "tc_hash.h"
 #include "tc_host.h"
