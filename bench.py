@@ -230,7 +230,7 @@ def make_graph(spec, device):
 
 
 def algorithmic_bytes(dag_ptr, dag_col, n: int, offset_bytes: int, per_vertex: bool) -> dict:
-    """Bytes the count must move at minimum (count kernel roofline):
+    """Bytes the count must move at minimum (the count kernel's roofline unit):
     4 B per enumerated wedge id, 4 B + two row bounds per middle v of a surviving
     source, two row bounds per vertex for binning, 8 B per per-vertex count."""
     import torch
@@ -796,8 +796,8 @@ def main():
             print(summarize_counters(args))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
-              "(the multi-GPU sharding is described in DESIGN.md but not implemented)",
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path "
+              "runs on one GPU; sharding it over several is not implemented)",
               file=sys.stderr)
         sys.exit(2)
     import torch
