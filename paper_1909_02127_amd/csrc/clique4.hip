@@ -7,13 +7,13 @@
 // d+(v) >= 2, a third node d+(w) >= 1.
 //
 // A workgroup takes runs of kGrab sources from a global cursor, one source at a
-// time; N+(u) (sorted) sits in LDS when it has at most kLdsKeys ids.  Its four waves take the v round robin.  For each
-// (u, v) a wave streams N+(v), finds each w in N+(u) by binary search, marks
-// w's position in a per-wave bitmap over N+(u) and keeps the positions in a
-// per-wave list; then it walks the N+(w) of 64 kept w at a time as one
-// concatenation (one round trip for their row bounds) and counts the x whose
-// position in N+(u) is marked.  Longer sources keep N+(u) in memory: w and x
-// are then tested by binary search in the sorted rows of u and v, and the
+// time; N+(u) (sorted) sits in LDS when it has at most kLdsKeys ids.  Its four
+// waves take the v round robin.  For each (u, v) a wave streams N+(v), finds
+// each w in N+(u) by binary search and keeps its position in a per-wave list
+// (S = the kept w, ascending); then it walks the N+(w) of 64 kept w at a time as
+// one concatenation (one round trip for their row bounds) and counts the x that
+// are in S, by binary search in S.  Longer sources keep N+(u) in memory: w and
+// x are then tested by binary search in the sorted rows of u and v, and the
 // kept w go through a bounded list in chunks.
 #include "tc_device.h"
 #include "tc_host.h"
@@ -26,7 +26,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLdsKeys = 2048;           // N+(u) ids held in LDS
-constexpr int kMarkWords = kLdsKeys / 32;
 constexpr int kListCap = 1024;           // kept w per chunk in the in-memory path
 constexpr int kGrab = 8;                 // sources per claim from the global cursor
 constexpr int32_t kWalkMax = 1 << 24;    // longest N+(w) walked in a concatenation of 64
@@ -56,13 +55,29 @@ __device__ __forceinline__ int32_t find_pos(const int32_t* keys, int32_t n, int3
   return lo < n && keys[lo] == w ? lo : -1;
 }
 
+// Whether x is one of the kept w: keys tkeys[lpos[0..ns)], ascending (the kept
+// positions are appended in list order and N+(u), N+(v) are sorted).
+__device__ __forceinline__ bool in_kept(const int32_t* tkeys, const uint16_t* lpos, int32_t ns,
+                                        int32_t x) {
+  int32_t lo = 0, len = ns;
+  while (len > 0) {
+    const int32_t half = len >> 1;
+    if (tkeys[lpos[lo + half]] < x) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo < ns && tkeys[lpos[lo]] == x;
+}
+
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col,
                                                     K4State* __restrict__ st,
                                                     uint64_t* __restrict__ total) {
   __shared__ int32_t tkeys[kLdsKeys];
-  __shared__ uint32_t marks[kWavesPerBlock][kMarkWords];
   // per-wave kept list: positions in N+(u) (< kLdsKeys, 16-bit) in the LDS path,
   // ids of w (32-bit, kListCap per chunk) in the in-memory path; 4 KB either way
   __shared__ int32_t list[kWavesPerBlock][kListCap];
@@ -71,11 +86,9 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
   __shared__ int32_t next_s;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
-  uint32_t* mk = marks[wave];
   int32_t* lst = list[wave];                                   // in-memory path: ids
   uint16_t* lpos = reinterpret_cast<uint16_t*>(list[wave]);    // LDS path: positions
   int32_t* seg = segs[wave];
-  for (int w = lane; w < kMarkWords; w += kWave) mk[w] = 0;
   seg[lane] = -1;
   uint64_t found = 0;
   if (threadIdx.x == 0) next_s = atomicAdd(&st->cursor, 1);
@@ -110,7 +123,6 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             const uint64_t hit = ballot(pos >= 0);
             if (pos >= 0) {
               if (in_lds) {
-                atomicOr(&mk[pos >> 5], 1u << (pos & 31));
                 lpos[ns + rank_below(hit)] = (uint16_t)pos;
               } else {
                 lst[ns + rank_below(hit)] = w;
@@ -139,16 +151,9 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
               ns = 0;
             }
           }
-          if (!in_lds || ns < 2) {
-            if (in_lds) {
-              wave_sync();
-              for (int32_t a = lane; a < ns; a += kWave) mk[lpos[a] >> 5] = 0;
-              wave_sync();
-            }
-            continue;
-          }
+          if (!in_lds || ns < 2) continue;
           wave_sync();
-          // The x in N+(w) whose position in N+(u) is marked, for the kept w 64 at a
+          // The x in N+(w) that are kept w themselves, for the kept w 64 at a
           // time: lane a takes w = kept[a0 + a] (one round trip for the row bounds of
           // all 64), and the wave walks the concatenation of their lists 64 positions
           // per step.  Each position's list is the last lane whose list starts at or
@@ -169,10 +174,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
                 const int32_t d1 = read_lane(dw, a);
                 for (int32_t xb = 0; xb < d1; xb += kWave) {
                   bool ok = false;
-                  if (xb + lane < d1) {
-                    const int32_t p = find_pos(tkeys, du, col[b1 + xb + lane]);
-                    ok = p >= 0 && ((mk[p >> 5] >> (p & 31)) & 1u);
-                  }
+                  if (xb + lane < d1) ok = in_kept(tkeys, lpos, ns, col[b1 + xb + lane]);
                   found += popc(ballot(ok));
                 }
               }
@@ -195,16 +197,12 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
               const int32_t off = base + lane - __shfl(start, src, kWave);
               const int64_t sb = __shfl(wb, src, kWave);
               bool ok = false;
-              if (base + lane < total_x) {  // then 0 <= off < dw of lane src
-                const int32_t p = find_pos(tkeys, du, col[sb + off]);
-                ok = p >= 0 && ((mk[p >> 5] >> (p & 31)) & 1u);
-              }
+              if (base + lane < total_x)  // then 0 <= off < dw of lane src
+                ok = in_kept(tkeys, lpos, ns, col[sb + off]);
               found += popc(ballot(ok));
             }
           }
-          wave_sync();
-          for (int32_t a = lane; a < ns; a += kWave) mk[lpos[a] >> 5] = 0;
-          wave_sync();
+          wave_sync();  // the list is rewritten by this wave's next middle
         }
       }
       __syncthreads();
