@@ -16,6 +16,7 @@
 // x are then tested by binary search in the sorted rows of u and v, and the
 // kept w go through a bounded list in chunks.
 #include "tc_device.h"
+#include "tc_hash.h"
 #include "tc_host.h"
 
 #include <algorithm>
@@ -29,6 +30,18 @@ constexpr int kLdsKeys = 2048;           // N+(u) ids held in LDS
 constexpr int kListCap = 1024;           // kept w per chunk in the in-memory path
 constexpr int kGrab = 8;                 // sources per claim from the global cursor
 constexpr int32_t kWalkMax = 1 << 24;    // longest N+(w) walked in a concatenation of 64
+constexpr int kHashKeys = 816;           // d+(u) up to which N+(u) goes into an LDS cuckoo table
+constexpr int kMaxKicks = 48;
+static_assert(kHashKeys <= kListCap, "a hashed source's kept w fit the per-wave list");
+
+// log2 of the slots per half for `keys` keys: load <= 0.4 over both halves.
+__host__ __device__ constexpr int k4_side_log2(int keys) {
+  const int want = keys + (keys >> 2) + 1;
+  int b = 4;
+  while ((1 << b) < want) ++b;
+  return b;
+}
+static_assert(2 * (1 << k4_side_log2(kHashKeys)) <= kLdsKeys, "the table fits the key array");
 
 struct K4State {
   int32_t cursor;
@@ -84,6 +97,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
   static_assert(kLdsKeys <= 65536 && kLdsKeys * 2 <= kListCap * 4, "kept positions fit the list");
   __shared__ int32_t segs[kWavesPerBlock][kWave];
   __shared__ int32_t next_s;
+  __shared__ int32_t kfail;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   int32_t* lst = list[wave];                                   // in-memory path: ids
@@ -101,12 +115,37 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
       const int32_t du = (int32_t)((int64_t)row_ptr[u + 1] - ub);
       const bool in_lds = du <= kLdsKeys;
       if (du >= 3) {
-        if (in_lds)
-          for (int i = threadIdx.x; i < du; i += kBlock) tkeys[i] = col[ub + i];
-        __syncthreads();
         const int32_t* urow = col + ub;
+        // N+(u) up to kHashKeys ids goes into a two-choice cuckoo table (tc_hash.h's
+        // hashes, two halves of `side` slots in tkeys); longer rows, or a table whose
+        // insertion fails, are copied sorted for binary search
+        bool hashed = du <= kHashKeys;
+        const int b = k4_side_log2(du);
+        const int side = 1 << b, shift = 32 - b;
+        if (hashed) {
+          for (int i = threadIdx.x; i < 2 * side; i += kBlock) tkeys[i] = -1;
+          if (threadIdx.x == 0) kfail = 0;
+          __syncthreads();
+          for (int i = threadIdx.x; i < du; i += kBlock) {
+            int32_t cur = urow[i];
+            int hs = 0;
+            for (int kick = 0; kick < kMaxKicks && cur != -1; ++kick) {
+              const uint32_t sl = hs ? (uint32_t)side + hash_b<true>(cur, shift)
+                                     : hash_a<true>(cur, shift);
+              cur = atomicExch(&tkeys[sl], cur);
+              hs ^= 1;
+            }
+            if (cur != -1) kfail = 1;
+          }
+          __syncthreads();
+          hashed = kfail == 0;
+          __syncthreads();
+        }
+        if (in_lds && !hashed)
+          for (int i = threadIdx.x; i < du; i += kBlock) tkeys[i] = urow[i];
+        __syncthreads();
         for (int32_t iv = wave; iv < du; iv += kWavesPerBlock) {
-          const int32_t v = in_lds ? tkeys[iv] : urow[iv];
+          const int32_t v = (in_lds && !hashed) ? tkeys[iv] : urow[iv];
           const int64_t vb = row_ptr[v];
           const int32_t dv = (int32_t)((int64_t)row_ptr[v + 1] - vb);
           if (dv < 2) continue;
@@ -118,14 +157,20 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             int32_t w = 0;
             if (j < dv) {
               w = col[vb + j];
-              pos = in_lds ? find_pos(tkeys, du, w) : find_pos(urow, du, w);
+              if (hashed) {
+                const uint32_t hp = hash_product(hash_input<true>(w));
+                pos = (tkeys[slot_a_of(hp, shift)] == w ||
+                       tkeys[(uint32_t)side + slot_b_of(hp, shift)] == w) ? 0 : -1;
+              } else {
+                pos = in_lds ? find_pos(tkeys, du, w) : find_pos(urow, du, w);
+              }
             }
             const uint64_t hit = ballot(pos >= 0);
             if (pos >= 0) {
-              if (in_lds) {
+              if (in_lds && !hashed) {
                 lpos[ns + rank_below(hit)] = (uint16_t)pos;
               } else {
-                lst[ns + rank_below(hit)] = w;
+                lst[ns + rank_below(hit)] = w;  // hashed: S as ascending ids
               }
             }
             ns += popc(hit);
@@ -163,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             int64_t wb = 0;
             int32_t dw = 0;
             if (a0 + lane < ns) {
-              const int32_t ww = tkeys[lpos[a0 + lane]];
+              const int32_t ww = hashed ? lst[a0 + lane] : tkeys[lpos[a0 + lane]];
               wb = row_ptr[ww];
               dw = (int32_t)((int64_t)row_ptr[ww + 1] - wb);
             }
@@ -174,7 +219,10 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
                 const int32_t d1 = read_lane(dw, a);
                 for (int32_t xb = 0; xb < d1; xb += kWave) {
                   bool ok = false;
-                  if (xb + lane < d1) ok = in_kept(tkeys, lpos, ns, col[b1 + xb + lane]);
+                  if (xb + lane < d1) {
+                    const int32_t x = col[b1 + xb + lane];
+                    ok = hashed ? find_pos(lst, ns, x) >= 0 : in_kept(tkeys, lpos, ns, x);
+                  }
                   found += popc(ballot(ok));
                 }
               }
@@ -197,8 +245,10 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
               const int32_t off = base + lane - __shfl(start, src, kWave);
               const int64_t sb = __shfl(wb, src, kWave);
               bool ok = false;
-              if (base + lane < total_x)  // then 0 <= off < dw of lane src
-                ok = in_kept(tkeys, lpos, ns, col[sb + off]);
+              if (base + lane < total_x) {  // then 0 <= off < dw of lane src
+                const int32_t x = col[sb + off];
+                ok = hashed ? find_pos(lst, ns, x) >= 0 : in_kept(tkeys, lpos, ns, x);
+              }
               found += popc(ballot(ok));
             }
           }
