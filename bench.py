@@ -101,6 +101,11 @@ def counter_traffic(workload: str):
     return rec.get("traffic_bytes_per_launch")
 
 
+def _profile_kernel(workload: str) -> str:
+    """The dominant kernel a workload's profile summaries are named for."""
+    return "k4_kernel" if WORKLOADS[workload]["kind"] == "k4" else "count_kernel"
+
+
 def _short_kernel_name(name: str) -> str:
     import re
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
@@ -135,7 +140,8 @@ def summarize_trace(args) -> str:
         lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:11.2f} "
                      f"{float(r['MinNs']) / 1e3:11.2f} {float(r['MaxNs']) / 1e3:11.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f}  {name}")
-    out = os.path.join(ROOT, "profiles", f"count_kernel_{args.workload}_kernel_trace.txt")
+    out = os.path.join(ROOT, "profiles",
+                       f"{_profile_kernel(args.workload)}_{args.workload}_kernel_trace.txt")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     return out
@@ -170,7 +176,8 @@ def summarize_counters(args) -> str:
             tot = cs["TCC_HIT_sum"] + cs["TCC_MISS_sum"]
             if tot:
                 lines.append(f"    {'L2 hit rate':28s} {cs['TCC_HIT_sum'] / tot:20.3f}")
-    out = os.path.join(ROOT, "profiles", f"count_kernel_{args.workload}_counters.txt")
+    out = os.path.join(ROOT, "profiles",
+                       f"{_profile_kernel(args.workload)}_{args.workload}_counters.txt")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     return out

@@ -102,3 +102,34 @@ def test_k4_empty_and_small(tc):
     for n, s, d in [(0, [], []), (1, [], []), (3, [0, 1, 2], [1, 2, 0]), (4, [0, 0, 0, 1, 1, 2],
                                                                          [1, 2, 3, 2, 3, 3])]:
         _check(tc, n, s, d)
+
+
+def _colliding_ids(count: int, bits: int = 4) -> list[int]:
+    """`count` ids below 2^24 whose 24-bit product with the table multiplier agrees in
+    its top 2 * bits bits: in a table with 2^bits slots per half they all share one
+    slot pair, so a cuckoo insertion of three of them cannot succeed."""
+    buckets: dict[int, list[int]] = {}
+    for x in range(1 << 20, 1 << 24):
+        key = ((x * 0x9E3779) & 0xFFFFFFFF) >> (32 - 2 * bits)
+        buckets.setdefault(key, []).append(x)
+        if len(buckets[key]) == count:
+            return buckets[key]
+    raise AssertionError("no colliding ids found")
+
+
+def test_k4_hash_insertion_failure_falls_back(tc):
+    """A source whose out-neighbours all share one slot pair overflows the cuckoo table;
+    the kernel must fall back to the sorted copy and still count exactly."""
+    xs = _colliding_ids(3)
+    _say("colliding ids", xs)
+    # K4 on {0} + xs (vertex 0 is the lowest rank: all degrees equal, ties by id), plus a
+    # K5 elsewhere so the graph also has ordinary sources
+    verts = [0] + xs
+    s = [a for i, a in enumerate(verts) for b in verts[i + 1:]]
+    d = [b for i, a in enumerate(verts) for b in verts[i + 1:]]
+    k5 = list(range(10, 15))
+    s += [a for i, a in enumerate(k5) for b in k5[i + 1:]]
+    d += [b for i, a in enumerate(k5) for b in k5[i + 1:]]
+    n = max(xs) + 1
+    got = _gpu_k4(tc, n, s, d)
+    assert got == oracle.k4(n, np.asarray(s), np.asarray(d)) == 1 + 5
