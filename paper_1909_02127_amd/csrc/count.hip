@@ -538,6 +538,8 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
   const int32_t incl = wave_inclusive_sum32(len);
   const int32_t start = incl - len;
   const int32_t total = read_lane(incl, kWave - 1);
+  // walk position pos of this lane's list is col[pos + delta]
+  const OffT delta = vb - (OffT)start;
   if (CNT) ws.shits[lane] = 0;
   int32_t carry = -1;
   uint32_t hv = 0;
@@ -562,12 +564,10 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
       const int32_t pos = base + k * kWave + lane;
       const int32_t sk = seg[k] < 0 ? 0 : seg[k];
       mid[k] = K == kKindList ? __shfl(v, sk, kWave) : 0;
-      const int32_t off = pos - __shfl(start, sk, kWave);
-      const int32_t slen = __shfl(len, sk, kWave);
-      const OffT sb = __shfl(vb, sk, kWave);
-      at[k] = (int64_t)sb + off;
-      // pos < total implies 0 <= off < slen; the check also keeps every read in bounds
-      w[k] = (pos < total && (uint32_t)off < (uint32_t)slen) ? col[sb + off] : kNoKey;
+      // the segment's list is the last non-empty one starting at or before pos,
+      // so for pos < total, start(sk) <= pos < start(sk) + len(sk)
+      at[k] = (int64_t)pos + (int64_t)__shfl(delta, sk, kWave);
+      w[k] = pos < total ? col[at[k]] : kNoKey;
     }
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {

@@ -69,24 +69,35 @@ __device__ __forceinline__ int64_t wave_inclusive_sum(int64_t x) {
   return x;
 }
 
-__device__ __forceinline__ int32_t wave_inclusive_sum32(int32_t x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    int32_t y = __shfl_up(x, off, kWave);
-    if (lane >= off) x += y;
-  }
+// 32-bit inclusive wave scans on DPP lane moves, which need no LDS round trip
+// (a shuffle is a ds_bpermute).  Kogge-Stone inside each row of 16 lanes
+// (row_shr 1, 2, 4, 8), then row_bcast:15 carries row 0 into row 1 and row 2
+// into row 3, and row_bcast:31 carries lanes 0-31 into rows 2 and 3.  A lane
+// whose source lies outside its row, or that the row mask leaves out, gets the
+// identity (bound_ctrl off: the destination keeps `old`).  Called by the whole
+// wave.
+namespace dpp {
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+}  // namespace dpp
+
+template <typename Op>
+__device__ __forceinline__ int32_t wave_inclusive_scan32(int32_t x, int32_t identity, Op op) {
+  x = op(x, __builtin_amdgcn_update_dpp(identity, x, dpp::kRowShr1, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(identity, x, dpp::kRowShr2, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(identity, x, dpp::kRowShr4, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(identity, x, dpp::kRowShr8, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(identity, x, dpp::kRowBcast15, 0xa, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(identity, x, dpp::kRowBcast31, 0xc, 0xf, false));
   return x;
 }
 
+__device__ __forceinline__ int32_t wave_inclusive_sum32(int32_t x) {
+  return wave_inclusive_scan32(x, 0, [](int32_t a, int32_t b) { return a + b; });
+}
+
 __device__ __forceinline__ int32_t wave_inclusive_max32(int32_t x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    int32_t y = __shfl_up(x, off, kWave);
-    if (lane >= off) x = x > y ? x : y;
-  }
-  return x;
+  return wave_inclusive_scan32(x, INT32_MIN, [](int32_t a, int32_t b) { return a > b ? a : b; });
 }
 
 __device__ __forceinline__ int64_t wave_sum(int64_t x) {
