@@ -231,6 +231,9 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             const int32_t incl = wave_inclusive_sum32(dw);
             const int32_t start = incl - dw;
             const int32_t total_x = read_lane(incl, kWave - 1);
+            // walk position pos of lane a's list is col[pos + delta(a)]; with 32-bit
+            // offsets wb < 2^31 and start <= total_x < 2^31, so delta fits OffT
+            const OffT delta = (OffT)(wb - start);
             int32_t carry = -1;
             for (int32_t base = 0; base < total_x; base += kWave) {
               const bool marks_here = dw > 0 && start >= base && start < base + kWave;
@@ -242,11 +245,10 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
               wave_sync();
               if (marks_here) seg[start - base] = -1;
               const int32_t src = sk < 0 ? 0 : sk;
-              const int32_t off = base + lane - __shfl(start, src, kWave);
-              const int64_t sb = __shfl(wb, src, kWave);
+              const int64_t at = (int64_t)(base + lane) + (int64_t)__shfl(delta, src, kWave);
               bool ok = false;
-              if (base + lane < total_x) {  // then 0 <= off < dw of lane src
-                const int32_t x = col[sb + off];
+              if (base + lane < total_x) {  // then start(src) <= base + lane < start(src) + dw(src)
+                const int32_t x = col[at];
                 ok = hashed ? find_pos(lst, ns, x) >= 0 : in_kept(tkeys, lpos, ns, x);
               }
               found += popc(ballot(ok));
