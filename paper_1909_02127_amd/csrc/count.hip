@@ -384,7 +384,7 @@ __device__ __forceinline__ void emit(const ListCtx& c, uint64_t hits, int32_t v,
   if (!hits) return;
   int32_t start = 0;
   if (lane_id() == 0) start = atomicAdd(c.cursor, (int32_t)popc(hits));
-  start = __shfl(start, 0, kWave);
+  start = read_lane(start, 0);  // a scalar read, no LDS round trip
   if ((hits >> lane_id()) & 1u) {
     const int64_t row = c.base + start + rank_below(hits);
     if (row < c.cap) {
