@@ -203,12 +203,7 @@ __global__ __launch_bounds__(kRadixBlock) void radix_scatter_kernel(
     tot += c;
   }
   {
-    uint32_t x = tot;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t y = __shfl_up(x, off, kWave);
-      if (lane >= off) x += y;
-    }
+    const uint32_t x = (uint32_t)wave_inclusive_sum32((int32_t)tot);  // tot <= kRadixTile
     if (lane == kWave - 1) wave_tot[wave] = x;
     __syncthreads();
     uint32_t before = 0;
@@ -248,6 +243,18 @@ constexpr int kDedupItems = 16;
 constexpr int kDedupRun = kDedupItems * kWave;
 constexpr int64_t kDedupTile = (int64_t)kDedupBlock * kDedupItems;
 
+// Lane l gets x of lane l - 1 and lane 0 gets `first`: a whole-wave DPP shift
+// (wave_shr:1, control 0x138) on each 32-bit half, with no LDS round trip.  A
+// lane without a source keeps `old` (bound_ctrl off).  Called by the whole wave.
+__device__ __forceinline__ uint64_t wave_shift_up1_u64(uint64_t x, uint64_t first) {
+  constexpr int kWaveShr1 = 0x138;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(
+      (int)(uint32_t)first, (int)(uint32_t)x, kWaveShr1, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+      (int)(uint32_t)(first >> 32), (int)(uint32_t)(x >> 32), kWaveShr1, 0xf, 0xf, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Loads the wave's run and returns the kept-key mask of every round.
 __device__ __forceinline__ void dedup_load(const uint64_t* __restrict__ keys, int64_t nk,
                                            int64_t base, uint64_t (&k)[kDedupItems],
@@ -263,11 +270,10 @@ __device__ __forceinline__ void dedup_load(const uint64_t* __restrict__ keys, in
   const bool first_key = base == 0;
 #pragma unroll
   for (int r = 0; r < kDedupItems; ++r) {
-    uint64_t p = __shfl_up(k[r], 1, kWave);
-    if (lane == 0) p = prev;
+    const uint64_t p = wave_shift_up1_u64(k[r], prev);
     const bool head = r == 0 && lane == 0 && first_key;
     keep[r] = ballot(k[r] != kSentinel && (head || p != k[r]));
-    prev = __shfl(k[r], kWave - 1, kWave);
+    prev = (uint64_t)read_lane64((int64_t)k[r], kWave - 1);
   }
 }
 
@@ -319,15 +325,14 @@ __global__ __launch_bounds__(kDedupBlock) void dedup_write_kernel(
 #pragma unroll
   for (int r = 0; r < kDedupItems; ++r) {
     const uint64_t row = k[r] >> cb;
-    uint64_t p = __shfl_up(row, 1, kWave);
-    if (lane == 0) p = prev_row;
+    const uint64_t p = wave_shift_up1_u64(row, prev_row);
     if ((keep[r] >> lane) & 1u) {
       const int64_t at = pos + rank_below(keep[r]);
       if (at < cap) col[at] = (int32_t)(k[r] & id_mask);
       if (p != row) start[row] = at;
     }
     pos += popc(keep[r]);
-    prev_row = __shfl(row, kWave - 1, kWave);
+    prev_row = (uint64_t)read_lane64((int64_t)row, kWave - 1);
   }
 }
 
