@@ -28,15 +28,39 @@ inline int64_t scan_num_tiles(int64_t len) { return (len + kScanTile - 1) / kSca
 // int64 entries the caller must provide as `partial` for a scan of `len` values.
 inline int64_t scan_partial_len(int64_t len) { return scan_num_tiles(len) + 1; }
 
+// A 64-bit DPP lane move (two 32-bit moves): lanes without a source under
+// control Ctrl, or outside RowMask, get `old` (bound_ctrl off).
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ int64_t dpp_move64(int64_t old, int64_t x) {
+  const uint64_t o = (uint64_t)old, v = (uint64_t)x;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v,
+                                                            Ctrl, RowMask, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+      (int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32), Ctrl, RowMask, 0xf, false);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive wave scan on DPP moves (no LDS round trips): Kogge-Stone inside
+// each row of 16 lanes, then row_bcast:15 and row_bcast:31 carry the row
+// prefixes across rows.  Called by the whole wave.
 template <class Op>
 __device__ __forceinline__ int64_t wave_inclusive(int64_t x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    int64_t y = __shfl_up(x, off, kWave);
-    if (lane >= off) x = Op::apply(y, x);
-  }
+  const int64_t id = Op::identity();
+  x = Op::apply(dpp_move64<dpp::kRowShr1, 0xf>(id, x), x);
+  x = Op::apply(dpp_move64<dpp::kRowShr2, 0xf>(id, x), x);
+  x = Op::apply(dpp_move64<dpp::kRowShr4, 0xf>(id, x), x);
+  x = Op::apply(dpp_move64<dpp::kRowShr8, 0xf>(id, x), x);
+  x = Op::apply(dpp_move64<dpp::kRowBcast15, 0xa>(id, x), x);
+  x = Op::apply(dpp_move64<dpp::kRowBcast31, 0xc>(id, x), x);
   return x;
+}
+
+// The value of lane l - 1 (lane 0: the identity), by a whole-wave DPP shift
+// (wave_shr:1).  Called by the whole wave.
+template <class Op>
+__device__ __forceinline__ int64_t wave_exclusive_from_inclusive(int64_t inc) {
+  constexpr int kWaveShr1 = 0x138;
+  return dpp_move64<kWaveShr1, 0xf>(Op::identity(), inc);
 }
 
 // Combination of one value per lane across the wave (every lane gets it).
@@ -100,8 +124,7 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(int64_t num, int64_
       if (w < wave) before = Op::apply(before, wave_tot[w]);
       all = Op::apply(all, wave_tot[w]);
     }
-    int64_t exc = __shfl_up(inc, 1, kWave);
-    if (lane == 0) exc = Op::identity();
+    const int64_t exc = wave_exclusive_from_inclusive<Op>(inc);
     int64_t run = Op::apply(before, exc);
 #pragma unroll
     for (int k = 0; k < kPartialItems; ++k) {
@@ -138,10 +161,9 @@ __global__ __launch_bounds__(kScanBlock) void scan_down_kernel(int64_t len, Load
   for (int r = 0; r < kScanItems; ++r) {
     const int64_t i = base + (int64_t)r * kWave + lane;
     const int64_t inc = wave_inclusive<Op>(x[r]);
-    int64_t exc = __shfl_up(inc, 1, kWave);
-    if (lane == 0) exc = Op::identity();
+    const int64_t exc = wave_exclusive_from_inclusive<Op>(inc);
     if (i < len) store(i, Op::apply(carry, exc));
-    carry = Op::apply(carry, __shfl(inc, kWave - 1, kWave));
+    carry = Op::apply(carry, read_lane64(inc, kWave - 1));
   }
 }
 
