@@ -110,3 +110,29 @@ def test_pmc_summary_scales_by_the_calibration_copy(fake_root, monkeypatch):
     assert rec["count_total_only"]["traffic_bytes_per_launch"] == pytest.approx(
         6000.0 * 1024 * 2 + 2.0 * 1024)
     assert rec["traffic_bytes_per_launch"] == pv["traffic_bytes_per_launch"]
+
+
+def _profile_commands(path):
+    if path.endswith(".json"):
+        with open(path) as f:
+            return json.load(f)["commands"]
+    with open(path) as f:
+        return [ln[1:].strip() for ln in f
+                if ln.startswith("#") and ln[1:].strip().startswith("rocprofv3 -")]
+
+
+def test_committed_profiles_name_commands_that_run_committed_files():
+    prof = os.path.join(ROOT, "profiles")
+    files = sorted(os.listdir(prof))
+    assert any(f.endswith("_kernel_trace.txt") for f in files)
+    for name in files:
+        cmds = _profile_commands(os.path.join(prof, name))
+        assert cmds, name
+        for c in cmds:
+            prog = c.split(" -- ", 1)[1].split()
+            # the program follows the profiler directly and is the committed benchmark
+            assert prog[0] == "python3" and "bench.py" in prog, (name, c)
+            assert os.path.exists(os.path.join(ROOT, "bench.py"))
+            workload = prog[prog.index("--workload") + 1]
+            assert workload in bench.WORKLOADS, (name, workload)
+            assert workload in name, (name, workload)
