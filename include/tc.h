@@ -91,7 +91,11 @@ typedef struct tc_tune {
   int32_t probe;         /* TC_PROBE_AUTO or TC_PROBE_SORTED */
   int32_t blocks_per_cu; /* persistent grid = blocks_per_cu x compute units, capped at the
                             occupancy limit; 0 = occupancy limit */
-  int32_t reserved;      /* must be 0 */
+  int32_t max_kicks;     /* cuckoo placements per key before it goes to the stash
+                            (the stash holds 32 keys; past it the slice is binary
+                            searched instead): 0 = default (48), 1 to 1024 = that many,
+                            -1 = none, so every key takes the stash or the sorted
+                            fallback (exercises those probe modes) */
 } tc_tune;
 
 /* Read-only view of a CSR graph in device memory. */

@@ -42,15 +42,16 @@ class tc_csr(ctypes.Structure):
 
 class tc_tune(ctypes.Structure):
     _fields_ = [("small_max", ctypes.c_int32), ("probe", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("max_kicks", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"small_max": self.small_max, "probe": self.probe,
-                "blocks_per_cu": self.blocks_per_cu}
+                "blocks_per_cu": self.blocks_per_cu, "max_kicks": self.max_kicks}
 
 
-def make_tune(small_max: int = 0, probe: int = TC_PROBE_AUTO, blocks_per_cu: int = 0) -> tc_tune:
-    return tc_tune(small_max, probe, blocks_per_cu, 0)
+def make_tune(small_max: int = 0, probe: int = TC_PROBE_AUTO, blocks_per_cu: int = 0,
+              max_kicks: int = 0) -> tc_tune:
+    return tc_tune(small_max, probe, blocks_per_cu, max_kicks)
 
 
 def _tune_ref(tune):

@@ -39,9 +39,8 @@
 #include "tc_host.h"
 #include "tc_scan.h"
 
-#include <stdlib.h>
-
 #include <algorithm>
+#include <atomic>
 
 namespace tc {
 namespace {
@@ -964,14 +963,18 @@ struct Tune {
   int small_max;
   int force_sorted;
   int blocks_per_cu;  // 0: occupancy limit
+  int max_kicks;      // cuckoo placements per key before the stash
 };
 
 tc_status read_tune(const tc_tune* tune, Tune* out) {
   out->small_max = kSmallDefault;
   out->force_sorted = 0;
   out->blocks_per_cu = 0;
+  out->max_kicks = kMaxKicks;
   if (!tune) return TC_OK;
-  if (tune->reserved != 0) return fail(TC_ERR_INVALID_ARG, "tc_tune.reserved must be 0");
+  if (tune->max_kicks < -1 || tune->max_kicks > 1024)
+    return fail(TC_ERR_INVALID_ARG, "tc_tune.max_kicks must be in [-1, 1024]");
+  if (tune->max_kicks != 0) out->max_kicks = tune->max_kicks < 0 ? 0 : tune->max_kicks;
   if (tune->small_max != 0) {
     if (tune->small_max < 1 || tune->small_max > kSmallMax)
       return fail(TC_ERR_INVALID_ARG, "tc_tune.small_max must be 0 or in [1, %d]", kSmallMax);
@@ -986,22 +989,25 @@ tc_status read_tune(const tc_tune* tune, Tune* out) {
   return TC_OK;
 }
 
+// Persistent grid of a count kernel instantiation: resident workgroups per CU
+// (queried once per device; concurrent first calls store the same value, and
+// the per-device slots are atomics so those stores do not race) x CUs.
 template <int K, bool Wide, typename OffT>
 int count_grid(int blocks_per_cu) {
-  static int cached[64] = {0};
+  static std::atomic<int> cached[64];
   int dev = 0;
   (void)hipGetDevice(&dev);
   if (dev < 0 || dev >= 64) dev = 0;
-  if (cached[dev] == 0) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_kernel<K, Wide, OffT>, kBlock, 0) !=
+  int occ = cached[dev].load(std::memory_order_relaxed);
+  if (occ == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, count_kernel<K, Wide, OffT>, kBlock, 0) !=
             hipSuccess ||
-        per_cu <= 0) {
-      per_cu = 2;
+        occ <= 0) {
+      occ = 2;
     }
-    cached[dev] = per_cu;
+    cached[dev].store(occ, std::memory_order_relaxed);
   }
-  const int per_cu = blocks_per_cu > 0 && blocks_per_cu < cached[dev] ? blocks_per_cu : cached[dev];
+  const int per_cu = blocks_per_cu > 0 && blocks_per_cu < occ ? blocks_per_cu : occ;
   return per_cu * device_cu_count();
 }
 
@@ -1013,10 +1019,7 @@ CountArgs base_args(const Tune& tune) {
   args.list_status = nullptr;
   args.list = ListArgs{nullptr, nullptr, 0, nullptr};
   args.force_sorted = tune.force_sorted;
-  // Test hook: TC_TEST_MAX_KICKS caps cuckoo evictions so that tests can drive
-  // keys into the stash (and past it, into the sorted fallback).
-  args.max_kicks = kMaxKicks;
-  if (const char* env = getenv("TC_TEST_MAX_KICKS")) args.max_kicks = atoi(env);
+  args.max_kicks = tune.max_kicks;
   return args;
 }
 

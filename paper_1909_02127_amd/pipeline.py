@@ -28,11 +28,14 @@ class Result:
 
 
 class Pipeline:
-    """Preallocated buffers for graphs with up to `num_pairs` raw pairs on `n` vertices."""
+    """Preallocated buffers for graphs with up to `num_pairs` raw pairs on `n` vertices.
+    `tune` (a tc_tune dict or struct) is the default launch configuration of the count
+    calls."""
 
     def __init__(self, n: int, num_pairs: int, *, offset_bytes: int = 4,
-                 order: int = TC_ORDER_DEGREE, device="cuda"):
+                 order: int = TC_ORDER_DEGREE, device="cuda", tune=None):
         self.n, self.num_pairs, self.order = int(n), int(num_pairs), order
+        self.tune = tune
         self.device = torch.device(device)
         odt = torch.int32 if offset_bytes == 4 else torch.int64
         dev = self.device
@@ -67,10 +70,12 @@ class Pipeline:
                        self.m, self.ws_orient, stream=stream)
 
     def count(self, stream=None, tune=None) -> None:
+        tune = self.tune if tune is None else tune
         _lib.tc_count(self.n, self.dag_ptr, self.dag_col, self.total, self.ws_count, tune=tune,
                       stream=stream)
 
     def count_per_vertex(self, stream=None, tune=None) -> None:
+        tune = self.tune if tune is None else tune
         pv = self.per_vertex[: self.n]
         _lib.tc_count_per_vertex(self.n, self.dag_ptr, self.dag_col, pv, self.total,
                                  self.ws_count, tune=tune, stream=stream)
@@ -79,6 +84,7 @@ class Pipeline:
         """Enqueue tc_list_triangles on the current DAG into a (capacity, 3) buffer that is
         kept across calls (grown when a larger capacity is asked for)."""
         capacity = int(capacity)
+        tune = self.tune if tune is None else tune
         if self.triples is None or self.triples.shape[0] < capacity:
             self.triples = torch.empty((max(capacity, 1), 3), dtype=torch.int32,
                                        device=self.device)
@@ -89,6 +95,7 @@ class Pipeline:
 
     def edge_support(self, stream=None, tune=None) -> None:
         """Enqueue tc_edge_support on the current DAG (one uint32 count per DAG edge)."""
+        tune = self.tune if tune is None else tune
         if self.support is None:
             self.support = torch.empty(self.dag_col.numel(), dtype=torch.int32, device=self.device)
             self.ws_support = _bytes(_lib.tc_edge_support_workspace(self.n), self.device)
@@ -134,8 +141,9 @@ class Pipeline:
 
 
 def triangle_count(src: torch.Tensor, dst: torch.Tensor, n: int, *, per_vertex: bool = False,
-                   order: int = TC_ORDER_DEGREE, offset_bytes: int = 4) -> Result:
+                   order: int = TC_ORDER_DEGREE, offset_bytes: int = 4, tune=None) -> Result:
     """One-shot count of a raw pair list already in device memory."""
-    p = Pipeline(n, src.numel(), offset_bytes=offset_bytes, order=order, device=src.device)
+    p = Pipeline(n, src.numel(), offset_bytes=offset_bytes, order=order, device=src.device,
+                 tune=tune)
     p.enqueue(src, dst, per_vertex=per_vertex)
     return p.result(per_vertex=per_vertex)

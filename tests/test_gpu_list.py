@@ -43,8 +43,8 @@ def _sorted_rows(a: np.ndarray) -> np.ndarray:
     return a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))] if len(a) else a
 
 
-def _gpu_listing(tc, n, s, d, *, order=0, offset_bytes=4, capacity=None):
-    p = tc.Pipeline(n, max(len(s), 1), offset_bytes=offset_bytes, order=order)
+def _gpu_listing(tc, n, s, d, *, order=0, offset_bytes=4, capacity=None, tune=None):
+    p = tc.Pipeline(n, max(len(s), 1), offset_bytes=offset_bytes, order=order, tune=tune)
     p.build(_dev(s), _dev(d))
     p.orient()
     p.count()
@@ -59,8 +59,8 @@ def _oracle_listing(n, s, d, order=0):
     return oracle.list_triangles(dp, dc)
 
 
-def _check_same(tc, n, s, d, order=0, offset_bytes=4):
-    p, T = _gpu_listing(tc, n, s, d, order=order, offset_bytes=offset_bytes)
+def _check_same(tc, n, s, d, order=0, offset_bytes=4, tune=None):
+    p, T = _gpu_listing(tc, n, s, d, order=order, offset_bytes=offset_bytes, tune=tune)
     rows = p.listing().cpu().numpy()
     want = _oracle_listing(n, s, d, order)
     assert len(rows) == len(want) == T
@@ -118,15 +118,15 @@ def test_list_hub_beyond_one_slice_and_clique(tc):
     _check_same(tc, n, s, d, 1)
 
 
-@pytest.mark.parametrize("kicks", [0, 1])
-def test_list_probe_fallback_modes(tc, kicks, monkeypatch):
-    """Stash and sorted probe modes write the same rows."""
-    monkeypatch.setenv("TC_TEST_MAX_KICKS", str(kicks))
+@pytest.mark.parametrize("kicks", [-1, 1])
+def test_list_probe_fallback_modes(tc, kicks):
+    """Stash and sorted probe modes (tc_tune.max_kicks) write the same rows."""
+    tune = {"max_kicks": kicks}
     s, d, n = graphgen.rmat(12, 16, 8)
     for order in (0, 1):
-        _check_same(tc, n, s.numpy(), d.numpy(), order)
+        _check_same(tc, n, s.numpy(), d.numpy(), order, tune=tune)
     n, s, d = pins.complete(60)
-    _check_same(tc, n, s, d, 0)
+    _check_same(tc, n, s, d, 0, tune=tune)
 
 
 def test_list_capacity_and_degenerate(tc):

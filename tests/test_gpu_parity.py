@@ -35,9 +35,9 @@ def _dev(x):
     return torch.as_tensor(np.asarray(x, dtype=np.int32)).cuda()
 
 
-def _gpu(tc, n, s, d, *, per_vertex=True, order=0, offset_bytes=4):
+def _gpu(tc, n, s, d, *, per_vertex=True, order=0, offset_bytes=4, tune=None):
     res = tc.triangle_count(_dev(s), _dev(d), n, per_vertex=per_vertex, order=order,
-                            offset_bytes=offset_bytes)
+                            offset_bytes=offset_bytes, tune=tune)
     pv = res.per_vertex.cpu().numpy().astype(np.uint64) if per_vertex else None
     return res, pv
 
@@ -258,19 +258,19 @@ def test_rmat_scale20_full_parity(tc):
         assert oracle.vertex_triangles(n, hs, hd, int(v)) == int(t[v])
 
 
-@pytest.mark.parametrize("kicks", [0, 1, 2])
-def test_probe_fallback_modes(tc, kicks, monkeypatch):
-    """Capping cuckoo evictions pushes keys into the stash (kicks 1-2, small tables) and past
-    it into the sorted binary-search fallback (kicks 0, tables over 32 keys); counts must
-    not change."""
-    monkeypatch.setenv("TC_TEST_MAX_KICKS", str(kicks))
+@pytest.mark.parametrize("kicks", [-1, 1, 2])
+def test_probe_fallback_modes(tc, kicks):
+    """Capping cuckoo placements (tc_tune.max_kicks) pushes keys into the stash (1-2
+    placements, small tables) and past it into the sorted binary-search fallback (-1: no
+    placement, tables over 32 keys); counts must not change."""
+    tune = {"max_kicks": kicks}
     cases = [pins.complete(40), pins.wheel(30), _hub_graph(1500, 9000, 3)]
     s, d, n = graphgen.rmat(12, 16, 8)
     cases.append((n, s.numpy(), d.numpy()))
     for n, s, d in cases:
         T, t = _oracle(n, s, d)
         for order in (0, 1):
-            res, pv = _gpu(tc, n, s, d, order=order)
+            res, pv = _gpu(tc, n, s, d, order=order, tune=tune)
             assert res.total == T
             np.testing.assert_array_equal(pv, t)
 

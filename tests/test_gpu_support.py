@@ -35,8 +35,8 @@ def _dev(x):
     return torch.as_tensor(np.asarray(x, dtype=np.int32)).cuda()
 
 
-def _gpu_support(tc, n, s, d, *, order=0, offset_bytes=4):
-    p = tc.Pipeline(n, max(len(s), 1), offset_bytes=offset_bytes, order=order)
+def _gpu_support(tc, n, s, d, *, order=0, offset_bytes=4, tune=None):
+    p = tc.Pipeline(n, max(len(s), 1), offset_bytes=offset_bytes, order=order, tune=tune)
     p.build(_dev(s), _dev(d))
     p.orient()
     p.edge_support()
@@ -50,8 +50,8 @@ def _oracle_support(n, s, d, order=0):
     return oracle.edge_support(dp, dc)
 
 
-def _check(tc, n, s, d, order=0, offset_bytes=4):
-    p, sup = _gpu_support(tc, n, s, d, order=order, offset_bytes=offset_bytes)
+def _check(tc, n, s, d, order=0, offset_bytes=4, tune=None):
+    p, sup = _gpu_support(tc, n, s, d, order=order, offset_bytes=offset_bytes, tune=tune)
     T, want = _oracle_support(n, s, d, order)
     np.testing.assert_array_equal(sup, want)
     assert int(p.total.item()) == T
@@ -98,14 +98,14 @@ def test_support_config1_and_hub(tc):
     _check(tc, n, s, d, 1)
 
 
-@pytest.mark.parametrize("kicks", [0, 1])
-def test_support_probe_fallback_modes(tc, kicks, monkeypatch):
-    monkeypatch.setenv("TC_TEST_MAX_KICKS", str(kicks))
+@pytest.mark.parametrize("kicks", [-1, 1])
+def test_support_probe_fallback_modes(tc, kicks):
+    tune = {"max_kicks": kicks}
     s, d, n = graphgen.rmat(12, 16, 8)
     for order in (0, 1):
-        _check(tc, n, s.numpy(), d.numpy(), order)
+        _check(tc, n, s.numpy(), d.numpy(), order, tune=tune)
     n, s, d = pins.complete(60)
-    _check(tc, n, s, d, 0)
+    _check(tc, n, s, d, 0, tune=tune)
 
 
 def test_support_capacity_and_degenerate(tc):
