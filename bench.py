@@ -3,12 +3,15 @@
 A step is one pass of the whole path over one graph already resident in HBM:
 tc_build_csr (raw R-MAT pairs -> symmetric CSR) -> tc_orient (degree order)
 -> tc_count_per_vertex (total and per-vertex counts).  The default workload is
-R-MAT scale 20, edge factor 16 (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), seed 20.
+R-MAT scale 24, edge factor 16 (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), seed 24,
+with int64 row offsets; the scale-20 graph (seed 20, int32 offsets) is measured
+after it and reported under "secondary".
 
 Prints ONE JSON line.  `value` is GTEPS over the whole step: m (unique undirected
 edges) / step time / 1e9.  Per-phase times come from HIP events recorded on the
 stream the library launches on (torch's current stream).  The roofline object
 covers the dominant kernel (the fused advance/filter/reduce count kernel).
+Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -22,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+DEFAULT_WORKLOAD = "rmat-s24-ef16"
+SECONDARY_WORKLOAD = "rmat-s20-ef16"
 
 WORKLOADS = {
     "rmat-s20-ef16": dict(kind="rmat", scale=20, ef=16, seed=20, offset_bytes=4),
@@ -48,7 +53,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat-s20-ef16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-secondary", dest="secondary", action="store_false",
+                    help=f"default workload only: skip the {SECONDARY_WORKLOAD} figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the count")
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
@@ -237,9 +244,12 @@ def make_graph(spec, device):
 
 
 def algorithmic_bytes(dag_ptr, dag_col, n: int, offset_bytes: int, per_vertex: bool) -> dict:
-    """Bytes the count must move at minimum (the count kernel's roofline unit):
-    4 B per enumerated wedge id, 4 B + two row bounds per middle v of a surviving
-    source, two row bounds per vertex for binning, 8 B per per-vertex count."""
+    """Algorithmic bytes of one count launch (the roofline unit of the count kernel): what the
+    wedge-probe method reads when no re-read is served by a cache -- 4 B per enumerated
+    wedge id, 4 B + two row bounds per middle v of a surviving source, two row bounds per
+    vertex for binning -- plus 8 B per per-vertex count written.  Caches serve part of the
+    N+(v) re-reads, and whole cache lines are fetched for row bounds, so the measured
+    traffic (FETCH_SIZE + WRITE_SIZE) can lie on either side of it."""
     import torch
     o = offset_bytes
     dp = (dag_ptr[1:] - dag_ptr[:-1]).to(torch.int64)
@@ -253,30 +263,197 @@ def algorithmic_bytes(dag_ptr, dag_col, n: int, offset_bytes: int, per_vertex: b
     return {"bytes": b, "wedges": wedges, "middle_edges": m_kept}
 
 
-def cpu_baseline(spec, s_host, d_host, n, budget_s: float):
-    """The oracle (clean -> orient -> count with per-vertex) on the host cores."""
-    import numpy as np
+def cpu_baseline(workload, s_host, d_host, n, m, frac: float | None = None):
+    """The oracle (clean -> orient -> count with per-vertex) on the host cores.  The clean and
+    orient take the whole graph; the count enumerates the sources whose ids lie below
+    frac * n (ids are permuted by the generator, so that is a uniform sample of sources;
+    frac = 1 for graphs of up to 2^22 vertices, 1/8 beyond) and its time is scaled by
+    n / sources to the whole graph."""
     import oracle
+    if frac is None:
+        frac = 1.0 if n <= (1 << 22) else 1 / 8
     threads = oracle.max_threads()
     t0 = time.perf_counter()
     rp, col = oracle.clean(n, s_host, d_host)
     t1 = time.perf_counter()
     dp, dc = oracle.orient(rp, col, oracle.ORDER_DEGREE)
+    del col
     t2 = time.perf_counter()
-    total, _ = oracle.count(dp, dc, per_vertex=True, threads=threads)
+    k = max(1, int(n * frac))
+    total, _ = oracle.count(dp, dc, per_vertex=True, threads=threads, sources=k)
     t3 = time.perf_counter()
-    m = int(dp[-1])
+    t_count = (t3 - t2) * n / k
+    whole = k >= n
     return {
-        "value": m / (t3 - t0) / 1e9,
+        "value": m / (t1 - t0 + t2 - t1 + t_count) / 1e9,
         "unit": "GTEPS",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"whole graph ({spec}): clean {t1 - t0:.2f}s, orient {t2 - t1:.2f}s, "
-                  f"count {t3 - t2:.2f}s (count uses {threads} OpenMP threads, clean/orient 1)",
-        "count_only_gteps": m / (t3 - t2) / 1e9,
-        "total": int(total),
-        "_np": np,
+        "sample": (f"{workload}: clean {t1 - t0:.2f}s and orient {t2 - t1:.2f}s of the whole graph "
+                   f"(one thread), count " + (f"{t3 - t2:.2f}s" if whole else
+                   f"of the sources below {k} of {n} ({frac:.3g} of the ids, a uniform sample) "
+                   f"{t3 - t2:.2f}s, scaled to {t_count:.2f}s for all") +
+                   f" ({threads} OpenMP threads)"),
+        "count_only_gteps": m / t_count / 1e9,
+        "total": int(total) if whole else None,
     }
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def golden_for(workload: str):
+    """The oracle's stored counts for a workload (tests/golden/make_*.py), or None."""
+    spec = WORKLOADS[workload]
+    if spec["kind"] != "rmat":
+        return None
+    path = os.path.join(ROOT, "tests", "golden",
+                        f"rmat_s{spec['scale']}_ef{spec['ef']}_seed{spec['seed']}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def graph_line(args, workload, dev, *, cpu: bool) -> dict:
+    """One graph: K timed steps of build -> orient -> count_per_vertex, the count kernel
+    alone, its roofline, the oracle check and (cpu) the oracle baseline."""
+    import hashlib
+
+    import numpy as np
+    import torch
+    import paper_1909_02127_amd as tc
+
+    spec = WORKLOADS[workload]
+    s, d, n = make_graph(spec, dev)
+    _say(f"{workload}: {s.numel()} raw pairs on {n} vertices")
+    ob = spec["offset_bytes"]
+    pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, order=tc.TC_ORDER_DEGREE, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        pipe.build(s, d)
+        if ev:
+            ev[1].record(stream)
+        pipe.orient()
+        if ev:
+            ev[2].record(stream)
+        pipe.count_per_vertex()
+        if ev:
+            ev[3].record(stream)
+
+    if args.calibrate_copy_mib > 0:
+        a = torch.empty(args.calibrate_copy_mib << 18, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    res = pipe.result(per_vertex=True)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for k in range(args.steps):
+        step(evs[k])
+    end.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = start.elapsed_time(end)
+    ms_step = ms_total / args.steps
+    phase = {"build_csr": [], "orient": [], "count_per_vertex": []}
+    for e in evs:
+        phase["build_csr"].append(e[0].elapsed_time(e[1]))
+        phase["orient"].append(e[1].elapsed_time(e[2]))
+        phase["count_per_vertex"].append(e[2].elapsed_time(e[3]))
+    avg = {k: sum(v) / len(v) for k, v in phase.items()}
+    _say(f"{workload}: {ms_step:.3f} ms per step {avg}")
+
+    # The plain total-only count on the same DAG, timed the same way.
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pipe.count()
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(args.steps):
+        pipe.count()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    ms_count_total = c0.elapsed_time(c1) / args.steps
+    total_only = pipe.result().total
+    assert total_only == res.total, "tc_count and tc_count_per_vertex disagree"
+
+    m, nnz = res.m, res.nnz
+    alg = algorithmic_bytes(pipe.dag_ptr, pipe.dag_col, n, ob, per_vertex=True)
+    t_cnt_s = avg["count_per_vertex"] / 1e3
+    achieved = alg["bytes"] / t_cnt_s / 1e9
+    traffic = counter_traffic(workload)
+
+    out = {
+        "metric": "GTEPS (bit-exact vs oracle)",
+        "value": m / (ms_step / 1e3) / 1e9,
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "m": m, "nnz": nnz, "raw_pairs": s.numel(),
+                   "offset_bytes": ob, "order": "degree", "per_vertex": True,
+                   "seed": spec["seed"], "parallelism": "single-gpu"},
+        "triangles": res.total,
+        "triangles_per_s": res.total / (ms_step / 1e3),
+        "phase_ms": avg,
+        "count_only": {"ms_per_vertex": avg["count_per_vertex"], "ms_total_only": ms_count_total,
+                       "gteps_per_vertex": m / t_cnt_s / 1e9,
+                       "gteps_total_only": m / (ms_count_total / 1e3) / 1e9,
+                       "triangles_per_s": res.total / t_cnt_s},
+        "roofline": {"bound": "hbm", "kernel": "count_kernel (tc_count_per_vertex)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbps": traffic / t_cnt_s / 1e9 if traffic else None,
+                     "algorithmic_bytes": alg["bytes"], "wedges": alg["wedges"]},
+        "wall_s_timed": t_wall,
+    }
+
+    golden = golden_for(workload)
+    if golden is not None:
+        # the oracle's stored counts: the total and every t(v) through the array's digest
+        t = np.ascontiguousarray(res.per_vertex.cpu().numpy().view(np.uint64), dtype="<u8")
+        out["oracle_match"] = bool(
+            res.total == golden["triangles"] and m == golden["m"]
+            and hashlib.sha256(t.tobytes()).hexdigest() == golden["t_sha256"])
+        out["oracle_check"] = "stored oracle counts (total and SHA-256 of every t(v))"
+        del t
+    if cpu or (golden is None and not args.no_check):
+        hs, hd = s.cpu().numpy(), d.cpu().numpy()
+        if cpu:
+            cb = cpu_baseline(workload, hs, hd, n, m)
+            total = cb.pop("total")
+            if "oracle_match" not in out and total is not None:
+                out["oracle_match"] = total == res.total
+                out["oracle_check"] = "live oracle total"
+            out["cpu_baseline"] = cb
+        elif "oracle_match" not in out:
+            import oracle
+            out["oracle_match"] = oracle.triangles(n, hs, hd) == res.total
+            out["oracle_check"] = "live oracle total"
+    del pipe
+    torch.cuda.empty_cache()
+    return out
 
 
 def oracle_prefix_baseline(fn, dp, dc, frac: float, value_of, unit: str, what: str) -> dict:
@@ -420,17 +597,16 @@ def batch_main(args, spec):
 
 
 def serve_main(args, spec):
-    """Continuous-batching engine vs a plain engine (one request per launch, serialized)
-    on the same Poisson request stream."""
+    """Continuous-batching engine on a resident lane pool vs a plain engine (one request per
+    launch, serialized, on one lane) on the same Poisson request stream."""
     import numpy as np
     import torch
 
     import graphgen
     import oracle
-    from paper_1909_02127_amd.serve import DeviceExecutor, Engine, Request
-
-    def say(msg):
-        print(msg, file=sys.stderr, flush=True)
+    from paper_1909_02127_amd import _lib
+    from paper_1909_02127_amd.serve import DeviceExecutor, Engine, Lane, Request, lane_bytes, \
+        plan_lanes
 
     rng = np.random.default_rng(spec["seed"])
     specs = graphgen.batch_suite_spec(4096, seed=4)
@@ -444,7 +620,7 @@ def serve_main(args, spec):
         s_, d_, n_ = graphgen.rmat(spec["large_scale"], 16, 220 + k, device="cuda")
         large.append((s_.cpu().pin_memory(), d_.cpu().pin_memory(), n_))
     torch.cuda.synchronize()
-    say(f"pool: {len(pool)} graphs + {len(large)} scale-{spec['large_scale']} graphs")
+    _say(f"pool: {len(pool)} graphs + {len(large)} scale-{spec['large_scale']} graphs")
 
     def stream(count, seed, qps=None):
         """Requests with Poisson arrivals at `qps` (None: args.qps; 0: all at time 0)."""
@@ -459,11 +635,16 @@ def serve_main(args, spec):
         return out
 
     budget = 64 << 30
-    ex = DeviceExecutor()
+    big_pairs = max(int(g[0].numel()) for g in large)
+    big_n = max(g[2] for g in large)
+    lanes = plan_lanes(_lib, budget, small_lanes=3, small_pairs=24_000_000,
+                       small_vertices=6_000_000, small_graphs=256, large_lanes=1,
+                       large_pairs=big_pairs, large_vertices=big_n)
+    ex = DeviceExecutor(lanes)
+    _say(f"lanes: {[(ln.index, ln.large, ln.max_pairs, ln.bytes) for ln in lanes]}")
 
     def engine():
-        return Engine(ex, budget_bytes=budget, max_inflight=3, max_batch=256,
-                      large_pairs=8_000_000)
+        return Engine(ex)
 
     sweep = None
     qps = args.qps
@@ -472,7 +653,7 @@ def serve_main(args, spec):
         cap_n = 3000
         cst = engine().run(stream(cap_n, 50, qps=0))
         capacity = cst.summary(warmup=cap_n // 10)["graphs_per_s"]
-        say(f"capacity: {capacity:.1f} graphs/s")
+        _say(f"capacity: {capacity:.1f} graphs/s")
         sweep = {"capacity_graphs_per_s": capacity, "points": []}
         warm = 1000
         for frac in (0.3, 0.5, 0.9):
@@ -482,7 +663,7 @@ def serve_main(args, spec):
             pt["load"] = frac
             pt["qps"] = frac * capacity
             sweep["points"].append(pt)
-            say(f"load {frac}: {pt}")
+            _say(f"load {frac}: {pt}")
         qps = 0.7 * capacity
     else:
         warm = max(1, args.requests // 10)
@@ -490,23 +671,36 @@ def serve_main(args, spec):
     reqs = stream(warm + args.requests, 51, qps=qps)
     st = eng.run(reqs)
     summ = st.summary(warmup=warm)
-    say(f"continuous batching at {qps:.1f} requests/s: {summ}")
+    _say(f"continuous batching at {qps:.1f} requests/s: {summ}")
     if sweep is not None:
         summ_pt = dict(summ, load=0.7, qps=qps)
         sweep["points"].insert(2, summ_pt)
-    # exactness: sample requests against the oracle (small ones) and against each other
-    ok = True
-    for r in reqs[:: max(1, len(reqs) // 20)]:
-        if r.num_pairs < 2_000_000:
-            ok &= r.total == oracle.triangles(r.n, r.src.numpy(), r.dst.numpy())
+    # exactness: every distinct graph that was served, total and t(v), against the oracle
+    served = {}
+    for r in reqs:
+        served.setdefault(id(r.src), r)
+    ok, checked = True, 0
+    for r in served.values():
+        if r.total is None:
+            ok = False
+            continue
+        T, t = oracle.triangles(r.n, r.src.numpy(), r.dst.numpy(), per_vertex=True,
+                                threads=oracle.max_threads())
+        ok &= r.total == T and bool(np.array_equal(r.per_vertex, t))
+        checked += 1
+    same = True  # every request of one graph got the same counts
+    for r in reqs:
+        ref = served[id(r.src)]
+        same &= r.total == ref.total and bool(np.array_equal(r.per_vertex, ref.per_vertex))
+    _say(f"oracle: {checked} distinct graphs checked, match={ok}; repeats identical={same}")
     plain_n = max(1, min(args.requests // 3, 2000))
-    peng = Engine(DeviceExecutor(), budget_bytes=budget, max_inflight=1, max_batch=1,
-                  large_pairs=1 << 62)
+    plane = Lane(0, True, big_pairs, big_n, 1, lane_bytes(_lib, big_pairs, big_n, 1))
+    peng = Engine(DeviceExecutor([plane]))
     preqs = stream(warm + plain_n, 51, qps=qps)
     pst = peng.run(preqs)
     psumm = pst.summary(warmup=warm)
-    say(f"plain: {psumm}")
-    same = all(a.total == b.total for a, b in zip(reqs, preqs))
+    _say(f"plain: {psumm}")
+    plain_same = all(a.total == b.total for a, b in zip(reqs, preqs))
     out = {
         "metric": "serving graphs/s (bit-exact vs oracle)",
         "value": summ["graphs_per_s"],
@@ -519,10 +713,14 @@ def serve_main(args, spec):
                    "warmup_requests": warm,
                    "pool": len(pool), "large_scale": spec["large_scale"],
                    "large_frac": spec["large_frac"], "budget_bytes": budget,
+                   "lanes": [{"large": ln.large, "max_pairs": ln.max_pairs,
+                              "max_vertices": ln.max_vertices, "max_graphs": ln.max_graphs,
+                              "bytes": ln.bytes} for ln in lanes],
                    "parallelism": "single-gpu"},
         "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "serving": summ,
         "plain": psumm, "plain_requests": plain_n, "sweep": sweep,
-        "oracle_match": bool(ok), "plain_equals_batched": bool(same),
+        "oracle_match": bool(ok), "oracle_graphs_checked": checked,
+        "repeats_identical": bool(same), "plain_equals_batched": bool(plain_same),
     }
     print(json.dumps(out), flush=True)
 
@@ -825,120 +1023,14 @@ def main():
         return ablation_main(args, spec)
     if spec["kind"] == "k4":
         return k4_main(args, spec)
-    s, d, n = make_graph(spec, dev)
-    ob = spec["offset_bytes"]
-    pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, order=tc.TC_ORDER_DEGREE, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        pipe.build(s, d)
-        if ev:
-            ev[1].record(stream)
-        pipe.orient()
-        if ev:
-            ev[2].record(stream)
-        pipe.count_per_vertex()
-        if ev:
-            ev[3].record(stream)
-
-    if args.calibrate_copy_mib > 0:
-        a = torch.empty(args.calibrate_copy_mib << 18, dtype=torch.int32, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    res = pipe.result(per_vertex=True)
-
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    start.record(stream)
-    for k in range(args.steps):
-        step(evs[k])
-    end.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms_total = start.elapsed_time(end)
-    ms_step = ms_total / args.steps
-    phase = {"build_csr": [], "orient": [], "count_per_vertex": []}
-    for e in evs:
-        phase["build_csr"].append(e[0].elapsed_time(e[1]))
-        phase["orient"].append(e[1].elapsed_time(e[2]))
-        phase["count_per_vertex"].append(e[2].elapsed_time(e[3]))
-    avg = {k: sum(v) / len(v) for k, v in phase.items()}
-
-    # The plain total-only count on the same DAG, timed the same way.
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    pipe.count()
-    torch.cuda.synchronize()
-    c0.record(stream)
-    for _ in range(args.steps):
-        pipe.count()
-    c1.record(stream)
-    torch.cuda.synchronize()
-    ms_count_total = c0.elapsed_time(c1) / args.steps
-    total_only = pipe.result().total
-    assert total_only == res.total, "tc_count and tc_count_per_vertex disagree"
-
-    m, nnz = res.m, res.nnz
-    alg = algorithmic_bytes(pipe.dag_ptr, pipe.dag_col, n, ob, per_vertex=True)
-    t_cnt_s = avg["count_per_vertex"] / 1e3
-    achieved = alg["bytes"] / t_cnt_s / 1e9
-
-    out = {
-        "metric": "GTEPS (bit-exact vs oracle)",
-        "value": m / (ms_step / 1e3) / 1e9,
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "nnz": nnz, "raw_pairs": s.numel(),
-                   "offset_bytes": ob, "order": "degree", "per_vertex": True,
-                   "seed": spec["seed"], "parallelism": "single-gpu"},
-        "triangles": res.total,
-        "triangles_per_s": res.total / (ms_step / 1e3),
-        "phase_ms": avg,
-        "count_only": {"ms_per_vertex": avg["count_per_vertex"], "ms_total_only": ms_count_total,
-                       "gteps_per_vertex": m / t_cnt_s / 1e9,
-                       "gteps_total_only": m / (ms_count_total / 1e3) / 1e9,
-                       "triangles_per_s": res.total / t_cnt_s},
-        "roofline": {"bound": "hbm", "kernel": "count_kernel (tc_count_per_vertex)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(args.workload),
-                     "algorithmic_bytes": alg["bytes"], "wedges": alg["wedges"]},
-        "wall_s_timed": t_wall,
-    }
-
-    if not args.no_cpu_baseline or not args.no_check:
-        import numpy as np
-        hs, hd = s.cpu().numpy(), d.cpu().numpy()
-        if not args.no_cpu_baseline:
-            cb = cpu_baseline(args.workload, hs, hd, n, args.cpu_budget_s)
-            ok = cb.pop("total") == res.total
-            cb.pop("_np")
-            out["cpu_baseline"] = cb
-            out["oracle_match"] = ok
-        elif not args.no_check:
-            import oracle
-            out["oracle_match"] = oracle.triangles(n, hs, hd) == res.total
-        del np
+    out = graph_line(args, args.workload, dev, cpu=not args.no_cpu_baseline)
+    if args.workload == DEFAULT_WORKLOAD and args.secondary:
+        # the scale-20 graph as well: its own timed steps, roofline and oracle check
+        sec = graph_line(args, SECONDARY_WORKLOAD, dev, cpu=False)
+        out["secondary"] = {k: sec[k] for k in (
+            "value", "unit", "ms_per_step", "config", "triangles", "triangles_per_s", "phase_ms",
+            "count_only", "roofline", "oracle_match") if k in sec}
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -221,6 +221,25 @@ tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, const int64_t*
                            const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
 
 /*
+ * tc_pack_pairs - the raw pairs of several graphs, concatenated, moved in place
+ * to the vertex ids of their disjoint union, the input tc_build_csr takes to
+ * build a batch for tc_count_batched (every triangle lies inside one graph, so
+ * the union's matches are the graphs' matches, Alg. 1 run on each graph).
+ *
+ *   num_graphs  G >= 0
+ *   pair_off    device int64[G+1]: graph g's pairs are [pair_off[g], pair_off[g+1])
+ *               of src and dst, with local ids in [0, n_g)
+ *   vtx_off     device int64[G+1]: graph g owns the union ids [vtx_off[g],
+ *               vtx_off[g+1]), so n_g = vtx_off[g+1] - vtx_off[g]
+ *   src, dst    device int32[pair_off[G]] (read and written): each local id x
+ *               becomes vtx_off[g] + x, or -1 when x lies outside [0, n_g), which
+ *               tc_build_csr then reports as TC_ERR_ID_OUT_OF_RANGE
+ * Offsets must be non-decreasing; nothing is allocated and no workspace is used.
+ */
+tc_status tc_pack_pairs(int64_t num_graphs, const int64_t* pair_off, const int64_t* vtx_off,
+                        int32_t* src, int32_t* dst, void* stream);
+
+/*
  * tc_list_triangles - the matches themselves.  Sec. II-A defines the output of
  * subgraph matching as every match; Alg. 1 collects the complete matches in M,
  * and under the unique mapping order each triangle is one match.  Each is

@@ -51,7 +51,7 @@ def _load():
         lib.oracle_orient.restype = i64
         lib.oracle_orient.argtypes = [i64, p, p, i32, p, p, p]
         lib.oracle_count.restype = ctypes.c_uint64
-        lib.oracle_count.argtypes = [i64, p, p, p, i32]
+        lib.oracle_count.argtypes = [i64, i64, p, p, p, i32]
         lib.oracle_vertex_triangles.restype = i64
         lib.oracle_vertex_triangles.argtypes = [i64, i64, p, p, i32]
         lib.oracle_count_k4.restype = ctypes.c_uint64
@@ -118,14 +118,16 @@ def orient(row_ptr: np.ndarray, col: np.ndarray, order: int = ORDER_DEGREE,
 
 
 def count(dag_ptr: np.ndarray, dag_col: np.ndarray, *, per_vertex: bool = False,
-          threads: int = 0):
-    """Triangles of an oriented graph; with per_vertex, also t(v) as uint64[n]."""
+          threads: int = 0, sources=None):
+    """Triangles of an oriented graph; with per_vertex, also t(v) as uint64[n].  With
+    `sources`, only the triangles whose source u (lowest rank) has an id below it."""
     lib = _load()
     dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
     dag_col = _i32(dag_col)
     n = dag_ptr.size - 1
     t = np.zeros(max(n, 1), dtype=np.uint64) if per_vertex else None
-    total = int(lib.oracle_count(n, _ptr(dag_ptr), _ptr(dag_col), _ptr(t), threads))
+    total = int(lib.oracle_count(n, _sources(dag_ptr, sources), _ptr(dag_ptr), _ptr(dag_col),
+                                 _ptr(t), threads))
     if per_vertex:
         return total, t[:n].copy()
     return total

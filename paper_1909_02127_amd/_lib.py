@@ -80,6 +80,8 @@ def _load() -> ctypes.CDLL:
     lib.tc_count_per_vertex.argtypes = [csr, p, p, tune, p, sz, p]
     lib.tc_count_batched.restype = i32
     lib.tc_count_batched.argtypes = [csr, i64, p, p, p, p, tune, p, sz, p]
+    lib.tc_pack_pairs.restype = i32
+    lib.tc_pack_pairs.argtypes = [i64, p, p, p, p, p]
     lib.tc_count_k4.restype = i32
     lib.tc_count_k4.argtypes = [csr, p, p, sz, p]
     lib.tc_ne_filter.restype = i32
@@ -219,6 +221,19 @@ def tc_count_batched(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_batched, ws, ctypes.byref(csr), g, _ptr(vtx_off), _ptr(totals),
              _ptr(per_vertex), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_pack_pairs(pair_off: torch.Tensor, vtx_off: torch.Tensor, src: torch.Tensor,
+                  dst: torch.Tensor, *, stream=None) -> None:
+    """In place: graph g's pairs src/dst[pair_off[g]:pair_off[g+1]] move from local ids to
+    vtx_off[g] + id (ids outside the graph become -1)."""
+    g = pair_off.numel() - 1
+    if pair_off.dtype != torch.int64 or vtx_off.dtype != torch.int64 or vtx_off.numel() != g + 1:
+        raise ValueError("pair_off and vtx_off must be int64[G+1]")
+    if src.dtype != torch.int32 or dst.dtype != torch.int32 or src.numel() != dst.numel():
+        raise ValueError("src and dst must be int32 tensors of equal length")
+    _check(LIB.tc_pack_pairs(max(g, 0), _ptr(pair_off), _ptr(vtx_off), _ptr(src), _ptr(dst),
+                             _stream(stream)))
 
 
 def tc_count_k4_workspace(n: int) -> int:

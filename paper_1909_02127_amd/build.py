@@ -24,7 +24,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", f"-I{ROOT / 'include'}", f"-I{CSRC}"]
 
-SOURCES = ["api.cpp", "build_csr.hip", "orient.hip", "count.hip", "bfs.hip", "clique4.hip"]
+SOURCES = ["api.cpp", "build_csr.hip", "orient.hip", "count.hip", "bfs.hip", "clique4.hip",
+           "pack.hip"]
 
 
 def _compile(src: str) -> Path:

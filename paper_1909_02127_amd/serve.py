@@ -1,24 +1,32 @@
 """Continuous-batching serving loop for triangle-count requests.
 
 A request is one undirected graph (raw int32 pairs with local ids, in host
-memory) that asks for its exact total and per-vertex counts.  The engine
+memory) that asks for its exact total and per-vertex counts.  The device side is
+a fixed pool of *lanes*, allocated once from the HBM budget and kept resident:
+each lane owns a HIP stream and every buffer one batch needs in flight (pairs,
+symmetric CSR, oriented DAG, the three workspaces, per-graph totals, per-vertex
+counts) plus pinned host buffers for the results, sized for the lane's capacity
+in pairs, vertices and graphs.  Launching a batch allocates nothing; it reuses
+the lane's buffers.  The engine
 
-  * admits waiting requests in arrival order while their estimated HBM
-    footprint fits the budget (a request larger than the whole budget is
-    rejected);
-  * packs the requests admitted since the last launch into one batch (the
-    disjoint union of their graphs) and launches it on a free stream: upload,
-    tc_build_csr, tc_orient, tc_count_batched with per-vertex counts, and
-    asynchronous copies of the results into pinned host memory, all enqueued
-    without host synchronisation, so batches on different streams overlap on
-    the device while new requests keep arriving;
-  * gives requests above `large_pairs` a lane of their own (one per batch) so a
-    large graph does not hold up the small ones behind it;
-  * polls the batches' completion events, hands each request its counts,
-    releases its memory, and records latency = completion - arrival.
+  * validates each request on submit (ids inside [0, n)) and routes it by size to
+    one of two admission queues: requests that fit a small lane, and larger ones
+    that only a large lane holds; a request larger than every lane is rejected;
+  * whenever a lane is free, packs the head of its queue (FIFO, as many requests
+    as fit the lane's capacity) into one batch and launches it on the lane's
+    stream: upload, tc_pack_pairs (local ids -> ids of the disjoint union),
+    tc_build_csr, tc_orient, tc_count_batched with per-vertex counts and the
+    copies of the results into pinned memory, with no host synchronisation, so
+    batches on different lanes overlap on the device while new requests arrive.
+    Small requests never queue behind large ones: large lanes take the large
+    queue first and small lanes never take large requests;
+  * polls the lanes' completion events, hands each request its counts (or the
+    batch's device-side error), frees the lane and records latency = completion
+    - arrival.
 
-The scheduling logic is independent of the device: `Engine` drives an
-executor with launch / ready / collect, so it can be exercised with a fake.
+The scheduling logic is independent of the device: `Engine` drives an executor
+that exposes its lanes and `launch / ready / collect`, so it is tested on the CPU
+with a fake.
 """
 from __future__ import annotations
 
@@ -47,14 +55,41 @@ class Request:
         return int(len(self.src))
 
 
-def footprint_bytes(n: int, num_pairs: int) -> int:
-    """Device bytes a request holds while in flight (its share of a batch): the
-    pairs (8 B each), the build keys (2 x 16 B per pair), the symmetric and
-    oriented CSR (12 B per pair, 16 B per vertex for int64 offsets), the orientation's
-    per-tile state (under 1 B per pair), per-vertex counts and scratch (about 24 B per
-    vertex)."""
-    return 8 * num_pairs + 32 * num_pairs + 12 * num_pairs + num_pairs + 16 * (n + 1) + 24 * n \
-        + 1024
+@dataclass(frozen=True)
+class Lane:
+    """Capacity of one preallocated device slot (one batch in flight)."""
+    index: int
+    large: bool
+    max_pairs: int
+    max_vertices: int
+    max_graphs: int
+    bytes: int = 0  # device bytes the lane holds
+
+    def fits(self, pairs: int, vertices: int, graphs: int = 1) -> bool:
+        return pairs <= self.max_pairs and vertices <= self.max_vertices and \
+            graphs <= self.max_graphs
+
+
+def _host_array(a) -> np.ndarray:
+    if isinstance(a, np.ndarray):
+        return a
+    return a.numpy()  # a (pinned) CPU torch tensor
+
+
+def validate(req: Request) -> str | None:
+    """Why the request cannot be counted, or None."""
+    if req.n < 0:
+        return "negative vertex count"
+    if len(req.src) != len(req.dst):
+        return "src and dst differ in length"
+    if req.num_pairs == 0:
+        return None
+    s, d = _host_array(req.src), _host_array(req.dst)
+    lo = min(int(s.min()), int(d.min()))
+    hi = max(int(s.max()), int(d.max()))
+    if lo < 0 or hi >= req.n:
+        return f"vertex id outside [0, {req.n})"
+    return None
 
 
 @dataclass
@@ -62,7 +97,9 @@ class Stats:
     latencies: list = field(default_factory=list)
     completed: int = 0
     rejected: int = 0
+    failed: int = 0
     batches: int = 0
+    large_batches: int = 0
     max_in_use: int = 0
     max_inflight_batches: int = 0
     first_arrival: float | None = None
@@ -74,7 +111,9 @@ class Stats:
         return {
             "completed": self.completed,
             "rejected": self.rejected,
+            "failed": self.failed,
             "batches": self.batches,
+            "large_batches": self.large_batches,
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_ms": float(lat.mean()) if lat.size else None,
@@ -85,94 +124,112 @@ class Stats:
 
 
 class Engine:
-    def __init__(self, executor, *, budget_bytes: int, max_inflight: int = 3,
-                 max_batch: int = 1024, large_pairs: int = 8_000_000, clock=time.perf_counter):
+    """Admission, batching and completion over an executor's lanes."""
+
+    def __init__(self, executor, *, clock=time.perf_counter):
         self.ex = executor
-        self.budget = int(budget_bytes)
-        self.max_inflight = max_inflight
-        self.max_batch = max_batch
-        self.large_pairs = large_pairs
+        self.lanes: list[Lane] = list(executor.lanes)
+        if not self.lanes:
+            raise ValueError("the executor has no lanes")
         self.clock = clock
-        self.waiting: collections.deque[Request] = collections.deque()
-        self.admitted_small: list[Request] = []
-        self.admitted_large: collections.deque[Request] = collections.deque()
-        self.inflight: list[tuple[object, list[Request], int, bool]] = []
-        self.in_use = 0
+        self.small_q: collections.deque[Request] = collections.deque()
+        self.large_q: collections.deque[Request] = collections.deque()
+        self.inflight: dict[int, tuple[object, list[Request]]] = {}  # lane -> (handle, reqs)
         self.stats = Stats()
         self.finished: list[Request] = []
+        small = [ln for ln in self.lanes if not ln.large]
+        large = [ln for ln in self.lanes if ln.large]
+        self._small_cap = small[0] if small else None
+        self._large_caps = large
 
     # -- admission ------------------------------------------------------------------
+    def _finish_now(self, req: Request, error: str, rejected: bool) -> None:
+        req.error = error
+        req.done = self.clock()
+        if rejected:
+            self.stats.rejected += 1
+        else:
+            self.stats.failed += 1
+        self.finished.append(req)
+
     def submit(self, req: Request) -> None:
         if self.stats.first_arrival is None or req.arrival < self.stats.first_arrival:
             self.stats.first_arrival = req.arrival
-        if footprint_bytes(req.n, req.num_pairs) > self.budget:
-            req.error = "request footprint exceeds the device budget"
-            req.done = self.clock()
-            self.stats.rejected += 1
-            self.finished.append(req)
+        why = validate(req)
+        if why is not None:
+            self._finish_now(req, why, True)
             return
-        self.waiting.append(req)
-
-    def _admit(self) -> None:
-        while self.waiting:
-            req = self.waiting[0]
-            need = footprint_bytes(req.n, req.num_pairs)
-            if self.in_use + need > self.budget:
-                break  # FIFO: later requests wait behind it (no starvation of large ones)
-            self.waiting.popleft()
-            self.in_use += need
-            self.stats.max_in_use = max(self.stats.max_in_use, self.in_use)
-            req.admitted = self.clock()
-            if req.num_pairs >= self.large_pairs:
-                self.admitted_large.append(req)
-            else:
-                self.admitted_small.append(req)
+        if self._small_cap is not None and self._small_cap.fits(req.num_pairs, req.n):
+            self.small_q.append(req)
+        elif any(ln.fits(req.num_pairs, req.n) for ln in self._large_caps):
+            self.large_q.append(req)
+        else:
+            self._finish_now(req, "request is larger than every lane of the device pool", True)
 
     # -- launching and completion ---------------------------------------------------------
-    def _lanes_busy(self, large: bool) -> int:
-        return sum(1 for _, _, _, lg in self.inflight if lg == large)
+    def _take(self, q: collections.deque, lane: Lane) -> list[Request]:
+        batch, pairs, verts = [], 0, 0
+        while q and len(batch) < lane.max_graphs:
+            r = q[0]
+            if not lane.fits(pairs + r.num_pairs, verts + r.n, len(batch) + 1):
+                break
+            q.popleft()
+            batch.append(r)
+            pairs += r.num_pairs
+            verts += r.n
+        return batch
 
     def _launch(self) -> None:
-        # one lane for large requests, the rest for packed batches of small ones
-        if self.admitted_large and self._lanes_busy(True) == 0:
-            req = self.admitted_large.popleft()
-            self._start([req], True)
-        small_lanes = max(1, self.max_inflight - 1)
-        while self.admitted_small and self._lanes_busy(False) < small_lanes:
-            batch = self.admitted_small[: self.max_batch]
-            self.admitted_small = self.admitted_small[self.max_batch:]
-            self._start(batch, False)
-
-    def _start(self, reqs: list[Request], large: bool) -> None:
-        handle = self.ex.launch(reqs)
-        mem = sum(footprint_bytes(r.n, r.num_pairs) for r in reqs)
-        self.inflight.append((handle, reqs, mem, large))
-        self.stats.batches += 1
-        self.stats.max_inflight_batches = max(self.stats.max_inflight_batches, len(self.inflight))
+        for lane in self.lanes:
+            if lane.index in self.inflight:
+                continue
+            batch = []
+            if lane.large and self.large_q:
+                batch = self._take(self.large_q, lane)
+            if not batch and self.small_q:
+                batch = self._take(self.small_q, lane)
+            if not batch:
+                continue
+            now = self.clock()
+            for r in batch:
+                r.admitted = now
+            handle = self.ex.launch(lane.index, batch)
+            self.inflight[lane.index] = (handle, batch)
+            self.stats.batches += 1
+            self.stats.large_batches += int(lane.large)
+            self.stats.max_inflight_batches = max(self.stats.max_inflight_batches,
+                                                  len(self.inflight))
+            in_use = sum(self.lanes[i].bytes for i in self.inflight)
+            self.stats.max_in_use = max(self.stats.max_in_use, in_use)
 
     def _poll(self) -> None:
-        still = []
-        for handle, reqs, mem, large in self.inflight:
+        for li in list(self.inflight):
+            handle, reqs = self.inflight[li]
             if not self.ex.ready(handle):
-                still.append((handle, reqs, mem, large))
                 continue
-            totals, per_vertex = self.ex.collect(handle)
+            totals, per_vertex, error = self.ex.collect(handle)
+            del self.inflight[li]
             now = self.clock()
-            for r, t, pv in zip(reqs, totals, per_vertex):
-                r.total, r.per_vertex, r.done = t, pv, now
-                self.stats.latencies.append(now - r.arrival)
-                self.stats.completed += 1
+            for k, r in enumerate(reqs):
+                r.done = now
+                if error is not None:
+                    r.error = error
+                    self.stats.failed += 1
+                else:
+                    r.total, r.per_vertex = totals[k], per_vertex[k]
+                    self.stats.latencies.append(now - r.arrival)
+                    self.stats.completed += 1
                 self.finished.append(r)
             self.stats.last_done = now
-            self.in_use -= mem
-        self.inflight = still
+
+    def busy(self) -> bool:
+        return bool(self.small_q or self.large_q or self.inflight)
 
     def step(self) -> bool:
         """One engine iteration; returns True while work is queued or in flight."""
         self._poll()
-        self._admit()
         self._launch()
-        return bool(self.waiting or self.admitted_small or self.admitted_large or self.inflight)
+        return self.busy()
 
     def run(self, requests: list[Request], *, idle_sleep: float = 50e-6) -> Stats:
         """Open-loop run: each request is submitted once the clock passes its arrival
@@ -199,10 +256,44 @@ class Engine:
         return self.stats
 
 
-class DeviceExecutor:
-    """Runs a batch of requests on the GPU through the C ABI, on its own stream."""
+def lane_bytes(lib, max_pairs: int, max_vertices: int, max_graphs: int) -> int:
+    """Device bytes of one lane: pairs, symmetric CSR and DAG with int64 offsets, the
+    three workspaces at capacity, graph offsets, totals and per-vertex counts."""
+    n, p, g = max_vertices, max_pairs, max_graphs
+    b = 8 * p                                    # src, dst
+    b += 8 * (n + 1) + 4 * 2 * p                 # row_ptr, col
+    b += 8 * (n + 1) + 4 * p                     # dag_ptr, dag_col
+    b += 16 * (g + 1) + 8 * g + 8 * n + 64       # pair/vtx offsets, totals, per-vertex, sizes
+    b += lib.tc_build_csr_workspace(n, p, 8)
+    b += lib.tc_orient_workspace(n, p)
+    b += lib.tc_count_batched_workspace(n)
+    return int(b)
 
-    def __init__(self, device="cuda", *, tune=None):
+
+def plan_lanes(lib, budget_bytes: int, *, small_lanes: int = 3, small_pairs: int = 32_000_000,
+               small_vertices: int = 8_000_000, small_graphs: int = 512, large_lanes: int = 1,
+               large_pairs: int = 70_000_000, large_vertices: int = 1 << 22) -> list[Lane]:
+    """The lane pool: large lanes (index 0 ...) holding one graph of up to large_pairs pairs
+    on large_vertices vertices each, then small lanes holding up to small_graphs graphs with
+    small_pairs pairs on small_vertices vertices together.  Raises ValueError when the pool
+    does not fit `budget_bytes` of device memory."""
+    lanes = []
+    for _ in range(large_lanes):
+        lanes.append(Lane(len(lanes), True, large_pairs, large_vertices, 1,
+                          lane_bytes(lib, large_pairs, large_vertices, 1)))
+    for _ in range(small_lanes):
+        lanes.append(Lane(len(lanes), False, small_pairs, small_vertices, small_graphs,
+                          lane_bytes(lib, small_pairs, small_vertices, small_graphs)))
+    total = sum(ln.bytes for ln in lanes)
+    if total > budget_bytes:
+        raise ValueError(f"the lane pool needs {total} bytes, above the budget of {budget_bytes}")
+    return lanes
+
+
+class DeviceExecutor:
+    """Runs batches on the GPU through the C ABI, one resident lane per batch in flight."""
+
+    def __init__(self, lanes: list[Lane], device="cuda", *, tune=None):
         import torch
 
         from . import _lib
@@ -210,95 +301,96 @@ class DeviceExecutor:
         self.lib = _lib
         self.device = torch.device(device)
         self.tune = tune
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(4)]
-        self.busy = [False] * 4
+        self.lanes = list(lanes)
+        self.slots = [self._alloc(ln) for ln in self.lanes]
 
-    def _stream(self):
-        for i, b in enumerate(self.busy):
-            if not b:
-                self.busy[i] = True
-                return i
-        raise RuntimeError("no free stream")
+    def _alloc(self, ln: Lane) -> dict:
+        torch, L, dev = self.torch, self.lib, self.device
+        p, n, g = max(ln.max_pairs, 1), max(ln.max_vertices, 1), max(ln.max_graphs, 1)
 
-    def launch(self, reqs: list[Request]):
+        def dbuf(k, dt):
+            return torch.empty(k, dtype=dt, device=dev)
+
+        def hbuf(k, dt):
+            return torch.empty(k, dtype=dt, pin_memory=True)
+
+        return {
+            "stream": torch.cuda.Stream(device=dev),
+            "event": torch.cuda.Event(),
+            "src": dbuf(p, torch.int32), "dst": dbuf(p, torch.int32),
+            "row_ptr": dbuf(n + 1, torch.int64), "col": dbuf(2 * p, torch.int32),
+            "dag_ptr": dbuf(n + 1, torch.int64), "dag_col": dbuf(p, torch.int32),
+            "offs": dbuf(2 * (g + 1), torch.int64),  # pair offsets, then vertex offsets
+            "totals": dbuf(g, torch.int64), "pv": dbuf(n, torch.int64),
+            "sizes": dbuf(2, torch.int64),  # nnz, m
+            "ws_build": dbuf(L.tc_build_csr_workspace(n, p, 8), torch.uint8),
+            "ws_orient": dbuf(L.tc_orient_workspace(n, p), torch.uint8),
+            "ws_count": dbuf(L.tc_count_batched_workspace(n), torch.uint8),
+            "h_src": hbuf(p, torch.int32), "h_dst": hbuf(p, torch.int32),
+            "h_offs": hbuf(2 * (g + 1), torch.int64),
+            "h_totals": hbuf(g, torch.int64), "h_pv": hbuf(n, torch.int64),
+            "h_sizes": hbuf(2, torch.int64),
+        }
+
+    def launch(self, lane_index: int, reqs: list[Request]):
         torch, L = self.torch, self.lib
-        si = self._stream()
-        stream = self.streams[si]
-        ns = [r.n for r in reqs]
-        off = np.zeros(len(reqs) + 1, dtype=np.int64)
-        off[1:] = np.cumsum(ns)
-        pairs = np.zeros(len(reqs) + 1, dtype=np.int64)
-        pairs[1:] = np.cumsum([r.num_pairs for r in reqs])
-        n, p, G = int(off[-1]), int(pairs[-1]), len(reqs)
-        dev = self.device
+        b = self.slots[lane_index]
+        G = len(reqs)
+        poff = np.zeros(G + 1, dtype=np.int64)
+        poff[1:] = np.cumsum([r.num_pairs for r in reqs])
+        voff = np.zeros(G + 1, dtype=np.int64)
+        voff[1:] = np.cumsum([r.n for r in reqs])
+        p, n = int(poff[-1]), int(voff[-1])
+        h_offs = b["h_offs"].numpy()
+        h_offs[: G + 1] = poff
+        h_offs[G + 1: 2 * G + 2] = voff
+        stream = b["stream"]
         with torch.cuda.stream(stream):
-            src = torch.empty(max(p, 1), dtype=torch.int32, device=dev)
-            dst = torch.empty(max(p, 1), dtype=torch.int32, device=dev)
-            for r, a in zip(reqs, pairs[:-1]):
+            for r, a in zip(reqs, poff[:-1]):
                 k = r.num_pairs
-                if k:
-                    src[a: a + k].copy_(_pinned(torch, r.src), non_blocking=True)
-                    dst[a: a + k].copy_(_pinned(torch, r.dst), non_blocking=True)
-            if G > 1 and p:
-                shift = torch.repeat_interleave(
-                    torch.as_tensor(off[:-1], device=dev),
-                    torch.as_tensor(pairs[1:] - pairs[:-1], device=dev))
-                src[:p] += shift.to(torch.int32)
-                dst[:p] += shift.to(torch.int32)
-            vtx_off = torch.as_tensor(off, device=dev)
-            row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
-            col = torch.empty(max(2 * p, 1), dtype=torch.int32, device=dev)
-            nnz = torch.empty(1, dtype=torch.int64, device=dev)
-            ws_b = torch.empty(max(L.tc_build_csr_workspace(n, p, 8), 1), dtype=torch.uint8,
-                               device=dev)
-            L.tc_build_csr(n, src[:p], dst[:p], row_ptr, col, nnz, ws_b, stream=stream)
-            dag_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
-            dag_col = torch.empty(max(p, 1), dtype=torch.int32, device=dev)
-            m = torch.empty(1, dtype=torch.int64, device=dev)
-            ws_o = torch.empty(max(L.tc_orient_workspace(n, dag_col.numel()), 1), dtype=torch.uint8,
-                               device=dev)
-            L.tc_orient(n, row_ptr, col, L.TC_ORDER_DEGREE, dag_ptr, dag_col, m, ws_o,
+                if not k:
+                    continue
+                for key, arr in (("src", r.src), ("dst", r.dst)):
+                    if isinstance(arr, torch.Tensor) and arr.is_pinned():
+                        b[key][a: a + k].copy_(arr, non_blocking=True)
+                    else:  # stage through the lane's pinned buffer
+                        h = b["h_" + key]
+                        h.numpy()[a: a + k] = _host_array(arr)
+                        b[key][a: a + k].copy_(h[a: a + k], non_blocking=True)
+            offs = b["offs"]
+            offs[: 2 * G + 2].copy_(b["h_offs"][: 2 * G + 2], non_blocking=True)
+            pair_off, vtx_off = offs[: G + 1], offs[G + 1: 2 * G + 2]
+            if G > 1:
+                L.tc_pack_pairs(pair_off, vtx_off, b["src"][:p], b["dst"][:p], stream=stream)
+            sizes = b["sizes"]
+            L.tc_build_csr(n, b["src"][:p], b["dst"][:p], b["row_ptr"][: n + 1], b["col"],
+                           sizes[0:1], b["ws_build"], stream=stream)
+            L.tc_orient(n, b["row_ptr"][: n + 1], b["col"], L.TC_ORDER_DEGREE,
+                        b["dag_ptr"][: n + 1], b["dag_col"], sizes[1:2], b["ws_orient"],
                         stream=stream)
-            totals = torch.empty(max(G, 1), dtype=torch.int64, device=dev)
-            pv = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
-            ws_c = torch.empty(max(L.tc_count_batched_workspace(n), 1), dtype=torch.uint8,
-                               device=dev)
-            L.tc_count_batched(n, dag_ptr, dag_col, vtx_off, totals[:G], ws_c,
-                               per_vertex=pv[:n], tune=self.tune, stream=stream)
-            h_totals = torch.empty(max(G, 1), dtype=torch.int64, pin_memory=True)
-            h_pv = torch.empty(max(n, 1), dtype=torch.int64, pin_memory=True)
-            h_err = torch.empty(2, dtype=torch.int64, pin_memory=True)
-            h_totals.copy_(totals, non_blocking=True)
-            h_pv.copy_(pv, non_blocking=True)
-            h_err[0:1].copy_(nnz, non_blocking=True)
-            h_err[1:2].copy_(m, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(stream)
-        # device buffers stay referenced by the handle until collect()
-        keep = (src, dst, vtx_off, row_ptr, col, nnz, ws_b, dag_ptr, dag_col, m, ws_o, totals,
-                pv, ws_c)
-        return {"ev": ev, "si": si, "G": G, "off": off, "h": (h_totals, h_pv, h_err), "keep": keep}
+            L.tc_count_batched(n, b["dag_ptr"][: n + 1], b["dag_col"], vtx_off, b["totals"][:G],
+                               b["ws_count"], per_vertex=b["pv"][:n], tune=self.tune,
+                               stream=stream)
+            b["h_totals"][:G].copy_(b["totals"][:G], non_blocking=True)
+            b["h_pv"][:n].copy_(b["pv"][:n], non_blocking=True)
+            b["h_sizes"].copy_(sizes, non_blocking=True)
+            b["event"].record(stream)
+        return {"lane": lane_index, "G": G, "voff": voff}
 
     def ready(self, handle) -> bool:
-        return handle["ev"].query()
+        return self.slots[handle["lane"]]["event"].query()
 
     def collect(self, handle):
-        h_totals, h_pv, h_err = handle["h"]
-        self.busy[handle["si"]] = False
-        handle["keep"] = None
-        if int(h_err[0]) < 0:
-            raise self.lib.TcError(-int(h_err[0]), "reported by tc_build_csr on the device")
-        if int(h_err[1]) < 0:
-            raise self.lib.TcError(-int(h_err[1]), "reported by tc_orient on the device")
+        """(totals, per-vertex arrays, error): a device-side error fails the whole batch."""
+        b = self.slots[handle["lane"]]
+        G, voff = handle["G"], handle["voff"]
+        nnz, m = (int(x) for x in b["h_sizes"].tolist())
+        if nnz < 0:
+            return None, None, f"tc_build_csr: {self.lib.status_string(-nnz)}"
+        if m < 0:
+            return None, None, f"tc_orient: {self.lib.status_string(-m)}"
         mask = (1 << 64) - 1
-        G, off = handle["G"], handle["off"]
-        totals = [x & mask for x in h_totals[:G].tolist()]
-        pv_all = h_pv.numpy().view(np.uint64)
-        per_vertex = [pv_all[off[i]: off[i + 1]].copy() for i in range(G)]
-        return totals, per_vertex
-
-
-def _pinned(torch, a):
-    if isinstance(a, torch.Tensor):
-        return a
-    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32))
+        totals = [x & mask for x in b["h_totals"][:G].tolist()]
+        pv_all = b["h_pv"].numpy().view(np.uint64)
+        per_vertex = [pv_all[voff[i]: voff[i + 1]].copy() for i in range(G)]
+        return totals, per_vertex, None

@@ -136,3 +136,28 @@ def test_committed_profiles_name_commands_that_run_committed_files():
             workload = prog[prog.index("--workload") + 1]
             assert workload in bench.WORKLOADS, (name, workload)
             assert workload in name, (name, workload)
+
+
+def test_cpu_baseline_whole_and_sampled():
+    """The oracle baseline reports the whole-graph total when it counts every source, and a
+    count time scaled from a uniform prefix of sources otherwise."""
+    import graphgen
+    import oracle
+    s, d, n = graphgen.rmat(11, 16, 3)
+    s, d = s.numpy(), d.numpy()
+    T = oracle.triangles(n, s, d)
+    m = int(oracle.clean(n, s, d)[0][-1]) // 2
+    whole = bench.cpu_baseline("rmat-s11", s, d, n, m, frac=1.0)
+    assert whole["total"] == T and whole["kind"] == "oracle" and whole["value"] > 0
+    assert "scaled" not in whole["sample"]
+    part = bench.cpu_baseline("rmat-s11", s, d, n, m, frac=0.25)
+    assert part["total"] is None and part["value"] > 0
+    assert f"below {n // 4} of {n}" in part["sample"]
+
+
+def test_default_workload_is_scale24_with_a_stored_oracle_count():
+    assert bench.DEFAULT_WORKLOAD == "rmat-s24-ef16"
+    assert bench.WORKLOADS[bench.DEFAULT_WORKLOAD]["offset_bytes"] == 8
+    g = bench.golden_for(bench.DEFAULT_WORKLOAD)
+    assert g is not None and g["triangles"] > 2**32 and g["sum_t"] == 3 * g["triangles"]
+    assert bench.golden_for("rmat-s20-ef16") is None

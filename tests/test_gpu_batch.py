@@ -130,3 +130,69 @@ def test_batched_edge_cases(tc):
     with pytest.raises(_lib.TcError):
         _lib.tc_count_batched(b.n, br.dag_ptr, br.dag_col, b.vtx_off, br.totals[:1], br.ws_count,
                               tune={"small_max": 97})
+
+
+def _t_digest(t: np.ndarray) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(t, dtype="<u8").tobytes()).hexdigest()[:16]
+
+
+@pytest.mark.slow
+def test_full_batch_4096_against_oracle(tc):
+    """The whole 4096-graph batch (n log-uniform in [2^8, 2^16], average degree U(4, 64), half
+    Erdos-Renyi and half R-MAT; sum n = 4.7e7 > 2^24, so the folded wide hash runs; int64
+    offsets) as the benchmark runs it, a HIP-graph replay: every graph's total and every
+    t(v) of every graph against the oracle's stored counts (tests/golden/make_batch4096.py:
+    totals and a digest of each graph's t), the tuned total-only launch too, and a stratified
+    sample of graphs (the largest by edges and by vertices, and random ones) recounted here by
+    the oracle, totals and t(v)."""
+    import json
+    import os
+    import time
+
+    from paper_1909_02127_amd.batch import BatchRunner, PackedBatch
+    from tests import goldens
+    with open(os.path.join(goldens.GOLDEN_DIR, "batch4096_seed4.json")) as f:
+        gold = json.load(f)["graphs"]
+    specs = graphgen.batch_suite_spec(4096, seed=4)
+    t0 = time.perf_counter()
+    graphs = []
+    for i, g in enumerate(specs):
+        graphs.append(graphgen.batch_graph(g, device="cuda"))
+        if (i + 1) % 1024 == 0:
+            _say(f"batch 4096: generated {i + 1} graphs ({time.perf_counter() - t0:.0f}s)")
+    b = PackedBatch(graphs, offset_bytes=8)
+    assert b.n > (1 << 24)
+    assert b.graph_edges() == [g["m"] for g in gold]
+    want = [g["triangles"] for g in gold]
+    br = BatchRunner(b, per_vertex=True)
+    br.capture()
+    br.totals.fill_(-1)
+    br.replay()
+    totals, grand = br.results()
+    assert totals == want
+    assert grand == sum(want)
+    pv = br.pv[: b.n].cpu().numpy().view(np.uint64)
+    off = b.vtx_off.cpu().numpy()
+    bad = [i for i, g in enumerate(gold) if _t_digest(pv[off[i]: off[i + 1]]) != g["t_digest"]]
+    assert not bad, f"t digests differ for graphs {bad[:10]}"
+    _say(f"batch 4096: totals and t of all graphs match ({time.perf_counter() - t0:.0f}s)")
+    # total-only launches: default and the split the tuner picks on this batch
+    for tune in (None, {"small_max": 96}):
+        bt = BatchRunner(b, tune=tune)
+        bt.capture()
+        bt.replay()
+        assert bt.results()[0] == want, tune
+        del bt
+    # live oracle on a stratified sample
+    ms = np.array([g["m"] for g in gold])
+    ns = np.array([g["n"] for g in gold])
+    rng = np.random.default_rng(4)
+    pick = sorted(set(np.argsort(-ms)[:3].tolist()) | set(np.argsort(-ns)[:2].tolist())
+                  | set(rng.choice(len(gold), 6, replace=False).tolist()))
+    for i in pick:
+        s, d, n = graphs[i]
+        T, t = oracle.triangles(n, s.cpu().numpy(), d.cpu().numpy(), per_vertex=True)
+        assert T == totals[i], i
+        np.testing.assert_array_equal(pv[off[i]: off[i + 1]], t)
+    _say(f"batch 4096: live oracle on {len(pick)} graphs ({time.perf_counter() - t0:.0f}s)")

@@ -154,13 +154,16 @@ def _hub_graph(n_leaves, extra, seed):
 
 
 def test_hub_beyond_one_table_slice(tc):
+    """Under id order N+(0) holds 5000 ids: beyond four table slices, so the source binary
+    searches its row in memory; with both offset widths."""
     n, s, d = _hub_graph(5000, 40000, 11)
     _say("hub", n)
     T, t = _oracle(n, s, d)
     for order in (0, 1):
-        res, pv = _gpu(tc, n, s, d, order=order)
-        assert res.total == T
-        np.testing.assert_array_equal(pv, t)
+        for ob in (4, 8):
+            res, pv = _gpu(tc, n, s, d, order=order, offset_bytes=ob)
+            assert res.total == T
+            np.testing.assert_array_equal(pv, t)
 
 
 def test_dense_clique_all_source_classes(tc):
@@ -256,6 +259,42 @@ def test_rmat_scale20_full_parity(tc):
     rng = np.random.default_rng(0)
     for v in rng.choice(np.flatnonzero(t), 3, replace=False):
         assert oracle.vertex_triangles(n, hs, hd, int(v)) == int(t[v])
+
+
+@pytest.mark.slow
+def test_rmat_scale24_full_parity(tc):
+    """R-MAT scale 24, edge factor 16, seed 24 with int64 offsets, in the benchmark's launch
+    configuration: T > 2^32 and every t(v).  The oracle's counts are stored by
+    tests/golden/make_rmat_s24.py (minutes of CPU): the total, sum(t) = 3T, t(v) of 576
+    vertices (the 64 largest and 512 random ones) and the SHA-256 of the whole t array, which
+    checks every t(v) at once.  Two t(v) are also recomputed here from the raw pairs."""
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(goldens.GOLDEN_DIR, "rmat_s24_ef16_seed24.json")) as f:
+        g = json.load(f)
+    s, d, n = graphgen.rmat(24, 16, 24, device="cuda")
+    _say("scale 24: gpu", n, s.numel())
+    p = tc.Pipeline(n, s.numel(), offset_bytes=8)
+    p.enqueue(s, d, per_vertex=True)
+    r = p.result(per_vertex=True)
+    assert (r.nnz, r.m) == (g["nnz"], g["m"])
+    assert r.total == g["triangles"] and r.total > 2**32
+    p.count()
+    assert p.result().total == r.total
+    t = np.ascontiguousarray(r.per_vertex.cpu().numpy().view(np.uint64), dtype="<u8")
+    del r
+    _say("scale 24: T", g["triangles"], "checking t")
+    assert int(t.sum(dtype=np.uint64)) == g["sum_t"] == 3 * g["triangles"]
+    for v, c in g["t_sample"].items():
+        assert int(t[int(v)]) == c, v
+    assert hashlib.sha256(t.tobytes()).hexdigest() == g["t_sha256"]
+    hs, hd = s.cpu().numpy(), d.cpu().numpy()
+    del p
+    # vertices whose t is near 1e5 and near 1e3 (the definition scans all pairs once each)
+    for want in (10**5, 10**3):
+        v = int(min(g["t_sample"], key=lambda x: abs(g["t_sample"][x] - want)))
+        assert oracle.vertex_triangles(n, hs, hd, v) == int(t[v]), v
 
 
 @pytest.mark.parametrize("kicks", [-1, 1, 2])
