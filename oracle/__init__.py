@@ -56,6 +56,8 @@ def _load():
         lib.oracle_vertex_triangles.argtypes = [i64, i64, p, p, i32]
         lib.oracle_count_k4.restype = ctypes.c_uint64
         lib.oracle_count_k4.argtypes = [i64, p, p]
+        lib.oracle_count_diamonds.restype = ctypes.c_uint64
+        lib.oracle_count_diamonds.argtypes = [i64, i64, p, p]
         lib.oracle_kcore.restype = i64
         lib.oracle_kcore.argtypes = [i64, p, p, i32, p]
         lib.oracle_edge_support.restype = i64
@@ -173,6 +175,24 @@ def k4(n: int, src, dst, *, order: int = ORDER_DEGREE) -> int:
     row_ptr, col = clean(n, src, dst)
     dag_ptr, dag_col = orient(row_ptr, col, order)
     return count_k4(dag_ptr, dag_col)
+
+
+def count_diamonds(row_ptr: np.ndarray, col: np.ndarray, sources=None) -> int:
+    """Number of diamonds (two triangles sharing an edge, counted as subgraphs) of a
+    symmetric CSR.  With `sources`, only the shared edges {b, c} (b < c) whose lower
+    end b has an id below it count."""
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = _i32(col)
+    n = row_ptr.size - 1
+    lim = n if sources is None else max(0, min(int(sources), n))
+    return int(lib.oracle_count_diamonds(n, lim, _ptr(row_ptr), _ptr(col)))
+
+
+def diamonds(n: int, src, dst) -> int:
+    """Diamonds from raw pairs: clean -> count."""
+    row_ptr, col = clean(n, src, dst)
+    return count_diamonds(row_ptr, col)
 
 
 def kcore(row_ptr: np.ndarray, col: np.ndarray, k: int = 2) -> np.ndarray:

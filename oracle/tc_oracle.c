@@ -42,6 +42,9 @@
  *    that use it, i.e. how many times it appears as a query edge among the
  *    matches of M.  Each match u -> v -> w, u -> w adds one to each of its
  *    three edges.
+ *  - oracle_count_diamonds: the diamond query (two triangles sharing an edge),
+ *    a query with two neighbourhood-equivalence classes (Def. 3), each with its
+ *    own unique mapping order.
  *
  * Every function is pinned by the CPU test suite against brute force over
  * vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms and invariants.
@@ -388,5 +391,42 @@ uint64_t oracle_count_k4(int64_t n, const int64_t* dag_ptr, const int32_t* dag_c
     }
   }
   free(common);
+  return total;
+}
+
+/*
+ * Number of diamonds: matches of the 4-node query made of two triangles
+ * {a,b,c} and {b,c,d} that share the edge {b,c}, counted as subgraphs (a and d
+ * may or may not be adjacent; Def. 2 asks only that query edges map to data
+ * edges).  The query's nodes form two neighbourhood-equivalence classes
+ * (Def. 3): {b, c}, each adjacent to all three others, and {a, d}, each
+ * adjacent to b and c only.  The unique mapping order fixes one order inside
+ * each class, b < c and a < d (Alg. 1 "Generate_UMO"; vertex ids here), so each
+ * diamond subgraph is matched once.  Matching order b, c, a, d: every edge
+ * {b, c} with b < c; the candidates for a and for d are the vertices adjacent
+ * to both b and c (the query edges a-b, a-c; d-b, d-c), found by merging the
+ * two sorted rows of the symmetric CSR; every pair a < d of the k candidates
+ * is one match: k(k-1)/2.  Only edges whose lower end b < sources take part
+ * (sources = n: all).  Single-threaded.
+ */
+uint64_t oracle_count_diamonds(int64_t n, int64_t sources, const int64_t* row_ptr,
+                               const int32_t* col) {
+  uint64_t total = 0;
+  if (sources > n) sources = n;
+  for (int64_t b = 0; b < sources; ++b) {
+    for (int64_t e = row_ptr[b]; e < row_ptr[b + 1]; ++e) {
+      int64_t c = col[e];
+      if (c <= b) continue;
+      int64_t i = row_ptr[b], iend = row_ptr[b + 1];
+      int64_t j = row_ptr[c], jend = row_ptr[c + 1];
+      uint64_t k = 0;
+      while (i < iend && j < jend) {
+        if (col[i] < col[j]) ++i;
+        else if (col[j] < col[i]) ++j;
+        else { ++k; ++i; ++j; }
+      }
+      total += k * (k - 1) / 2;  /* k >= 2 only: 2-look-ahead on the candidates */
+    }
+  }
   return total;
 }

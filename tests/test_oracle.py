@@ -471,3 +471,110 @@ def test_k4_small_rmat_against_edge_enumeration(seed):
     assert want > 0
     for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
         assert oracle.k4(n, s.numpy(), d.numpy(), order=order) == want
+
+
+# -- diamonds (two triangles sharing an edge) -------------------------------------------------
+
+def _diamond_maps(n, s, d):
+    """The definition itself (Def. 2): injective maps of the query nodes (a, b, c, d) onto data
+    vertices that send the five query edges a-b, a-c, b-c, b-d, c-d onto data edges, divided
+    by the query's 4 automorphisms (swap a/d, swap b/c).  Tiny n only."""
+    import itertools
+    e = pins.edge_set(s, d)
+    adj = lambda x, y: frozenset((x, y)) in e  # noqa: E731
+    maps = sum(1 for a, b, c, dd in itertools.permutations(range(n), 4)
+               if adj(a, b) and adj(a, c) and adj(b, c) and adj(b, dd) and adj(c, dd))
+    assert maps % 4 == 0
+    return maps // 4
+
+
+def _diamond_subsets(n, s, d):
+    """Per 4-subset: with e of its six pairs present it holds C(e, 5) diamonds (K4 minus any one
+    edge is a diamond, and a diamond needs five edges).  Returns (diamonds, induced ones)."""
+    import itertools
+    from math import comb
+    e = pins.edge_set(s, d)
+    tot = ind = 0
+    for q in itertools.combinations(range(n), 4):
+        k = sum(1 for p in itertools.combinations(q, 2) if frozenset(p) in e)
+        tot += comb(k, 5) if k >= 5 else 0
+        ind += k == 5
+    return tot, ind
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_diamonds_definition_random_tiny(seed):
+    rng = np.random.default_rng(9100 + seed)
+    n = int(rng.integers(1, 11))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.3, 0.5, 0.7, 0.9, 1.0])), seed)
+    want = _diamond_maps(n, s, d)
+    assert _diamond_subsets(n, s, d)[0] == want
+    assert oracle.diamonds(n, s, d) == want
+    n2, s2, d2 = pins.noisy(n, s, d, seed)  # duplicates, reversed pairs, self-loops
+    assert oracle.diamonds(n2, s2, d2) == want
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_diamonds_are_induced_ones_plus_six_per_4_clique(seed):
+    """Every K4 holds six diamonds, every other diamond is induced: pins the count against
+    the 4-clique oracle and the induced count on random graphs up to 18 vertices."""
+    rng = np.random.default_rng(9200 + seed)
+    n = int(rng.integers(4, 19))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.3, 0.5, 0.7, 0.9])), seed)
+    tot, ind = _diamond_subsets(n, s, d)
+    assert oracle.diamonds(n, s, d) == tot == ind + 6 * oracle.k4(n, s, d)
+
+
+def test_diamonds_closed_forms():
+    from math import comb
+    for n in range(0, 12):
+        _, s, d = pins.complete(n)
+        assert oracle.diamonds(n, s, d) == 6 * comb(n, 4)
+    # wheels: W_3 = K4; from 4 rim vertices on, each spoke is the shared edge of one diamond
+    n, s, d = pins.wheel(3)
+    assert oracle.diamonds(n, s, d) == 6
+    for r in range(4, 12):
+        n, s, d = pins.wheel(r)
+        assert oracle.diamonds(n, s, d) == r
+    # book: the edge {0, 1} and k pages 2..k+1 adjacent to both
+    for k in range(0, 9):
+        s = [0] + [0] * k + [1] * k
+        d = [1] + list(range(2, k + 2)) * 2
+        assert oracle.diamonds(k + 2, s, d) == comb(k, 2)
+    # complete tripartite: an edge between two parts has the third part as common neighbours
+    for a, b, c in [(1, 1, 1), (2, 2, 2), (1, 2, 3), (3, 4, 5)]:
+        n, s, d = pins.complete_tripartite(a, b, c)
+        want = a * b * comb(c, 2) + a * c * comb(b, 2) + b * c * comb(a, 2)
+        assert oracle.diamonds(n, s, d) == want
+    # no two triangles share an edge
+    for k in range(0, 6):
+        n, s, d = pins.friendship(k)
+        assert oracle.diamonds(n, s, d) == 0
+    for n in range(3, 10):
+        assert oracle.diamonds(*pins.cycle(n)) == 0
+    for a, b in [(1, 1), (3, 3), (4, 7)]:
+        assert oracle.diamonds(*pins.complete_bipartite(a, b)) == 0
+    assert oracle.diamonds(*pins.petersen()) == 0
+    assert oracle.diamonds(0, [], []) == 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_diamonds_small_rmat_against_edge_support(seed):
+    """R-MAT scale 10: the diamonds sharing edge e are the pairs of triangles on e, so the count
+    is the sum over edges of C(support, 2), with the support from the oriented-graph support
+    oracle (another code path), in both orders; relabelling the vertices changes nothing."""
+    s, d, n = graphgen.rmat(10, 8, 400 + seed)
+    s, d = s.numpy(), d.numpy()
+    want = oracle.diamonds(n, s, d)
+    assert want > 0
+    rp, col = oracle.clean(n, s, d)
+    for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+        dp, dc = oracle.orient(rp, col, order)
+        _, sup = oracle.edge_support(dp, dc)
+        sup = sup.astype(np.int64)
+        assert int((sup * (sup - 1) // 2).sum()) == want
+    perm = np.random.default_rng(seed).permutation(n).astype(np.int32)
+    assert oracle.diamonds(n, perm[s], perm[d]) == want
+    # the bounded sample of the benchmark's baseline: all lower ends = the whole count
+    assert oracle.count_diamonds(rp, col, sources=n) == want
+    assert oracle.count_diamonds(rp, col, sources=0) == 0
