@@ -33,7 +33,8 @@ WORKLOADS = {
     "rmat-s24-ef16": dict(kind="rmat", scale=24, ef=16, seed=24, offset_bytes=8),
     "er-n1024-m8192": dict(kind="er", n=1024, m=8192, seed=0, offset_bytes=4),
     # 4096 graphs, n log-uniform in [2^8, 2^16], average degree U(4, 64), ER/R-MAT alternating
-    "batch-4096": dict(kind="batch", count=4096, seed=4, offset_bytes=8),
+    # int32 row offsets when the symmetric union fits them (it does: 2 * 8.07e8 < 2^31)
+    "batch-4096": dict(kind="batch", count=4096, seed=4, offset_bytes=None),
     # Poisson request stream: batch-suite graphs plus 2% R-MAT scale 22 (edge factor 16)
     "serve-poisson": dict(kind="serve", pool=256, seed=5, large_scale=22, large_frac=0.02),
     # triangle listing (every triangle as a (u, v, w) row) on the scale-20 graph
@@ -45,6 +46,11 @@ WORKLOADS = {
     "k4-rmat-s18-ef16": dict(kind="k4", scale=18, ef=16, seed=18, offset_bytes=4),
     # per-edge support (triangles on every edge) on the scale-20 graph
     "support-rmat-s20-ef16": dict(kind="support", scale=20, ef=16, seed=20, offset_bytes=4),
+    # the segmented-intersection operator (merge path per DAG edge, count and support)
+    # timed beside the wedge probe on the scale-20 graph
+    "intersect-rmat-s20-ef16": dict(kind="intersect", scale=20, ef=16, seed=20, offset_bytes=4),
+    # the diamond query (two triangles sharing an edge) on the scale-20 graph
+    "diamond-rmat-s20-ef16": dict(kind="diamond", scale=20, ef=16, seed=20, offset_bytes=4),
 }
 
 
@@ -541,7 +547,7 @@ def batch_main(args, spec):
     c1.record()
     torch.cuda.synchronize()
     ms_count = c0.elapsed_time(c1) / args.steps
-    alg = algorithmic_bytes(br.dag_ptr, br.dag_col, b.n, spec["offset_bytes"], per_vertex=False)
+    alg = algorithmic_bytes(br.dag_ptr, br.dag_col, b.n, b.offset_bytes, per_vertex=False)
     achieved = alg["bytes"] / (ms_count / 1e3) / 1e9
 
     rng = np.random.default_rng(0)
@@ -549,6 +555,12 @@ def batch_main(args, spec):
     oracle_ok = all(
         oracle.triangles(graphs[i][2], graphs[i][0].cpu().numpy(), graphs[i][1].cpu().numpy())
         == totals[i] for i in sample)
+    # every graph's total against the oracle's stored counts (tests/golden/make_batch4096.py)
+    gpath = os.path.join(ROOT, "tests", "golden", f"batch{spec['count']}_seed{spec['seed']}.json")
+    stored_ok = None
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            stored_ok = [g["triangles"] for g in json.load(f)["graphs"]] == totals
     G = b.G
     cb = None
     if not args.no_cpu_baseline:
@@ -575,7 +587,7 @@ def batch_main(args, spec):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": args.workload, "graphs": G, "n": b.n, "m": b.m,
-                   "offset_bytes": spec["offset_bytes"], "order": "degree",
+                   "offset_bytes": b.offset_bytes, "order": "degree",
                    "parallelism": "single-gpu", "tune": best},
         "plain": {"ms_per_batch": ms_plain, "host_wall_ms_per_batch": wall_plain,
                   "graphs_per_s": G / (ms_plain / 1e3)},
@@ -584,6 +596,7 @@ def batch_main(args, spec):
         "triangles": grand,
         "plain_equals_batched": plain_totals == totals,
         "oracle_sample_graphs": len(sample), "oracle_match": oracle_ok,
+        "oracle_stored_all_graphs_match": stored_ok,
         "roofline": {"bound": "hbm", "kernel": "count_kernel (tc_count_batched)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -846,6 +859,162 @@ def support_main(args, spec):
     print(json.dumps(out), flush=True)
 
 
+def _time_ms(fn, steps: int, warmup: int) -> float:
+    """Average ms of fn() over `steps` launches (after `warmup`), HIP events on torch's
+    current stream, the stream the library launches on."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def merge_bytes(dag_ptr, dag_col, n: int, offset_bytes: int) -> dict:
+    """Algorithmic bytes of the merge kernel of tc_segmented_intersect: every merge step
+    loads one 4-byte list element (S = the sum over the edges with d+(u) >= 2 and
+    d+(v) >= 1 of d+(u) + d+(v)), and every such edge its source, its v, its two scan
+    entries and the row bounds of u and v."""
+    import torch
+    o = offset_bytes
+    dp = (dag_ptr[1:] - dag_ptr[:-1]).to(torch.int64)
+    rows = torch.repeat_interleave(torch.arange(n, device=dag_ptr.device), dp)
+    du = dp[rows]
+    dv = dp[dag_col[: rows.numel()].to(torch.int64)]
+    live = (du >= 2) & (dv >= 1)
+    steps = int((du + dv)[live].sum().item())
+    edges = int(live.sum().item())
+    return {"bytes": 4 * steps + (4 + 4 + 16 + 4 * o) * edges, "merge_steps": steps,
+            "live_edges": edges}
+
+
+def intersect_main(args, spec):
+    """tc_segmented_intersect (merge path per DAG edge) against the wedge probe on the same
+    resident DAG: total-only and per-edge support, both checked against the oracle."""
+    import numpy as np
+    import torch
+    import paper_1909_02127_amd as tc
+
+    dev = torch.device("cuda:0")
+    s, d, n = make_graph(dict(spec, kind="rmat"), dev)
+    ob = spec["offset_bytes"]
+    pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, device=dev)
+    pipe.enqueue(s, d)
+    res = pipe.result()
+    T = res.total
+    ms_merge = _time_ms(lambda: pipe.intersect(), args.steps, args.warmup)
+    T_merge = pipe.intersect_total()
+    ms_merge_sup = _time_ms(lambda: pipe.intersect(support=True), args.steps, args.warmup)
+    sup_merge = pipe.supports().clone()
+    ms_hash = _time_ms(lambda: pipe.count(), args.steps, args.warmup)
+    ms_hash_sup = _time_ms(lambda: pipe.edge_support(), args.steps, args.warmup)
+    sup_hash = pipe.supports()
+    ok = T_merge == T and torch.equal(sup_merge, sup_hash)
+    cb = None
+    if not args.no_check or not args.no_cpu_baseline:
+        import oracle
+        rp, col = oracle.clean(n, s.cpu().numpy(), d.cpu().numpy())
+        dp, dc = oracle.orient(rp, col)
+        if not args.no_check:
+            T0, want = oracle.edge_support(dp, dc)
+            ok = ok and T0 == T and np.array_equal(sup_merge.cpu().numpy().view(np.uint32), want)
+        if not args.no_cpu_baseline:
+            cb = oracle_prefix_baseline(
+                lambda a, b, sources: oracle.count(a, b, threads=1, sources=sources), dp, dc, 1 / 2,
+                                        lambda r, k: int(dp[k]) / 1e9, "GTEPS",
+                                        "the count (node iterator, sorted merge per edge)")
+    mb = merge_bytes(pipe.dag_ptr, pipe.dag_col, n, ob)
+    # the kernel alone: the full call minus its edge-work pass and scan, timed separately
+    # would need a split entry point; the whole call is reported and the roofline uses it
+    achieved = mb["bytes"] / (ms_merge / 1e3) / 1e9
+    out = {
+        "metric": "GTEPS of the segmented intersection (bit-exact vs oracle)",
+        "value": res.m / (ms_merge / 1e3) / 1e9,
+        "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_merge,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": res.m, "triangles": T,
+                   "offset_bytes": ob, "order": "degree", "parallelism": "single-gpu"},
+        "ms": {"merge_total": ms_merge, "merge_support": ms_merge_sup,
+               "hash_total": ms_hash, "hash_support": ms_hash_sup},
+        "merge_over_hash": {"total": ms_merge / ms_hash, "support": ms_merge_sup / ms_hash_sup},
+        "oracle_match": bool(ok),
+        "roofline": {"bound": "hbm", "kernel": "tc_segmented_intersect (whole call)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": mb["bytes"], "merge_steps": mb["merge_steps"]},
+    }
+    if cb is not None:
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+def diamond_main(args, spec):
+    """tc_count_diamonds on the resident DAG: diamonds/s, checked against the oracle."""
+    import numpy as np
+    import torch
+    import paper_1909_02127_amd as tc
+
+    dev = torch.device("cuda:0")
+    s, d, n = make_graph(dict(spec, kind="rmat"), dev)
+    ob = spec["offset_bytes"]
+    pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, device=dev)
+    pipe.enqueue(s, d)
+    res = pipe.result()
+    ms = _time_ms(lambda: pipe.diamonds(), args.steps, args.warmup)
+    D = pipe.diamond_count()
+    ok = None
+    cb = None
+    if not args.no_check or not args.no_cpu_baseline:
+        import oracle
+        hs, hd = s.cpu().numpy(), d.cpu().numpy()
+        rp, col = oracle.clean(n, hs, hd)
+        if not args.no_check:
+            dp, dc = oracle.orient(rp, col)
+            _, sup = oracle.edge_support(dp, dc)
+            w = sup.astype(np.uint64)
+            ok = D == int((w * (w - 1) // 2).sum())
+        if not args.no_cpu_baseline:
+            # the oracle's diamond enumeration on the edges whose lower end lies in a prefix
+            # of the (permuted) ids, scaled to all of them
+            k = n // 8
+            t0 = time.perf_counter()
+            oracle.count_diamonds(rp, col, sources=k)
+            dt = (time.perf_counter() - t0) * n / k
+            cb = {"value": res.m / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                  "sample": f"the diamond enumeration for the edges whose lower end is below "
+                            f"{k} of {n} ids, {dt * k / n:.1f}s, scaled to {dt:.1f}s for all"}
+    # support enumeration (the count's bytes + support updates) and the C(s, 2) reduce
+    alg = algorithmic_bytes(pipe.dag_ptr, pipe.dag_col, n, ob, per_vertex=False)
+    b = alg["bytes"] + 8 * res.total + 20 * res.m + 4 * res.m
+    achieved = b / (ms / 1e3) / 1e9
+    out = {
+        "metric": "diamonds/s (bit-exact vs oracle)",
+        "value": D / (ms / 1e3),
+        "unit": "diamonds/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": res.m, "diamonds": D,
+                   "offset_bytes": ob, "order": "degree", "parallelism": "single-gpu"},
+        "gteps": res.m / (ms / 1e3) / 1e9,
+        "oracle_match": ok,
+        "roofline": {"bound": "hbm", "kernel": "count_kernel (support kind) + C(s,2) reduce",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b},
+    }
+    if cb is not None:
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
 def ablation_main(args, spec):
     """Time the fused count and the paper's materialised two-iteration advance (with and
     without the NE filter) in both orders on one graph; all counts must agree."""
@@ -1023,6 +1192,10 @@ def main():
         return ablation_main(args, spec)
     if spec["kind"] == "k4":
         return k4_main(args, spec)
+    if spec["kind"] == "intersect":
+        return intersect_main(args, spec)
+    if spec["kind"] == "diamond":
+        return diamond_main(args, spec)
     out = graph_line(args, args.workload, dev, cpu=not args.no_cpu_baseline)
     if args.workload == DEFAULT_WORKLOAD and args.secondary:
         # the scale-20 graph as well: its own timed steps, roofline and oracle check

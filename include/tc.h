@@ -24,6 +24,11 @@
  *   tc_edge_support      for every edge, the number of matches (triangles)
  *                        that use it.
  *   tc_count_k4          the 4-clique query (the next clique after the triangle).
+ *   tc_segmented_intersect  the segmented-intersection operator: a merge of
+ *                        N+(u) and N+(v) for every oriented edge (count and
+ *                        per-edge support).
+ *   tc_count_diamonds    the diamond query (two triangles sharing an edge), a
+ *                        query with two neighbourhood-equivalence classes.
  *   tc_ne_filter,        the paper's own pipeline, kept for comparison: the NE
  *   tc_count_bfs         candidate filter and the two-iteration advance with
  *                        its partial and complete matches written out.
@@ -96,6 +101,11 @@ typedef struct tc_tune {
                             searched instead): 0 = default (48), 1 to 1024 = that many,
                             -1 = none, so every key takes the stash or the sorted
                             fallback (exercises those probe modes) */
+  int32_t split_log2;    /* equal-work quanta: a workgroup-mode source u whose work
+                            w(u) = sum of d+(v) over v in N+(u) (its wedges) exceeds
+                            2^split_log2 is cut into ceil(w(u) / 2^split_log2) parts
+                            (at most 1024) that any workgroup may take; 0 = default
+                            (2^20), 1 to 40 = that quantum, -1 = never split */
 } tc_tune;
 
 /* Read-only view of a CSR graph in device memory. */
@@ -284,6 +294,59 @@ tc_status tc_list_triangles(const tc_csr* dag, int32_t* triples, int64_t capacit
 tc_status tc_edge_support(const tc_csr* dag, uint32_t* support, int64_t capacity, int64_t* m_out,
                           uint64_t* total, const tc_tune* tune, void* ws, size_t* ws_bytes,
                           void* stream);
+
+/*
+ * tc_segmented_intersect - the segmented-intersection operator (Sec. II-B
+ * lists it with advance, filter and compute) applied to the triangle query:
+ * for every oriented edge (u, v) the sorted lists N+(u) and N+(v) are
+ * intersected by a merge, and every common out-neighbour w closes the match
+ * u -> v -> w (Alg. 1's non-tree edge (u, w) exists and so does (v, w)).  Under
+ * the unique mapping order each triangle is found once, at its lowest edge, so
+ * the number of common out-neighbours summed over the edges is |M|/|Q|.  The
+ * edge-centric alternative to tc_count's wedge probe; same results.
+ *
+ *   dag           oriented CSR (as written by tc_orient, either order); rows
+ *                 must be ascending
+ *   edge_capacity upper bound on m = dag row_ptr[n] (e.g. the DAG column
+ *                 capacity given to tc_orient); sizes the workspace
+ *   total         device uint64[1] (written): T, or 0 on a capacity error
+ *   support       device uint32[edge_capacity] or NULL: when non-NULL, entry e
+ *                 (aligned with dag->col) receives the triangles on edge
+ *                 (u, dag->col[e]), as tc_edge_support writes them
+ *   m_out         device int64[1] (written): m, or -TC_ERR_CAPACITY when m >
+ *                 edge_capacity (then nothing else is computed)
+ *   ws, ws_bytes  workspace; 16 bytes per edge of capacity plus scan partials.
+ * Load balance: the merge lengths d+(u) + d+(v) of all edges (0 where the
+ * look-ahead of Sec. III-C rules the edge out) are scanned into one merge
+ * space, cut into equal chunks of merge steps.
+ */
+tc_status tc_segmented_intersect(const tc_csr* dag, int64_t edge_capacity, uint64_t* total,
+                                 uint32_t* support, int64_t* m_out, void* ws, size_t* ws_bytes,
+                                 void* stream);
+
+/*
+ * tc_count_diamonds - number of diamonds: matches of the query made of two
+ * triangles {a, b, c} and {b, c, d} sharing the edge {b, c}, counted as
+ * subgraphs (a and d may be adjacent).  The query has two neighbourhood-
+ * equivalence classes (Def. 3): {b, c} (adjacent to every other node) and
+ * {a, d} (adjacent to b and c only).  The unique mapping order fixes one order
+ * in each class (Alg. 1 "Generate_UMO"): {b, c} is matched as an oriented edge,
+ * and the candidates for a and d are the common neighbours of b and c, of
+ * which every pair a < d is one match.  So the count is the sum over the edges
+ * of C(s, 2), s = the edge's support (triangles on it); an edge with s < 2
+ * adds nothing (the look-ahead of Sec. III-C).
+ *
+ *   dag           oriented CSR (as written by tc_orient, either order)
+ *   edge_capacity upper bound on m = dag row_ptr[n]; sizes the workspace
+ *   total         device uint64[1] (written): the number of diamonds
+ *   m_out         device int64[1] (written): m, or -TC_ERR_CAPACITY when m >
+ *                 edge_capacity (then total is 0)
+ *   tune          launch parameters of the support enumeration, or NULL
+ *   ws, ws_bytes  workspace; O(n) bytes plus 4 bytes per edge of capacity.
+ */
+tc_status tc_count_diamonds(const tc_csr* dag, int64_t edge_capacity, uint64_t* total,
+                            int64_t* m_out, const tc_tune* tune, void* ws, size_t* ws_bytes,
+                            void* stream);
 
 /*
  * tc_ne_filter - the candidate filter of Alg. 1: a data vertex can stand for a

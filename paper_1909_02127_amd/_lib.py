@@ -42,16 +42,18 @@ class tc_csr(ctypes.Structure):
 
 class tc_tune(ctypes.Structure):
     _fields_ = [("small_max", ctypes.c_int32), ("probe", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("max_kicks", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("max_kicks", ctypes.c_int32),
+                ("split_log2", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"small_max": self.small_max, "probe": self.probe,
-                "blocks_per_cu": self.blocks_per_cu, "max_kicks": self.max_kicks}
+                "blocks_per_cu": self.blocks_per_cu, "max_kicks": self.max_kicks,
+                "split_log2": self.split_log2}
 
 
 def make_tune(small_max: int = 0, probe: int = TC_PROBE_AUTO, blocks_per_cu: int = 0,
-              max_kicks: int = 0) -> tc_tune:
-    return tc_tune(small_max, probe, blocks_per_cu, max_kicks)
+              max_kicks: int = 0, split_log2: int = 0) -> tc_tune:
+    return tc_tune(small_max, probe, blocks_per_cu, max_kicks, split_log2)
 
 
 def _tune_ref(tune):
@@ -90,6 +92,10 @@ def _load() -> ctypes.CDLL:
     lib.tc_count_bfs.argtypes = [csr, p, i64, p, i64, p, p, p, sz, p]
     lib.tc_edge_support.restype = i32
     lib.tc_edge_support.argtypes = [csr, p, i64, p, p, tune, p, sz, p]
+    lib.tc_segmented_intersect.restype = i32
+    lib.tc_segmented_intersect.argtypes = [csr, i64, p, p, p, p, sz, p]
+    lib.tc_count_diamonds.restype = i32
+    lib.tc_count_diamonds.argtypes = [csr, i64, p, p, tune, p, sz, p]
     lib.tc_list_triangles.restype = i32
     lib.tc_list_triangles.argtypes = [csr, p, i64, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
@@ -306,6 +312,46 @@ def tc_edge_support(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_edge_support, ws, ctypes.byref(csr), _ptr(support), support.numel(),
              _ptr(m_out), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_segmented_intersect_workspace(n: int, edge_capacity: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_segmented_intersect, ctypes.byref(csr), edge_capacity, None, None,
+                     None)
+
+
+def tc_segmented_intersect(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                           total: torch.Tensor, m_out: torch.Tensor, ws: torch.Tensor, *,
+                           support: torch.Tensor | None = None, stream=None) -> None:
+    """Merge-path intersection of N+(u) and N+(v) for every DAG edge: total (int64[1])
+    receives T; with support (4-byte counts, at least dag_col.numel() entries) every
+    edge's triangles; m_out (int64[1]) receives m or -TC_ERR_CAPACITY.  The edge capacity
+    is dag_col.numel()."""
+    if m_out.dtype != torch.int64 or m_out.numel() != 1:
+        raise ValueError("m_out must be int64[1]")
+    cap = dag_col.numel()
+    if support is not None and (support.element_size() != 4 or support.numel() < cap):
+        raise ValueError("support must hold 4-byte counts for every dag_col entry")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_segmented_intersect, ws, ctypes.byref(csr), cap, _ptr(total),
+             _ptr(support), _ptr(m_out), stream=stream)
+
+
+def tc_count_diamonds_workspace(n: int, edge_capacity: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_count_diamonds, ctypes.byref(csr), edge_capacity, None, None, None)
+
+
+def tc_count_diamonds(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                      total: torch.Tensor, m_out: torch.Tensor, ws: torch.Tensor, *, tune=None,
+                      stream=None) -> None:
+    """Number of diamonds (two triangles sharing an edge) into total (int64[1]); m_out
+    (int64[1]) receives m or -TC_ERR_CAPACITY.  The edge capacity is dag_col.numel()."""
+    if m_out.dtype != torch.int64 or m_out.numel() != 1:
+        raise ValueError("m_out must be int64[1]")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count_diamonds, ws, ctypes.byref(csr), dag_col.numel(), _ptr(total),
+             _ptr(m_out), _tune_ref(tune), stream=stream)
 
 
 def tc_list_triangles_workspace(n: int) -> int:

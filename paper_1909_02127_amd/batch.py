@@ -20,7 +20,9 @@ from .pipeline import _bytes
 class PackedBatch:
     """Union CSR of G graphs given as lists of per-graph (src, dst, n) with local ids."""
 
-    def __init__(self, graphs, *, device="cuda", offset_bytes: int = 8):
+    def __init__(self, graphs, *, device="cuda", offset_bytes: int | None = None):
+        """offset_bytes: width of the union's row offsets; None picks 4 when the symmetric
+        union fits int32 offsets (2 * pairs < 2^31), else 8."""
         dev = torch.device(device)
         self.device = dev
         ns = [int(n) for _, _, n in graphs]
@@ -35,6 +37,9 @@ class PackedBatch:
         dst = torch.cat([d.to(dev, torch.int64) + o for (_, d, _), o in zip(graphs, off)]) \
             if graphs else torch.zeros(0, dtype=torch.int64, device=dev)
         self.num_pairs = src.numel()
+        if offset_bytes is None:
+            offset_bytes = 4 if 2 * self.num_pairs < 2**31 else 8
+        self.offset_bytes = offset_bytes
         src, dst = src.to(torch.int32), dst.to(torch.int32)
         odt = torch.int32 if offset_bytes == 4 else torch.int64
         self.offset_dtype = odt

@@ -122,7 +122,31 @@ struct CountState {
   int32_t class_cursor[kNumClasses];
   int32_t large_cursor;
   int32_t small_cursor;
-  int32_t pad[6];
+  int32_t split_count;  // entries taken in the split table
+  int32_t pad[5];
+};
+
+// Equal-work quanta.  The work of a source is w(u) = sum of d+(v) over its
+// middles v, the wedges it enumerates.  A workgroup-mode source with w(u) above
+// the quantum is cut into P = ceil(w(u) / quantum) parts (at most kMaxParts):
+// part k takes the middles k, k + P, k + 2P, ... (each part then holds about
+// w(u) / P wedges).  Its workgroup publishes it in the split table, and parts
+// are claimed through the entry's counter, by that workgroup and by any other
+// that has run out of sources, so a heavy source no longer sets the tail.
+constexpr int kSplitCap = 4096;       // split table entries (a fuller table keeps parts local)
+constexpr int32_t kMaxParts = 1024;
+constexpr int kSplitDefaultLog2 = 20;  // default quantum: 2^20 wedges
+
+// The workgroup's schedule in LDS (written by thread 0).
+constexpr int kSchedState = 0, kSchedU = 1, kSchedPart = 2, kSchedParts = 3, kSchedIdx = 4,
+              kSchedEnt = 5, kSchedHelp = 6, kSchedHelpEnd = 7, kSchedLocalK = 8, kSchedWords = 9;
+constexpr int32_t kStateDone = 0, kStateWork = 1, kStateNew = 2, kStateSkip = 3;
+constexpr int32_t kNoEntry = -1, kLocalEntry = -2;
+
+struct SplitEntry {
+  unsigned long long word;  // (P << 32) | u once published, 0 before
+  int32_t next;             // parts claimed so far
+  int32_t pad;
 };
 
 constexpr int kSmallGrab = 16;  // wave-mode sources per run in the dynamic hand-out
@@ -216,9 +240,11 @@ void launch_bins(int64_t n, const OffT* row_ptr, CountState* st, int32_t* list, 
   bin_write_kernel<OffT><<<grid, 256, 0, s>>>(n, row_ptr, st, list, small_max);
 }
 
-__global__ void init_state_kernel(CountState* st, uint64_t* total) {
+__global__ void init_state_kernel(CountState* st, SplitEntry* split, uint64_t* total) {
   int32_t* p = reinterpret_cast<int32_t*>(st);
   for (int i = threadIdx.x; i < (int)(sizeof(CountState) / 4); i += blockDim.x) p[i] = 0;
+  int32_t* q = reinterpret_cast<int32_t*>(split);
+  for (int i = threadIdx.x; i < kSplitCap * (int)(sizeof(SplitEntry) / 4); i += blockDim.x) q[i] = 0;
   if (threadIdx.x == 0) *total = 0;
 }
 
@@ -588,6 +614,12 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
   return hv;
 }
 
+// One of the equal-work parts of a split source: the middles i = part + j parts.
+struct Part {
+  int64_t part;
+  int64_t parts;
+};
+
 // All middles v of source u handled by this wave: v = N+(u)[i] for
 // i = gwave, gwave + Waves, ...; 64 of them are prefetched per batch.  Lists of
 // kShortMax or more ids are streamed one at a time; shorter ones are walked
@@ -596,18 +628,23 @@ template <int Waves, int K, int Mode, bool Wide, typename OffT>
 __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
                                  const OffT* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                  uint64_t* __restrict__ tv, const Table& t, const Slice& sl,
-                                 const WaveScratch& ws, const ListCtx& lc) {
+                                 const WaveScratch& ws, const ListCtx& lc, const Part& pt) {
   constexpr bool PV = K == kKindPerVertex;
   const int lane = lane_id();
   const int gwave = Waves == 1 ? 0 : (int)threadIdx.x / kWave;
   // every middle is a key of this table (one slice): (u, v) counts go to its slot
   const bool local_v = Mode != kModeGlobal && (int64_t)sl.keys == d;
+  // a workgroup-mode source may be split: part k of P takes the middles i = k + j P
+  const int64_t first = Waves > 1 ? pt.part : 0;
+  const int64_t stride = Waves > 1 ? pt.parts : 1;
+  const int64_t mine = first < d ? (d - first + stride - 1) / stride : 0;
   uint64_t src_hits = 0;
-  for (int64_t i0 = 0; i0 < d; i0 += (int64_t)Waves * kWave) {
-    const int64_t i = i0 + (int64_t)Waves * lane + gwave;
+  for (int64_t i0 = 0; i0 < mine; i0 += (int64_t)Waves * kWave) {
+    const int64_t j = i0 + (int64_t)Waves * lane + gwave;
+    const int64_t i = first + j * stride;
     int32_t v = 0;
     OffT vb = 0, ve = 0;
-    if (i < d) {
+    if (j < mine) {
       v = nbrs[i];
       vb = row_ptr[v];
       ve = row_ptr[v + 1];
@@ -687,7 +724,8 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
                                    const OffT* __restrict__ row_ptr,
                                    const int32_t* __restrict__ col, uint64_t* __restrict__ tv,
                                    const Table& t, const WaveScratch& ws, int max_keys,
-                                   int max_kicks, bool force_sorted, const ListArgs& la) {
+                                   int max_kicks, bool force_sorted, const ListArgs& la,
+                                   const Part& pt) {
   constexpr bool PV = K == kKindPerVertex;
   constexpr bool CNT = counted(K);
   const int lane = lane_id();
@@ -710,7 +748,7 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
     sl.stash_n = 0;
     sl.gkeys = nbrs;
     const uint64_t src_hits =
-        scan_middles<Waves, K, kModeGlobal, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
+        scan_middles<Waves, K, kModeGlobal, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc, pt);
     if (PV && src_hits && lane == 0)
       atomicAdd((unsigned long long*)&tv[u], (unsigned long long)src_hits);
     group_sync<Waves>();
@@ -757,11 +795,11 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
     }
     uint64_t src_hits;
     if (mode == kModeCuckoo)
-      src_hits = scan_middles<Waves, K, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
+      src_hits = scan_middles<Waves, K, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc, pt);
     else if (mode == kModeStash)
-      src_hits = scan_middles<Waves, K, kModeStash, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
+      src_hits = scan_middles<Waves, K, kModeStash, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc, pt);
     else
-      src_hits = scan_middles<Waves, K, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc);
+      src_hits = scan_middles<Waves, K, kModeSorted, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc, pt);
     wave_hits += src_hits;
     if (K == kKindSupport) {
       // the edges (u, w): hits counted on w's slot
@@ -796,6 +834,8 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
 
 // Runtime parameters of one count launch.
 struct CountArgs {
+  SplitEntry* split;   // split table (kSplitCap entries)
+  uint64_t quantum;    // wedges per part of a split source; 0: never split
   const int32_t* gid;  // batched mode: graph of each vertex (-1: none); else null
   uint64_t* totals;    // batched mode: per-graph totals; else null
   uint64_t* src_cnt;   // listing, first pass: hits of each source; else null
@@ -850,23 +890,118 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
     if (g >= 0) pend_h += h;
   };
 
-  // A workgroup's first source is static (its id); later ones come from the
-  // cursor, offset past that first round, so small launches need few atomics.
+  // Workgroup-mode sources.  Thread 0 schedules, the workgroup follows: the
+  // next piece of work is a part of the split source being drained, else the
+  // next source of the list (its first one static, by the workgroup's id, later
+  // ones from the cursor), else, once the list is used up, a part of a split
+  // source some other workgroup published.  The schedule lives in LDS so that
+  // process_source has one call site.
   const Table big = table_at<PV>(smem, kSideMax);
-  for (int32_t idx = blockIdx.x; idx < n_large;) {
-    const int32_t u = list[idx];
+  __shared__ int32_t sched[kSchedWords];
+  const bool splitting = K != kKindList && args.quantum != 0;
+  if (threadIdx.x == 0) {
+    sched[kSchedIdx] = blockIdx.x;
+    sched[kSchedEnt] = kNoEntry;
+    sched[kSchedHelp] = 0;
+    sched[kSchedHelpEnd] = -1;
+  }
+  while (true) {
+    __syncthreads();  // every thread has read the previous step's schedule
+    if (threadIdx.x == 0) {
+      int32_t state = kStateDone;
+      int32_t ent = sched[kSchedEnt];
+      if (ent != kNoEntry) {
+        const int32_t k = ent >= 0 ? atomicAdd(&args.split[ent].next, 1) : sched[kSchedLocalK]++;
+        if (k < sched[kSchedParts]) {
+          sched[kSchedPart] = k;
+          state = kStateWork;
+        } else {
+          ent = kNoEntry;
+        }
+      }
+      if (state == kStateDone && sched[kSchedIdx] < n_large) {
+        sched[kSchedU] = list[sched[kSchedIdx]];
+        sched[kSchedIdx] = (int32_t)gridDim.x + atomicAdd(&st->large_cursor, 1);
+        state = kStateNew;
+      }
+      if (state == kStateDone && splitting) {
+        if (sched[kSchedHelpEnd] < 0) {
+          const int32_t c = __hip_atomic_load(&st->split_count, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+          sched[kSchedHelpEnd] = c < kSplitCap ? c : kSplitCap;
+        }
+        while (state == kStateDone && sched[kSchedHelp] < sched[kSchedHelpEnd]) {
+          const int32_t e = sched[kSchedHelp]++;
+          // 0 until published; an unpublished entry is drained by its own workgroup
+          const unsigned long long word = __hip_atomic_load(&args.split[e].word, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+          if (!word) continue;
+          const int32_t parts = (int32_t)(word >> 32);
+          const int32_t k = atomicAdd(&args.split[e].next, 1);
+          if (k < parts) {
+            ent = e;
+            sched[kSchedU] = (int32_t)(uint32_t)word;
+            sched[kSchedParts] = parts;
+            sched[kSchedPart] = k;
+            state = kStateWork;
+          }
+        }
+      }
+      sched[kSchedEnt] = ent;
+      sched[kSchedState] = state;
+    }
+    __syncthreads();
+    const int32_t state = sched[kSchedState];
+    if (state == kStateDone) break;
+    const int32_t u = sched[kSchedU];
     const int64_t beg = row_ptr[u];
     const int64_t d = (int64_t)row_ptr[u + 1] - beg;
+    if (state == kStateNew) {
+      // a new source: its work w(u), the out-degrees of its middles summed over
+      // the workgroup, decides whether it is split
+      int32_t parts = 1;
+      if (splitting) {
+        uint64_t w = 0;
+        for (int64_t i = threadIdx.x; i < d; i += kBlock) {
+          const int32_t v = col[beg + i];
+          w += (uint64_t)(row_ptr[v + 1] - row_ptr[v]);
+        }
+        w = (uint64_t)wave_sum((int64_t)w);
+        uint64_t* red = reinterpret_cast<uint64_t*>(big.slot);
+        if (lane == 0) red[wave] = w;
+        __syncthreads();
+        w = red[0] + red[1] + red[2] + red[3];
+        const uint64_t p = (w + args.quantum - 1) / args.quantum;
+        parts = p < 2 ? 1 : (p > (uint64_t)kMaxParts ? kMaxParts : (int32_t)p);
+      }
+      if (threadIdx.x == 0) {
+        sched[kSchedParts] = parts;
+        sched[kSchedPart] = 0;
+        if (parts > 1) {
+          int32_t slot = atomicAdd(&st->split_count, 1);
+          if (slot < kSplitCap) {
+            atomicExch(&args.split[slot].word, ((unsigned long long)parts << 32) | (uint32_t)u);
+            const int32_t k = atomicAdd(&args.split[slot].next, 1);
+            sched[kSchedPart] = k;
+            sched[kSchedEnt] = k < parts ? slot : kNoEntry;
+            if (k >= parts) sched[kSchedState] = kStateSkip;  // helpers took every part
+          } else {
+            sched[kSchedEnt] = kLocalEntry;  // table full: this workgroup takes every part
+            sched[kSchedLocalK] = 1;
+          }
+        }
+      }
+      __syncthreads();
+      if (sched[kSchedState] == kStateSkip) continue;
+    }
+    const Part pt{sched[kSchedPart], sched[kSchedParts]};
     const uint64_t h = process_source<kWavesPerBlock, K, Wide, OffT>(
-        u, beg, d, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, args.list);
+        u, beg, d, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, args.list,
+        pt);
     hits += h;
     credit(u, h);
     if (args.src_cnt && h && lane == 0)
       atomicAdd((unsigned long long*)&args.src_cnt[u], (unsigned long long)h);
-    if (threadIdx.x == 0) big.meta[2] = (int32_t)gridDim.x + atomicAdd(&st->large_cursor, 1);
-    __syncthreads();
-    idx = big.meta[2];
-    __syncthreads();
   }
 
   const Table mine = table_at<PV>(smem + wave * small_bytes_per_wave(PV), kSmallSide);
@@ -903,7 +1038,7 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
       }
       const uint64_t h = process_source<1, K, Wide, OffT>(u, beg, d, row_ptr, col, tv, mine, ws,
                                                           kSmallMax, args.max_kicks,
-                                                          args.force_sorted, args.list);
+                                                          args.force_sorted, args.list, Part{0, 1});
       hits += h;
       credit(u, h);
       if (args.src_cnt && h && lane == 0)
@@ -942,6 +1077,7 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t len, int32_t v) {
 
 struct CountLayout {
   CountState* st;
+  SplitEntry* split;
   int32_t* list;
   uint64_t* total_scratch;
   int32_t* gid;  // batched mode only
@@ -952,6 +1088,7 @@ CountLayout carve_count(void* ws, int64_t n, bool batched) {
   Carver c(ws);
   CountLayout L;
   L.st = c.take<CountState>(1);
+  L.split = c.take<SplitEntry>(kSplitCap);
   L.list = c.take<int32_t>(n);
   L.total_scratch = c.take<uint64_t>(1);
   L.gid = batched ? c.take<int32_t>(n) : nullptr;
@@ -964,6 +1101,7 @@ struct Tune {
   int force_sorted;
   int blocks_per_cu;  // 0: occupancy limit
   int max_kicks;      // cuckoo placements per key before the stash
+  uint64_t quantum;   // wedges per part of a split source; 0: never split
 };
 
 tc_status read_tune(const tc_tune* tune, Tune* out) {
@@ -971,7 +1109,12 @@ tc_status read_tune(const tc_tune* tune, Tune* out) {
   out->force_sorted = 0;
   out->blocks_per_cu = 0;
   out->max_kicks = kMaxKicks;
+  out->quantum = uint64_t(1) << kSplitDefaultLog2;
   if (!tune) return TC_OK;
+  if (tune->split_log2 < -1 || tune->split_log2 > 40)
+    return fail(TC_ERR_INVALID_ARG, "tc_tune.split_log2 must be in [-1, 40]");
+  if (tune->split_log2 == -1) out->quantum = 0;
+  else if (tune->split_log2 > 0) out->quantum = uint64_t(1) << tune->split_log2;
   if (tune->max_kicks < -1 || tune->max_kicks > 1024)
     return fail(TC_ERR_INVALID_ARG, "tc_tune.max_kicks must be in [-1, 1024]");
   if (tune->max_kicks != 0) out->max_kicks = tune->max_kicks < 0 ? 0 : tune->max_kicks;
@@ -1020,6 +1163,8 @@ CountArgs base_args(const Tune& tune) {
   args.list = ListArgs{nullptr, nullptr, 0, nullptr};
   args.force_sorted = tune.force_sorted;
   args.max_kicks = tune.max_kicks;
+  args.quantum = tune.quantum;
+  args.split = nullptr;
   return args;
 }
 
@@ -1027,8 +1172,10 @@ CountArgs base_args(const Tune& tune) {
 // per 16 vertices so that a small graph launches a small grid.
 template <int K, typename OffT>
 void launch_count(int64_t n, const OffT* row_ptr, const int32_t* col, const CountLayout& L,
-                  uint64_t* tot, uint64_t* tv, const CountArgs& args, const Tune& tune,
+                  uint64_t* tot, uint64_t* tv, const CountArgs& args_in, const Tune& tune,
                   hipStream_t s) {
+  CountArgs args = args_in;
+  args.split = L.split;
   const int64_t cap = (n + 15) / 16;
   if (n <= (int64_t(1) << 24)) {
     const int grid = (int)std::min<int64_t>(count_grid<K, false, OffT>(tune.blocks_per_cu), cap);
@@ -1046,7 +1193,7 @@ tc_status count_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint64_
   constexpr int K = PV ? kKindPerVertex : kKindTotal;
   uint64_t* tot = total ? total : L.total_scratch;
   CountArgs args = base_args(tune);
-  init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
+  init_state_kernel<<<1, 256, 0, s>>>(L.st, L.split, tot);
   if (PV) zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(tv, n);
   if (totals) {
     zero_u64_kernel<<<grid_for(num_graphs, 256, 1024), 256, 0, s>>>(totals, num_graphs);
@@ -1134,6 +1281,7 @@ ListLayout carve_list(void* ws, int64_t n) {
   Carver c(ws);
   ListLayout L;
   L.c.st = c.take<CountState>(1);
+  L.c.split = c.take<SplitEntry>(kSplitCap);
   L.c.list = c.take<int32_t>(n);
   L.c.total_scratch = c.take<uint64_t>(1);
   L.c.gid = nullptr;
@@ -1153,7 +1301,7 @@ template <typename OffT>
 tc_status list_impl(int64_t n, const OffT* row_ptr, const int32_t* col, int32_t* out, int64_t cap,
                     int64_t* count_out, const Tune& tune, const ListLayout& L, hipStream_t s) {
   uint64_t* tot = L.c.total_scratch;
-  init_state_kernel<<<1, 64, 0, s>>>(L.c.st, tot);
+  init_state_kernel<<<1, 256, 0, s>>>(L.c.st, L.c.split, tot);
   zero_u64_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(L.src_cnt, n);
   if (n > 0) {
     launch_bins<OffT>(n, row_ptr, L.c.st, L.c.list, tune.small_max, s);
@@ -1195,7 +1343,7 @@ tc_status support_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint3
                        int64_t cap, int64_t* m_out, uint64_t* total, const Tune& tune,
                        const CountLayout& L, hipStream_t s) {
   uint64_t* tot = total ? total : L.total_scratch;
-  init_state_kernel<<<1, 64, 0, s>>>(L.st, tot);
+  init_state_kernel<<<1, 256, 0, s>>>(L.st, L.split, tot);
   support_init_kernel<OffT><<<grid_for(cap, 256, 8192), 256, 0, s>>>(row_ptr, n, cap, sup, m_out);
   if (n > 0) {
     launch_bins<OffT>(n, row_ptr, L.st, L.list, tune.small_max, s);
@@ -1205,6 +1353,46 @@ tc_status support_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint3
     launch_count<kKindSupport, OffT>(n, row_ptr, col, L, tot, nullptr, args, tune, s);
   }
   return check_hip(hipGetLastError(), "tc_edge_support launch");
+}
+
+// ---- diamonds: two triangles sharing an edge ---------------------------------
+
+__global__ void diamond_init_kernel(uint64_t* total) { *total = 0; }
+
+// Sum over the edges of C(s, 2), s = the edge's support (m from m_out; nothing
+// when it reports an error).
+__global__ void diamond_reduce_kernel(const uint32_t* __restrict__ sup,
+                                      const int64_t* __restrict__ m_out,
+                                      uint64_t* __restrict__ total) {
+  const int64_t m = *m_out;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint64_t acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint64_t c = sup[i];
+    acc += c * (c - 1) / 2;  // 0 for c = 0 and c = 1
+  }
+  const uint64_t w = (uint64_t)wave_sum((int64_t)acc);
+  if (lane_id() == 0 && w) atomicAdd((unsigned long long*)total, (unsigned long long)w);
+}
+
+struct DiamondLayout {
+  CountLayout c;
+  uint32_t* sup;
+  size_t bytes;
+};
+
+DiamondLayout carve_diamonds(void* ws, int64_t n, int64_t cap) {
+  Carver c(ws);
+  DiamondLayout L;
+  L.c.st = c.take<CountState>(1);
+  L.c.split = c.take<SplitEntry>(kSplitCap);
+  L.c.list = c.take<int32_t>(n);
+  L.c.total_scratch = c.take<uint64_t>(1);
+  L.c.gid = nullptr;
+  L.sup = c.take<uint32_t>(cap);
+  L.bytes = c.used();
+  L.c.bytes = L.bytes;
+  return L;
 }
 
 }  // namespace
@@ -1280,4 +1468,32 @@ extern "C" tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, con
                                     ws, ws_bytes, stream);
   return tc::count_dispatch<false>(dag, total, nullptr, true, num_graphs, vtx_off, totals, tune, ws,
                                    ws_bytes, stream);
+}
+
+extern "C" tc_status tc_count_diamonds(const tc_csr* dag, int64_t edge_capacity, uint64_t* total,
+                                       int64_t* m_out, const tc_tune* tune, void* ws,
+                                       size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  tc_status st = check_dag(dag);
+  if (st != TC_OK) return st;
+  Tune t;
+  if ((st = read_tune(tune, &t)) != TC_OK) return st;
+  if (edge_capacity < 0) return fail(TC_ERR_INVALID_ARG, "negative edge_capacity");
+  if (edge_capacity > ((int64_t)1 << 40))
+    return fail(TC_ERR_UNSUPPORTED, "edge_capacity=%lld is beyond 2^40", (long long)edge_capacity);
+  if (workspace_query(ws, ws_bytes, carve_diamonds(nullptr, dag->n, edge_capacity).bytes, &st))
+    return st;
+  if (!dag->row_ptr || !total || !m_out) return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const DiamondLayout L = carve_diamonds(ws, dag->n, edge_capacity);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  diamond_init_kernel<<<1, 1, 0, s>>>(total);
+  if (dag->offset_bytes == 4)
+    st = support_impl<int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col, L.sup,
+                               edge_capacity, m_out, nullptr, t, L.c, s);
+  else
+    st = support_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, L.sup,
+                               edge_capacity, m_out, nullptr, t, L.c, s);
+  if (st != TC_OK) return st;
+  diamond_reduce_kernel<<<grid_for(edge_capacity, 256, 8192), 256, 0, s>>>(L.sup, m_out, total);
+  return check_hip(hipGetLastError(), "tc_count_diamonds launch") == TC_OK ? ok() : TC_ERR_HIP;
 }

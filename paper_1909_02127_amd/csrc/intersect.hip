@@ -1,0 +1,280 @@
+// intersect.hip - tc_segmented_intersect: the segmented-intersection operator
+// (Sec. II-B lists it beside advance, filter and compute) applied to triangle
+// counting: for every oriented edge (u, v) the sorted lists N+(u) and N+(v) are
+// intersected; each common out-neighbour w closes the triangle u -> v -> w, and
+// under the unique mapping order every triangle is found once, at its lowest
+// edge.  This is the edge-centric alternative to the wedge probe of count.hip.
+//
+// Load balance is a segmented merge path over the whole graph.  Edge e = (u, v)
+// owns a stretch of the merge space of length d+(u) + d+(v) (0 when d+(u) < 2
+// or d+(v) = 0: the look-ahead of Sec. III-C), and an exclusive scan P lays the
+// stretches end to end.  The merge space is cut into chunks of kSteps merge
+// steps, 64 consecutive chunks per wave, and every wave takes one contiguous
+// run of those spans.  A lane finds its edge by a search of P, its place in
+// that edge's merge by the merge-path diagonal search, and merges one element
+// per step, moving on to the next edge with a non-empty stretch at a
+// stretch's end.  Ties take A = N+(u) first, and a match is counted when A[i]
+// is taken while B = N+(v)'s head equals it, so each common neighbour is found
+// exactly once, in the chunk that takes A[i].
+//
+// Per-edge support adds one to (u, v), to (u, w) at A's position and to (v, w)
+// at B's position for every match.
+#include "tc_device.h"
+#include "tc_host.h"
+#include "tc_scan.h"
+
+#include <algorithm>
+
+namespace tc {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSteps = 32;                        // merge steps per lane and span chunk
+constexpr int64_t kSpan = (int64_t)kWave * kSteps;  // merge steps per wave and span
+constexpr int32_t kPastEnd = INT32_MAX;            // head of an exhausted list (ids < 2^31 - 1)
+
+// Source of every edge and the length of its stretch; stretches past m are 0.
+// One wave per source (rows are walked 64 entries at a time).
+template <typename OffT>
+__global__ __launch_bounds__(256) void edge_work_kernel(int64_t n, const OffT* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        int64_t cap, int32_t* __restrict__ src_of,
+                                                        uint32_t* __restrict__ work,
+                                                        int64_t* __restrict__ m_out) {
+  const int64_t m = (int64_t)rp[n];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *m_out = m > cap ? -(int64_t)TC_ERR_CAPACITY : m;
+  if (m > cap) return;
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  for (int64_t u = gw; u < n; u += nwaves) {
+    const int64_t beg = (int64_t)rp[u];
+    const int64_t du = (int64_t)rp[u + 1] - beg;
+    for (int64_t i = lane; i < du; i += kWave) {
+      const int64_t e = beg + i;
+      const int32_t v = col[e];
+      const int64_t dv = (int64_t)rp[v + 1] - (int64_t)rp[v];
+      src_of[e] = (int32_t)u;
+      work[e] = du >= 2 && dv >= 1 ? (uint32_t)(du + dv) : 0u;
+    }
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cap; e += stride)
+    work[e] = 0u;
+}
+
+struct WorkLoad {
+  const uint32_t* work;
+  __device__ int64_t operator()(int64_t i) const { return (int64_t)work[i]; }
+};
+struct PrefixStore {
+  int64_t* p;
+  __device__ void operator()(int64_t i, int64_t x) const { p[i] = x; }
+};
+
+// P[cap] = the grand total S; the support array is cleared to m entries.
+__global__ void intersect_finish_scan_kernel(const int64_t* __restrict__ partial, int64_t tiles,
+                                             int64_t cap, int64_t* __restrict__ P) {
+  P[cap] = tiles > 0 ? partial[tiles] : 0;
+}
+
+__global__ void intersect_init_kernel(uint64_t* total) { *total = 0; }
+
+__global__ void clear_u32_kernel(uint32_t* __restrict__ p, const int64_t* __restrict__ m_out) {
+  const int64_t m = *m_out;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) p[i] = 0u;
+}
+
+// First index in [lo, hi) with P[idx] > x, or hi.
+__device__ __forceinline__ int64_t upper_bound(const int64_t* __restrict__ P, int64_t lo, int64_t hi,
+                                               int64_t x) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (P[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// The same, probing lo, lo + 1, lo + 3, lo + 7, ... first (the answer is
+// usually close to lo), then a binary search inside the last gap.
+__device__ __forceinline__ int64_t gallop_upper(const int64_t* __restrict__ P, int64_t lo,
+                                                int64_t hi, int64_t x) {
+  int64_t step = 1, prev = lo;
+  int64_t at = lo;
+  while (at < hi && P[at] <= x) {
+    prev = at + 1;
+    at = lo + step * 2 - 1;
+    step *= 2;
+  }
+  return upper_bound(P, prev, at < hi ? at : hi, x);
+}
+
+// One list element, or kPastEnd past its end.
+__device__ __forceinline__ int32_t head(const int32_t* __restrict__ col, int64_t beg, int64_t i,
+                                        int64_t len) {
+  return i < len ? col[beg + i] : kPastEnd;
+}
+
+template <bool Support, typename OffT>
+__global__ __launch_bounds__(kBlock) void merge_kernel(int64_t cap, const OffT* __restrict__ rp,
+                                                     const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ src_of,
+                                                     const int64_t* __restrict__ P,
+                                                     const int64_t* __restrict__ m_out,
+                                                     uint64_t* __restrict__ total,
+                                                     uint32_t* __restrict__ sup) {
+  if (*m_out < 0) return;
+  const int64_t S = P[cap];
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  // this wave's contiguous run of spans
+  const int64_t spans = (S + kSpan - 1) / kSpan;
+  const int64_t per = (spans + nwaves - 1) / nwaves;
+  const int64_t s_beg = gw * per;
+  const int64_t s_end = s_beg + per < spans ? s_beg + per : spans;
+  uint64_t hits = 0;
+  int64_t e_lo = 0;
+  bool first = true;
+  for (int64_t sp = s_beg; sp < s_end; ++sp) {
+    const int64_t base = sp * kSpan;
+    const int64_t last = (base + kSpan < S ? base + kSpan : S) - 1;
+    // the span's edge range [e_lo, e_hi] (uniform across the wave)
+    e_lo = (first ? upper_bound(P, 0, cap + 1, base) : gallop_upper(P, e_lo, cap + 1, base)) - 1;
+    first = false;
+    const int64_t e_hi = gallop_upper(P, e_lo, cap + 1, last) - 1;
+    int64_t p = base + (int64_t)lane * kSteps;
+    if (p > last) continue;
+    const int64_t pend = p + kSteps <= last + 1 ? p + kSteps : last + 1;
+    int64_t e = upper_bound(P, e_lo, e_hi + 2, p) - 1;
+    while (true) {
+      const int64_t pe = P[e];
+      const int64_t pe1 = P[e + 1];
+      const int32_t u = src_of[e];
+      const int32_t v = col[e];
+      const int64_t ab = (int64_t)rp[u];
+      const int64_t a = (int64_t)rp[u + 1] - ab;
+      const int64_t bb = (int64_t)rp[v];
+      const int64_t b = (int64_t)rp[v + 1] - bb;
+      // merge-path diagonal k: i elements of A and k - i of B come first
+      const int64_t k = p - pe;
+      int64_t lo = k - b > 0 ? k - b : 0;
+      int64_t hi = k < a ? k : a;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[ab + mid] <= col[bb + k - mid - 1]) lo = mid + 1;
+        else hi = mid;
+      }
+      int64_t i = lo, j = k - lo;
+      int32_t av = head(col, ab, i, a);
+      int32_t bv = head(col, bb, j, b);
+      const int64_t stop = pend < pe1 ? pend : pe1;
+      uint32_t cuv = 0;
+      for (int64_t q = p; q < stop; ++q) {
+        const bool take_a = av <= bv;
+        if (take_a && av == bv) {
+          ++cuv;
+          if (Support) {
+            atomicAdd(&sup[ab + i], 1u);  // the edge (u, w)
+            atomicAdd(&sup[bb + j], 1u);  // the edge (v, w)
+          }
+        }
+        // one load per step: the next element of the list just taken from
+        const int64_t nbeg = take_a ? ab : bb;
+        const int64_t nidx = take_a ? i + 1 : j + 1;
+        const int64_t nlen = take_a ? a : b;
+        const int32_t x = head(col, nbeg, nidx, nlen);
+        if (take_a) {
+          i = nidx;
+          av = x;
+        } else {
+          j = nidx;
+          bv = x;
+        }
+      }
+      hits += cuv;
+      if (Support && cuv) atomicAdd(&sup[e], cuv);  // the edge (u, v)
+      p = stop;
+      if (p >= pend) break;
+      e = gallop_upper(P, e + 1, e_hi + 2, p) - 1;
+    }
+  }
+  const uint64_t wh = (uint64_t)wave_sum((int64_t)hits);
+  if (lane == 0 && wh) atomicAdd((unsigned long long*)total, (unsigned long long)wh);
+}
+
+struct IntersectLayout {
+  int32_t* src_of;
+  uint32_t* work;
+  int64_t* P;
+  int64_t* partial;
+  size_t bytes;
+};
+
+IntersectLayout carve_intersect(void* ws, int64_t cap) {
+  Carver c(ws);
+  IntersectLayout L;
+  L.src_of = c.take<int32_t>(cap);
+  L.work = c.take<uint32_t>(cap);
+  L.P = c.take<int64_t>(cap + 1);
+  L.partial = c.take<int64_t>(scan_partial_len(cap));
+  L.bytes = c.used();
+  return L;
+}
+
+template <typename OffT>
+tc_status intersect_impl(int64_t n, const OffT* rp, const int32_t* col, int64_t cap,
+                         uint64_t* total, uint32_t* sup, int64_t* m_out, const IntersectLayout& L,
+                         hipStream_t s) {
+  intersect_init_kernel<<<1, 1, 0, s>>>(total);
+  edge_work_kernel<OffT><<<grid_for(std::max<int64_t>(n, cap / 64), 256 / kWave, 8192), 256, 0, s>>>(
+      n, rp, col, cap, L.src_of, L.work, m_out);
+  hipError_t e = scan_exclusive<OpSum>(cap, WorkLoad{L.work}, PrefixStore{L.P}, L.partial, s);
+  if (e != hipSuccess) return check_hip(e, "segmented intersection scan");
+  intersect_finish_scan_kernel<<<1, 1, 0, s>>>(L.partial, scan_num_tiles(cap), cap, L.P);
+  if (sup) clear_u32_kernel<<<grid_for(cap, 256, 8192), 256, 0, s>>>(sup, m_out);
+  int per_cu = 0;
+  if (sup)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, merge_kernel<true, OffT>, kBlock, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, merge_kernel<false, OffT>, kBlock, 0);
+  const int grid = std::max(per_cu, 1) * device_cu_count();
+  if (sup)
+    merge_kernel<true, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out, total, sup);
+  else
+    merge_kernel<false, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out, total,
+                                                      nullptr);
+  return check_hip(hipGetLastError(), "tc_segmented_intersect launch");
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_segmented_intersect(const tc_csr* dag, int64_t edge_capacity,
+                                            uint64_t* total, uint32_t* support, int64_t* m_out,
+                                            void* ws, size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  if (!dag) return fail(TC_ERR_INVALID_ARG, "dag is NULL");
+  const int64_t n = dag->n;
+  if (n < 0) return fail(TC_ERR_INVALID_ARG, "negative n");
+  if (n > INT32_MAX) return fail(TC_ERR_UNSUPPORTED, "n=%lld needs ids beyond int32", (long long)n);
+  if (dag->offset_bytes != 4 && dag->offset_bytes != 8)
+    return fail(TC_ERR_INVALID_ARG, "offset_bytes must be 4 or 8, got %d", dag->offset_bytes);
+  if (edge_capacity < 0) return fail(TC_ERR_INVALID_ARG, "negative edge_capacity");
+  if (edge_capacity > ((int64_t)1 << 40))
+    return fail(TC_ERR_UNSUPPORTED, "edge_capacity=%lld is beyond 2^40", (long long)edge_capacity);
+  tc_status st;
+  if (workspace_query(ws, ws_bytes, carve_intersect(nullptr, edge_capacity).bytes, &st)) return st;
+  if (!dag->row_ptr || !total || !m_out) return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const IntersectLayout L = carve_intersect(ws, edge_capacity);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dag->offset_bytes == 4)
+    st = intersect_impl<int32_t>(n, static_cast<const int32_t*>(dag->row_ptr), dag->col,
+                                 edge_capacity, total, support, m_out, L, s);
+  else
+    st = intersect_impl<int64_t>(n, static_cast<const int64_t*>(dag->row_ptr), dag->col,
+                                 edge_capacity, total, support, m_out, L, s);
+  return st == TC_OK ? ok() : st;
+}

@@ -54,6 +54,9 @@ class Pipeline:
         self.support = None
         self.ws_support = None
         self.support_m = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws_intersect = None
+        self.ws_diamonds = None
+        self.diamond_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.list_count = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_count = _bytes(max(_lib.tc_count_workspace(n),
                                    _lib.tc_count_per_vertex_workspace(n)), dev)
@@ -101,6 +104,46 @@ class Pipeline:
             self.ws_support = _bytes(_lib.tc_edge_support_workspace(self.n), self.device)
         _lib.tc_edge_support(self.n, self.dag_ptr, self.dag_col, self.support, self.support_m,
                              self.ws_support, total=self.total, tune=tune, stream=stream)
+
+    def intersect(self, *, support: bool = False, stream=None) -> None:
+        """Enqueue tc_segmented_intersect (merge-path N+(u) & N+(v) for every DAG edge) on
+        the current DAG: the total into self.total and, with support, every edge's
+        triangles into self.support (read with supports())."""
+        cap = self.dag_col.numel()
+        if self.ws_intersect is None:
+            self.ws_intersect = _bytes(_lib.tc_segmented_intersect_workspace(self.n, cap),
+                                       self.device)
+        if support and self.support is None:
+            self.support = torch.empty(cap, dtype=torch.int32, device=self.device)
+        _lib.tc_segmented_intersect(self.n, self.dag_ptr, self.dag_col, self.total,
+                                    self.support_m, self.ws_intersect,
+                                    support=self.support if support else None, stream=stream)
+
+    def diamonds(self, stream=None, tune=None) -> None:
+        """Enqueue tc_count_diamonds on the current DAG (result in self.diamond_total)."""
+        tune = self.tune if tune is None else tune
+        if self.ws_diamonds is None:
+            self.ws_diamonds = _bytes(
+                _lib.tc_count_diamonds_workspace(self.n, self.dag_col.numel()), self.device)
+        _lib.tc_count_diamonds(self.n, self.dag_ptr, self.dag_col, self.diamond_total,
+                               self.support_m, self.ws_diamonds, tune=tune, stream=stream)
+
+    def diamond_count(self) -> int:
+        """Synchronise and read the result of diamonds()."""
+        torch.cuda.synchronize(self.device)
+        m = int(self.support_m.item())
+        if m < 0:
+            raise TcError(-m, "reported by tc_count_diamonds on the device")
+        return int(self.diamond_total.item()) & ((1 << 64) - 1)
+
+    def intersect_total(self) -> int:
+        """Synchronise and read the total written by intersect(); raises TcError when the
+        DAG had more edges than the column capacity."""
+        torch.cuda.synchronize(self.device)
+        m = int(self.support_m.item())
+        if m < 0:
+            raise TcError(-m, "reported by tc_segmented_intersect on the device")
+        return int(self.total.item()) & ((1 << 64) - 1)
 
     def supports(self) -> torch.Tensor:
         """Synchronise and return the per-edge supports written by edge_support (int32 view

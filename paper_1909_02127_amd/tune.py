@@ -22,6 +22,10 @@ DEFAULT_CANDIDATES = [
     for s in (16, 32, 64, 96)
     for p in (TC_PROBE_AUTO, TC_PROBE_SORTED)
     for b in (0, 4)
+] + [
+    # the equal-work quantum of split sources, at the default split and probe
+    {"small_max": 96, "probe": TC_PROBE_AUTO, "blocks_per_cu": 0, "split_log2": q}
+    for q in (14, 17, -1)
 ]
 
 
@@ -67,16 +71,20 @@ def time_ms(run, reps: int = 3) -> float:
 
 
 def autotune(run_with, workload_class: str, *, candidates=None, reps: int = 3,
-             use_cache: bool = True) -> tuple[dict, list]:
-    """run_with(tune_dict) enqueues one count.  Returns (best tune, [(tune, ms), ...])."""
-    dev = torch.cuda.get_device_name()
+             use_cache: bool = True, timer=None, device_name: str | None = None
+             ) -> tuple[dict, list]:
+    """run_with(tune_dict) enqueues one count.  Returns (best tune, [(tune, ms), ...]).
+    `timer(run, reps)` measures one candidate (default: HIP events, time_ms); the cache key
+    is the device name and the caller's workload class."""
+    dev = device_name if device_name is not None else torch.cuda.get_device_name()
     key = f"{dev}|{workload_class}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key]["tune"], cache[key].get("table", [])
+    timer = timer or time_ms
     table = []
     for cand in candidates or DEFAULT_CANDIDATES:
-        table.append((cand, time_ms(lambda c=cand: run_with(c), reps)))
+        table.append((cand, timer(lambda c=cand: run_with(c), reps)))
     best = min(table, key=lambda x: x[1])[0]
     if use_cache:
         cache[key] = {"tune": best, "table": table}

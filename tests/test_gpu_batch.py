@@ -88,7 +88,8 @@ def test_batched_tuning_never_changes_counts(tc):
     b = PackedBatch(graphs)
     for tune in [None, {"small_max": 1}, {"small_max": 16}, {"probe": tc.TC_PROBE_SORTED},
                  {"blocks_per_cu": 1}, {"small_max": 64, "probe": 1, "blocks_per_cu": 2},
-                 {"small_max": 96}]:
+                 {"small_max": 96}, {"small_max": 8, "split_log2": 3},
+                 {"split_log2": -1}]:
         br = BatchRunner(b, tune=tune)
         br.enqueue()
         assert br.results()[0] == want, tune
@@ -140,12 +141,13 @@ def _t_digest(t: np.ndarray) -> str:
 @pytest.mark.slow
 def test_full_batch_4096_against_oracle(tc):
     """The whole 4096-graph batch (n log-uniform in [2^8, 2^16], average degree U(4, 64), half
-    Erdos-Renyi and half R-MAT; sum n = 4.7e7 > 2^24, so the folded wide hash runs; int64
-    offsets) as the benchmark runs it, a HIP-graph replay: every graph's total and every
-    t(v) of every graph against the oracle's stored counts (tests/golden/make_batch4096.py:
-    totals and a digest of each graph's t), the tuned total-only launch too, and a stratified
+    Erdos-Renyi and half R-MAT; sum n = 4.7e7 > 2^24, so the folded wide hash runs; int32
+    offsets, as 2 * pairs < 2^31) as the benchmark runs it, a HIP-graph replay: every graph's
+    total and every t(v) of every graph against the oracle's stored counts
+    (tests/golden/make_batch4096.py: totals and a digest of each graph's t), the tuned
+    total-only launch too, and a stratified
     sample of graphs (the largest by edges and by vertices, and random ones) recounted here by
-    the oracle, totals and t(v)."""
+    the oracle, totals and t(v); then every total again with int64 offsets."""
     import json
     import os
     import time
@@ -161,7 +163,8 @@ def test_full_batch_4096_against_oracle(tc):
         graphs.append(graphgen.batch_graph(g, device="cuda"))
         if (i + 1) % 1024 == 0:
             _say(f"batch 4096: generated {i + 1} graphs ({time.perf_counter() - t0:.0f}s)")
-    b = PackedBatch(graphs, offset_bytes=8)
+    b = PackedBatch(graphs)  # the benchmark's choice: int32 offsets (2 * pairs < 2^31)
+    assert b.offset_bytes == 4
     assert b.n > (1 << 24)
     assert b.graph_edges() == [g["m"] for g in gold]
     want = [g["triangles"] for g in gold]
@@ -196,3 +199,12 @@ def test_full_batch_4096_against_oracle(tc):
         assert T == totals[i], i
         np.testing.assert_array_equal(pv[off[i]: off[i + 1]], t)
     _say(f"batch 4096: live oracle on {len(pick)} graphs ({time.perf_counter() - t0:.0f}s)")
+    # the same union with int64 offsets: every total again
+    del br, pv
+    b8 = PackedBatch(graphs, offset_bytes=8)
+    del b
+    br8 = BatchRunner(b8)
+    br8.capture()
+    br8.replay()
+    assert br8.results()[0] == want
+    _say(f"batch 4096: int64 offsets match ({time.perf_counter() - t0:.0f}s)")

@@ -118,6 +118,17 @@ def test_list_hub_beyond_one_slice_and_clique(tc):
     _check_same(tc, n, s, d, 1)
 
 
+def test_list_with_split_sources(tc):
+    """Equal-work quanta (tc_tune.split_log2) split the heavy sources of the counting pass;
+    the rows of the writing pass (never split) must land in the same per-source ranges."""
+    tune = {"split_log2": 3, "small_max": 16}
+    s, d, n = graphgen.rmat(12, 16, 8)
+    for order in (0, 1):
+        _check_same(tc, n, s.numpy(), d.numpy(), order, tune=tune)
+    n, s, d = pins.complete(60)
+    _check_same(tc, n, s, d, 1, tune=tune)
+
+
 @pytest.mark.parametrize("kicks", [-1, 1])
 def test_list_probe_fallback_modes(tc, kicks):
     """Stash and sorted probe modes (tc_tune.max_kicks) write the same rows."""

@@ -360,3 +360,28 @@ def test_wave_workgroup_split_thresholds(tc):
             assert int(total.item()) == T, sm
         with pytest.raises(_lib.TcError):
             _lib.tc_count(n, p.dag_ptr, p.dag_col, total, ws, tune={"small_max": 97})
+
+
+@pytest.mark.parametrize("split_log2", [1, 6, 10, -1])
+def test_equal_work_quanta(tc, split_log2):
+    """Workgroup-mode sources whose work w(u) (wedges) exceeds 2^split_log2 are cut into
+    parts that any workgroup may claim (tc_tune.split_log2).  Small quanta split almost
+    every such source, in both orders and with per-vertex counts; counts must not change.
+    Splitting 1 ("2 wedges per part") also runs into the 1024-part cap and, with several
+    thousand heavy sources, into the full split table."""
+    tune = {"split_log2": split_log2, "small_max": 16}
+    cases = [pins.complete(60), _hub_graph(3000, 20000, 5)]
+    s, d, n = graphgen.rmat(13, 16, 9)
+    cases.append((n, s.numpy(), d.numpy()))
+    s, d, n = graphgen.erdos_renyi(20000, 400000, 3)
+    cases.append((n, s.numpy(), d.numpy()))
+    for n, s, d in cases:
+        _say("quanta", split_log2, "n", n, "pairs", len(s))
+        T, t = _oracle(n, s, d)
+        for order in (0, 1):
+            res, pv = _gpu(tc, n, s, d, order=order, tune=tune)
+            assert res.total == T
+            np.testing.assert_array_equal(pv, t)
+            res2, _ = _gpu(tc, n, s, d, order=order, tune=tune, per_vertex=False,
+                           offset_bytes=8)
+            assert res2.total == T

@@ -98,6 +98,17 @@ def test_support_config1_and_hub(tc):
     _check(tc, n, s, d, 1)
 
 
+def test_support_with_split_sources(tc):
+    """Equal-work quanta (tc_tune.split_log2): every part of a split source adds its own
+    edge counts; the supports must not change."""
+    tune = {"split_log2": 3, "small_max": 16}
+    s, d, n = graphgen.rmat(12, 16, 8)
+    for order in (0, 1):
+        _check(tc, n, s.numpy(), d.numpy(), order, tune=tune)
+    n, s, d = pins.complete(60)
+    _check(tc, n, s, d, 1, tune=tune)
+
+
 @pytest.mark.parametrize("kicks", [-1, 1])
 def test_support_probe_fallback_modes(tc, kicks):
     tune = {"max_kicks": kicks}
