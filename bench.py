@@ -182,9 +182,12 @@ def summarize_counters(args) -> str:
         if "SQ_LDS_BANK_CONFLICT" in cs and cs.get("SQ_INSTS_LDS"):
             lines.append(f"    {'bank-conflict cycles / LDS instr':28s} "
                          f"{cs['SQ_LDS_BANK_CONFLICT'] / cs['SQ_INSTS_LDS']:20.3f}")
-        if "SQ_LEVEL_WAVES" in cs and cs.get("SQ_BUSY_CYCLES"):
-            lines.append(f"    {'waves in flight (mean)':28s} "
-                         f"{cs['SQ_LEVEL_WAVES'] / cs['SQ_BUSY_CYCLES']:20.1f}")
+        if "SQ_WAVE_CYCLES" in cs and cs.get("SQ_BUSY_CYCLES"):
+            # SQ_WAVE_CYCLES sums the resident cycles of all waves in units of 4 cycles;
+            # SQ_BUSY_CYCLES sums the busy cycles of the 32 shader engines: waves per SIMD
+            # (1024 SIMDs) = 4 * WAVE_CYCLES / (BUSY_CYCLES / 32) / 1024
+            lines.append(f"    {'waves per SIMD (mean)':28s} "
+                         f"{cs['SQ_WAVE_CYCLES'] / cs['SQ_BUSY_CYCLES'] / 8:20.2f}")
         if "TCC_HIT_sum" in cs and "TCC_MISS_sum" in cs:
             tot = cs["TCC_HIT_sum"] + cs["TCC_MISS_sum"]
             if tot:
@@ -234,7 +237,10 @@ def summarize_pmc(args) -> str:
         rec[key] = {"kernel": name, "dispatches": len(fv), "fetch_kib": fk, "write_kib": wk,
                     "fetch_bytes_scaled": fk * 1024 * f_fac, "write_bytes_scaled": wk * 1024 * w_fac,
                     "traffic_bytes_per_launch": fk * 1024 * f_fac + wk * 1024 * w_fac}
-    rec["traffic_bytes_per_launch"] = rec.get("count_per_vertex", {}).get("traffic_bytes_per_launch")
+    # the per-vertex launch where the workload runs one (graphs), else the total-only one (batch)
+    rec["traffic_bytes_per_launch"] = (rec.get("count_per_vertex") or
+                                       rec.get("count_total_only") or {}).get(
+                                           "traffic_bytes_per_launch")
     out = os.path.join(ROOT, "profiles", f"count_kernel_{args.workload}_pmc.json")
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
@@ -599,7 +605,7 @@ def batch_main(args, spec):
         "oracle_stored_all_graphs_match": stored_ok,
         "roofline": {"bound": "hbm", "kernel": "count_kernel (tc_count_batched)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(args.workload),
                      "algorithmic_bytes": alg["bytes"], "wedges": alg["wedges"],
                      "ms_count": ms_count},
         "autotune_table": table,

@@ -19,6 +19,8 @@
  *   tc_count_per_vertex  the same, plus t(v) = number of triangles containing v.
  *   tc_count_batched     per-graph counts of many graphs packed as one disjoint
  *                        union, in one launch sequence.
+ *   tc_source_work       the wedge work w(u) of every source and its prefix
+ *                        (equal-work ranges of sources).
  *   tc_list_triangles    the match set M itself: every triangle as one row
  *                        (u, v, w) of the oriented graph.
  *   tc_edge_support      for every edge, the number of matches (triangles)
@@ -102,10 +104,11 @@ typedef struct tc_tune {
                             -1 = none, so every key takes the stash or the sorted
                             fallback (exercises those probe modes) */
   int32_t split_log2;    /* equal-work quanta: a workgroup-mode source u whose work
-                            w(u) = sum of d+(v) over v in N+(u) (its wedges) exceeds
-                            2^split_log2 is cut into ceil(w(u) / 2^split_log2) parts
-                            (at most 1024) that any workgroup may take; 0 = default
-                            (2^20), 1 to 40 = that quantum, -1 = never split */
+                            w(u) = sum of d+(v) over v in N+(u) (its wedges; x8 when
+                            N+(u) is too long for LDS and is searched in memory)
+                            exceeds 2^split_log2 is cut into ceil(w(u) / 2^split_log2)
+                            parts (at most 1024) that any workgroup may take;
+                            0 = default (2^21), 1 to 40 = that quantum, -1 = never */
 } tc_tune;
 
 /* Read-only view of a CSR graph in device memory. */
@@ -248,6 +251,22 @@ tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, const int64_t*
  */
 tc_status tc_pack_pairs(int64_t num_graphs, const int64_t* pair_off, const int64_t* vtx_off,
                         int32_t* src, int32_t* dst, void* stream);
+
+/*
+ * tc_source_work - the wedge work of every source and its exclusive prefix.
+ * In the all-source advance (Alg. 1 "Advance", Sec. III-B) source u enumerates
+ * one wedge u -> v -> w per v in N+(u) and w in N+(v): w(u) = sum of d+(v) over
+ * N+(u), and 0 when d+(u) < 2 (the 2-look-ahead of Sec. III-C).  The prefix
+ * cuts the sources into contiguous ranges of equal work (how the count would be
+ * sharded) and its last entry is the total W the count enumerates.
+ *
+ *   dag      oriented CSR
+ *   work     device int64[n] or NULL: w(u) (written)
+ *   prefix   device int64[n+1] (written): prefix[u] = sum of w over ids < u
+ *   ws, ws_bytes  workspace; about 8 n bytes.
+ */
+tc_status tc_source_work(const tc_csr* dag, int64_t* work, int64_t* prefix, void* ws,
+                         size_t* ws_bytes, void* stream);
 
 /*
  * tc_list_triangles - the matches themselves.  Sec. II-A defines the output of

@@ -16,7 +16,7 @@ _EXPORTS = {
     "TC_PROBE_SORTED": "_lib", "TcError": "_lib", "make_tune": "_lib", "tc_build_csr": "_lib",
     "tc_count": "_lib", "tc_count_batched": "_lib", "tc_count_per_vertex": "_lib",
     "tc_count_bfs": "_lib", "tc_count_k4": "_lib", "tc_count_diamonds": "_lib",
-    "tc_segmented_intersect": "_lib", "tc_edge_support": "_lib", "tc_list_triangles": "_lib",
+    "tc_segmented_intersect": "_lib", "tc_source_work": "_lib", "tc_edge_support": "_lib", "tc_list_triangles": "_lib",
     "tc_ne_filter": "_lib", "tc_orient": "_lib", "tc_version": "_lib",
     "Pipeline": "pipeline", "Result": "pipeline", "triangle_count": "pipeline",
 }

@@ -92,6 +92,8 @@ def _load() -> ctypes.CDLL:
     lib.tc_count_bfs.argtypes = [csr, p, i64, p, i64, p, p, p, sz, p]
     lib.tc_edge_support.restype = i32
     lib.tc_edge_support.argtypes = [csr, p, i64, p, p, tune, p, sz, p]
+    lib.tc_source_work.restype = i32
+    lib.tc_source_work.argtypes = [csr, p, p, p, sz, p]
     lib.tc_segmented_intersect.restype = i32
     lib.tc_segmented_intersect.argtypes = [csr, i64, p, p, p, p, sz, p]
     lib.tc_count_diamonds.restype = i32
@@ -312,6 +314,23 @@ def tc_edge_support(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_edge_support, ws, ctypes.byref(csr), _ptr(support), support.numel(),
              _ptr(m_out), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_source_work_workspace(n: int) -> int:
+    csr = tc_csr(n, 4, None, None)
+    return _ws_query(LIB.tc_source_work, ctypes.byref(csr), None, None)
+
+
+def tc_source_work(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                   prefix: torch.Tensor, ws: torch.Tensor, *, work: torch.Tensor | None = None,
+                   stream=None) -> None:
+    """w(u) (int64[n], optional) and its exclusive prefix (int64[n+1]) of a DAG."""
+    if prefix.dtype != torch.int64 or prefix.numel() != n + 1:
+        raise ValueError("prefix must be int64[n+1]")
+    if work is not None and (work.dtype != torch.int64 or work.numel() != n):
+        raise ValueError("work must be int64[n]")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_source_work, ws, ctypes.byref(csr), _ptr(work), _ptr(prefix), stream=stream)
 
 
 def tc_segmented_intersect_workspace(n: int, edge_capacity: int) -> int:

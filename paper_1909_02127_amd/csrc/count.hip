@@ -123,23 +123,29 @@ struct CountState {
   int32_t large_cursor;
   int32_t small_cursor;
   int32_t split_count;  // entries taken in the split table
-  int32_t pad[5];
+  int32_t help_cursor;  // entries below it are drained
+  int32_t max_dplus;    // largest out-degree (bounds every w(u) by d+(u) max_dplus)
+  int32_t pad[3];
 };
 
 // Equal-work quanta.  The work of a source is w(u) = sum of d+(v) over its
-// middles v, the wedges it enumerates.  A workgroup-mode source with w(u) above
-// the quantum is cut into P = ceil(w(u) / quantum) parts (at most kMaxParts):
+// middles v, the wedges it enumerates; a source whose out-list is searched in
+// memory (d+(u) above kGlobalMin) counts each wedge kGlobalWeight times, for the
+// binary search it costs.  A workgroup-mode source with such work above the
+// quantum is cut into P = ceil(work / quantum) parts (at most kMaxParts):
 // part k takes the middles k, k + P, k + 2P, ... (each part then holds about
 // w(u) / P wedges).  Its workgroup publishes it in the split table, and parts
 // are claimed through the entry's counter, by that workgroup and by any other
 // that has run out of sources, so a heavy source no longer sets the tail.
 constexpr int kSplitCap = 4096;       // split table entries (a fuller table keeps parts local)
 constexpr int32_t kMaxParts = 1024;
-constexpr int kSplitDefaultLog2 = 20;  // default quantum: 2^20 wedges
+constexpr int kSplitDefaultLog2 = 21;  // default quantum: 2^21 wedges
+constexpr uint64_t kGlobalWeight = 8;
 
 // The workgroup's schedule in LDS (written by thread 0).
 constexpr int kSchedState = 0, kSchedU = 1, kSchedPart = 2, kSchedParts = 3, kSchedIdx = 4,
-              kSchedEnt = 5, kSchedHelp = 6, kSchedHelpEnd = 7, kSchedLocalK = 8, kSchedWords = 9;
+              kSchedEnt = 5, kSchedLocalK = 6, kSchedMaxD = 7, kSchedWords = 8;
+constexpr int kHelpWindows = 4;  // 64-entry windows of the split table one step looks at
 constexpr int32_t kStateDone = 0, kStateWork = 1, kStateNew = 2, kStateSkip = 3;
 constexpr int32_t kNoEntry = -1, kLocalEntry = -2;
 
@@ -177,25 +183,30 @@ __device__ __forceinline__ void bin_degrees(int64_t n, const OffT* __restrict__ 
 template <typename OffT>
 __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n, const OffT* __restrict__ row_ptr,
                                                         CountState* __restrict__ st, int small_max) {
-  __shared__ int32_t h[kNumClasses];
-  if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
+  __shared__ int32_t h[kNumClasses + 1];
+  if (threadIdx.x <= kNumClasses) h[threadIdx.x] = 0;
   __syncthreads();
   int64_t d[kBinItems];
   bin_degrees(n, row_ptr, (int64_t)blockIdx.x * (256 * kBinItems), d);
   int32_t mine[kNumClasses] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t dmax = 0;
 #pragma unroll
   for (int r = 0; r < kBinItems; ++r) {
     const int c = d[r] >= 0 ? source_class(d[r], small_max) : -1;
 #pragma unroll
     for (int k = 0; k < kNumClasses; ++k) mine[k] += (c == k);
+    dmax = d[r] > dmax ? (int32_t)d[r] : dmax;
   }
 #pragma unroll
   for (int k = 0; k < kNumClasses; ++k) {
     const int64_t s = wave_sum(mine[k]);
     if (lane_id() == 0 && s) atomicAdd(&h[k], (int32_t)s);
   }
+  dmax = read_lane(wave_inclusive_max32(dmax), kWave - 1);
+  if (lane_id() == 0 && dmax) atomicMax(&h[kNumClasses], dmax);
   __syncthreads();
   if (threadIdx.x < kNumClasses && h[threadIdx.x]) atomicAdd(&st->class_count[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == kNumClasses && h[kNumClasses]) atomicMax(&st->max_dplus, h[kNumClasses]);
 }
 
 template <typename OffT>
@@ -835,7 +846,7 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
 // Runtime parameters of one count launch.
 struct CountArgs {
   SplitEntry* split;   // split table (kSplitCap entries)
-  uint64_t quantum;    // wedges per part of a split source; 0: never split
+  int32_t split_shift;  // log2 of the wedges per part of a split source; 0: never split
   const int32_t* gid;  // batched mode: graph of each vertex (-1: none); else null
   uint64_t* totals;    // batched mode: per-graph totals; else null
   uint64_t* src_cnt;   // listing, first pass: hits of each source; else null
@@ -898,57 +909,84 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   // process_source has one call site.
   const Table big = table_at<PV>(smem, kSideMax);
   __shared__ int32_t sched[kSchedWords];
-  const bool splitting = K != kKindList && args.quantum != 0;
+  const bool splitting = K != kKindList && args.split_shift != 0;
   if (threadIdx.x == 0) {
     sched[kSchedIdx] = blockIdx.x;
     sched[kSchedEnt] = kNoEntry;
-    sched[kSchedHelp] = 0;
-    sched[kSchedHelpEnd] = -1;
+    // read once per workgroup: the state's cache line takes the cursor atomics
+    sched[kSchedMaxD] = st->max_dplus;
   }
   while (true) {
     __syncthreads();  // every thread has read the previous step's schedule
-    if (threadIdx.x == 0) {
-      int32_t state = kStateDone;
-      int32_t ent = sched[kSchedEnt];
-      if (ent != kNoEntry) {
-        const int32_t k = ent >= 0 ? atomicAdd(&args.split[ent].next, 1) : sched[kSchedLocalK]++;
-        if (k < sched[kSchedParts]) {
-          sched[kSchedPart] = k;
-          state = kStateWork;
-        } else {
-          ent = kNoEntry;
-        }
-      }
-      if (state == kStateDone && sched[kSchedIdx] < n_large) {
-        sched[kSchedU] = list[sched[kSchedIdx]];
-        sched[kSchedIdx] = (int32_t)gridDim.x + atomicAdd(&st->large_cursor, 1);
-        state = kStateNew;
-      }
-      if (state == kStateDone && splitting) {
-        if (sched[kSchedHelpEnd] < 0) {
-          const int32_t c = __hip_atomic_load(&st->split_count, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-          sched[kSchedHelpEnd] = c < kSplitCap ? c : kSplitCap;
-        }
-        while (state == kStateDone && sched[kSchedHelp] < sched[kSchedHelpEnd]) {
-          const int32_t e = sched[kSchedHelp]++;
-          // 0 until published; an unpublished entry is drained by its own workgroup
-          const unsigned long long word = __hip_atomic_load(&args.split[e].word, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-          if (!word) continue;
-          const int32_t parts = (int32_t)(word >> 32);
-          const int32_t k = atomicAdd(&args.split[e].next, 1);
-          if (k < parts) {
-            ent = e;
-            sched[kSchedU] = (int32_t)(uint32_t)word;
-            sched[kSchedParts] = parts;
+    if (wave == 0) {
+      if (lane == 0) {
+        int32_t state = kStateDone;
+        int32_t ent = sched[kSchedEnt];
+        if (ent != kNoEntry) {
+          const int32_t k = ent >= 0 ? atomicAdd(&args.split[ent].next, 1) : sched[kSchedLocalK]++;
+          if (k < sched[kSchedParts]) {
             sched[kSchedPart] = k;
             state = kStateWork;
+          } else {
+            ent = kNoEntry;
           }
         }
+        if (state == kStateDone && sched[kSchedIdx] < n_large) {
+          sched[kSchedU] = list[sched[kSchedIdx]];
+          sched[kSchedIdx] = (int32_t)gridDim.x + atomicAdd(&st->large_cursor, 1);
+          state = kStateNew;
+        }
+        sched[kSchedEnt] = ent;
+        sched[kSchedState] = state;
       }
-      sched[kSchedEnt] = ent;
-      sched[kSchedState] = state;
+      wave_sync();
+      if (sched[kSchedState] == kStateDone && splitting) {
+        // Out of sources: look for an open part in a few 64-entry windows of the
+        // split table from the shared cursor (entries below it are drained).  An
+        // unpublished entry reads 0 and is left to the workgroup that reserved
+        // it, which claims every part nobody else takes.
+        int32_t end = 0, at = 0;
+        if (lane == 0) {
+          end = __hip_atomic_load(&st->split_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          at = __hip_atomic_load(&st->help_cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        end = read_lane(end, 0);
+        end = end < kSplitCap ? end : kSplitCap;
+        at = read_lane(at, 0);
+        for (int win = 0; win < kHelpWindows && at < end; ++win) {
+          const int32_t e = at + lane;
+          unsigned long long word = 0;
+          int32_t nx = 0;
+          if (e < end) {
+            word = __hip_atomic_load(&args.split[e].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            nx = __hip_atomic_load(&args.split[e].next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          const int32_t parts = (int32_t)(word >> 32);
+          const uint64_t open = ballot(word != 0 && nx < parts);
+          const uint64_t drained = ballot(word != 0 && nx >= parts);
+          // entries drained in a row from the window's start: nobody needs them again
+          const int lead = (int)__builtin_ctzll(~drained);
+          if (lane == 0 && lead > 0) atomicMax(&st->help_cursor, at + lead);
+          if (open) {
+            const int j = (int)__builtin_ctzll(open);
+            int32_t got = 0;
+            if (lane == j) {
+              const int32_t k = atomicAdd(&args.split[e].next, 1);
+              if (k < parts) {
+                sched[kSchedEnt] = e;
+                sched[kSchedU] = (int32_t)(uint32_t)word;
+                sched[kSchedParts] = parts;
+                sched[kSchedPart] = k;
+                sched[kSchedState] = kStateWork;
+                got = 1;
+              }
+            }
+            if (read_lane(got, j)) break;
+            continue;  // lost the race for that entry: look at the same window again
+          }
+          at += kWave;
+        }
+      }
     }
     __syncthreads();
     const int32_t state = sched[kSchedState];
@@ -960,7 +998,11 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
       // a new source: its work w(u), the out-degrees of its middles summed over
       // the workgroup, decides whether it is split
       int32_t parts = 1;
-      if (splitting) {
+      const uint64_t weight = d > kGlobalMin ? kGlobalWeight : 1;
+      // w(u) <= d+(u) max_dplus: compute it only when that bound reaches the quantum
+      // (compared in float, no 64-bit division; a loose bound only costs a sum)
+      if (splitting && (float)d * (float)sched[kSchedMaxD] * (float)weight >=
+                           (float)(uint64_t(1) << args.split_shift)) {
         uint64_t w = 0;
         for (int64_t i = threadIdx.x; i < d; i += kBlock) {
           const int32_t v = col[beg + i];
@@ -971,7 +1013,8 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
         if (lane == 0) red[wave] = w;
         __syncthreads();
         w = red[0] + red[1] + red[2] + red[3];
-        const uint64_t p = (w + args.quantum - 1) / args.quantum;
+        w *= weight;
+        const uint64_t p = (w + (uint64_t(1) << args.split_shift) - 1) >> args.split_shift;
         parts = p < 2 ? 1 : (p > (uint64_t)kMaxParts ? kMaxParts : (int32_t)p);
       }
       if (threadIdx.x == 0) {
@@ -1101,7 +1144,7 @@ struct Tune {
   int force_sorted;
   int blocks_per_cu;  // 0: occupancy limit
   int max_kicks;      // cuckoo placements per key before the stash
-  uint64_t quantum;   // wedges per part of a split source; 0: never split
+  int split_shift;    // log2 of the wedges per part of a split source; 0: never split
 };
 
 tc_status read_tune(const tc_tune* tune, Tune* out) {
@@ -1109,12 +1152,12 @@ tc_status read_tune(const tc_tune* tune, Tune* out) {
   out->force_sorted = 0;
   out->blocks_per_cu = 0;
   out->max_kicks = kMaxKicks;
-  out->quantum = uint64_t(1) << kSplitDefaultLog2;
+  out->split_shift = kSplitDefaultLog2;
   if (!tune) return TC_OK;
   if (tune->split_log2 < -1 || tune->split_log2 > 40)
     return fail(TC_ERR_INVALID_ARG, "tc_tune.split_log2 must be in [-1, 40]");
-  if (tune->split_log2 == -1) out->quantum = 0;
-  else if (tune->split_log2 > 0) out->quantum = uint64_t(1) << tune->split_log2;
+  if (tune->split_log2 == -1) out->split_shift = 0;
+  else if (tune->split_log2 > 0) out->split_shift = tune->split_log2;
   if (tune->max_kicks < -1 || tune->max_kicks > 1024)
     return fail(TC_ERR_INVALID_ARG, "tc_tune.max_kicks must be in [-1, 1024]");
   if (tune->max_kicks != 0) out->max_kicks = tune->max_kicks < 0 ? 0 : tune->max_kicks;
@@ -1163,7 +1206,7 @@ CountArgs base_args(const Tune& tune) {
   args.list = ListArgs{nullptr, nullptr, 0, nullptr};
   args.force_sorted = tune.force_sorted;
   args.max_kicks = tune.max_kicks;
-  args.quantum = tune.quantum;
+  args.split_shift = tune.split_shift;
   args.split = nullptr;
   return args;
 }
