@@ -101,6 +101,7 @@ class Pipeline:
         tune = self.tune if tune is None else tune
         if self.support is None:
             self.support = torch.empty(self.dag_col.numel(), dtype=torch.int32, device=self.device)
+        if self.ws_support is None:
             self.ws_support = _bytes(_lib.tc_edge_support_workspace(self.n), self.device)
         _lib.tc_edge_support(self.n, self.dag_ptr, self.dag_col, self.support, self.support_m,
                              self.ws_support, total=self.total, tune=tune, stream=stream)
