@@ -206,6 +206,28 @@ tc_status tc_count_per_vertex(const tc_csr* dag, uint64_t* per_vertex, uint64_t*
                               const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
 
 /*
+ * tc_count_per_vertex_noalloc - tc_count_per_vertex for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and results, with the
+ * scratch (class counters, the split table, the binned source list, a scratch
+ * total) in one static device array of the library instead of a caller
+ * workspace.  The caller still passes the DAG and the outputs.
+ *
+ *   dag         oriented CSR with n <= 2^22 vertices (the array holds 16.1 MiB
+ *               per device); a larger n returns TC_ERR_CAPACITY, nothing launched
+ *   per_vertex  device uint64[dag->n] (written, not accumulated)
+ *   total       device uint64[1] or NULL (written when non-NULL)
+ *   tune        launch parameters or NULL
+ * Each device holds its own copy of the array (looked up on the first call on
+ * that device) until the process ends.  Every call on one device shares it:
+ * calls that overlap on one device, on any streams, race and give wrong counts;
+ * serialise them.  Nothing is allocated and no allocating library routine is
+ * called.
+ */
+tc_status tc_count_per_vertex_noalloc(const tc_csr* dag, uint64_t* per_vertex, uint64_t* total,
+                                      const tc_tune* tune, void* stream);
+
+/*
  * tc_count_batched - per-graph triangle counts of many independent graphs in
  * one launch.
  *

@@ -80,6 +80,8 @@ def _load() -> ctypes.CDLL:
     lib.tc_count.argtypes = [csr, p, tune, p, sz, p]
     lib.tc_count_per_vertex.restype = i32
     lib.tc_count_per_vertex.argtypes = [csr, p, p, tune, p, sz, p]
+    lib.tc_count_per_vertex_noalloc.restype = i32
+    lib.tc_count_per_vertex_noalloc.argtypes = [csr, p, p, tune, p]
     lib.tc_count_batched.restype = i32
     lib.tc_count_batched.argtypes = [csr, i64, p, p, p, p, tune, p, sz, p]
     lib.tc_pack_pairs.restype = i32
@@ -210,6 +212,18 @@ def tc_count_per_vertex(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_per_vertex, ws, ctypes.byref(csr), _ptr(per_vertex), _ptr(total),
              _tune_ref(tune), stream=stream)
+
+
+def tc_count_per_vertex_noalloc(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                                per_vertex: torch.Tensor, total: torch.Tensor | None, *,
+                                tune=None, stream=None) -> None:
+    """tc_count_per_vertex with its scratch in the library's static device array (no
+    workspace argument; n up to 2^22)."""
+    if per_vertex.numel() != n:
+        raise ValueError("per_vertex must hold n counts")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _check(LIB.tc_count_per_vertex_noalloc(ctypes.byref(csr), _ptr(per_vertex), _ptr(total),
+                                           _tune_ref(tune), _stream(stream)))
 
 
 def tc_count_batched_workspace(n: int) -> int:

@@ -41,6 +41,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 
 namespace tc {
 namespace {
@@ -1539,4 +1540,66 @@ extern "C" tc_status tc_count_diamonds(const tc_csr* dag, int64_t edge_capacity,
   if (st != TC_OK) return st;
   diamond_reduce_kernel<<<grid_for(edge_capacity, 256, 8192), 256, 0, s>>>(L.sup, m_out, total);
   return check_hip(hipGetLastError(), "tc_count_diamonds launch") == TC_OK ? ok() : TC_ERR_HIP;
+}
+
+// ---- per-vertex count without a caller workspace ------------------------------
+//
+// The workspace of tc_count_per_vertex (class counters, the binned source list,
+// a scratch total) lives in one file-scope device array instead.  Host code
+// never passes the array's name to a kernel: its device address is taken once
+// per device with hipGetSymbolAddress and kept below.
+
+namespace tc {
+namespace {
+
+constexpr int64_t kNoAllocMaxVertices = int64_t(1) << 22;
+// carve_count(nullptr, kNoAllocMaxVertices, false).bytes, checked on every call
+constexpr size_t kNoAllocBytes =
+    (size_t(4) << 22) + kSplitCap * sizeof(SplitEntry) + 1024;
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {nullptr};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+tc_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(TC_ERR_UNSUPPORTED, "device %d beyond 64 devices", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return check_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(TC_ERR_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TC_OK;
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_count_per_vertex_noalloc(const tc_csr* dag, uint64_t* per_vertex,
+                                                 uint64_t* total, const tc_tune* tune,
+                                                 void* stream) {
+  using namespace tc;
+  tc_status st = check_dag(dag);
+  if (st != TC_OK) return st;
+  if (dag->n > kNoAllocMaxVertices)
+    return fail(TC_ERR_CAPACITY, "n=%lld is above the %lld vertices the static scratch holds",
+                (long long)dag->n, (long long)kNoAllocMaxVertices);
+  const size_t need = carve_count(nullptr, dag->n, false).bytes;
+  if (need > kNoAllocBytes)
+    return fail(TC_ERR_CAPACITY, "scratch of %zu bytes is below the required %zu", kNoAllocBytes,
+                need);
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws)) != TC_OK) return st;
+  size_t ws_bytes = kNoAllocBytes;
+  return count_dispatch<true>(dag, total, per_vertex, false, 0, nullptr, nullptr, tune, ws,
+                              &ws_bytes, stream);
 }
