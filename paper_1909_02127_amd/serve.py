@@ -273,14 +273,15 @@ def lane_bytes(lib, max_pairs: int, max_vertices: int, max_graphs: int) -> int:
 def plan_lanes(lib, budget_bytes: int, *, small_lanes: int = 3, small_pairs: int = 32_000_000,
                small_vertices: int = 8_000_000, small_graphs: int = 512, large_lanes: int = 1,
                large_pairs: int = 70_000_000, large_vertices: int = 1 << 22) -> list[Lane]:
-    """The lane pool: large lanes (index 0 ...) holding one graph of up to large_pairs pairs
-    on large_vertices vertices each, then small lanes holding up to small_graphs graphs with
-    small_pairs pairs on small_vertices vertices together.  Raises ValueError when the pool
-    does not fit `budget_bytes` of device memory."""
+    """The lane pool: large lanes (index 0 ...) holding graphs of up to large_pairs pairs
+    on large_vertices vertices together, then small lanes holding up to small_graphs graphs
+    with small_pairs pairs on small_vertices vertices together.  A large lane takes large
+    requests first and, when none is queued, a batch of small ones (up to small_graphs).
+    Raises ValueError when the pool does not fit `budget_bytes` of device memory."""
     lanes = []
     for _ in range(large_lanes):
-        lanes.append(Lane(len(lanes), True, large_pairs, large_vertices, 1,
-                          lane_bytes(lib, large_pairs, large_vertices, 1)))
+        lanes.append(Lane(len(lanes), True, large_pairs, large_vertices, small_graphs,
+                          lane_bytes(lib, large_pairs, large_vertices, small_graphs)))
     for _ in range(small_lanes):
         lanes.append(Lane(len(lanes), False, small_pairs, small_vertices, small_graphs,
                           lane_bytes(lib, small_pairs, small_vertices, small_graphs)))
@@ -363,10 +364,13 @@ class DeviceExecutor:
             if G > 1:
                 L.tc_pack_pairs(pair_off, vtx_off, b["src"][:p], b["dst"][:p], stream=stream)
             sizes = b["sizes"]
-            L.tc_build_csr(n, b["src"][:p], b["dst"][:p], b["row_ptr"][: n + 1], b["col"],
-                           sizes[0:1], b["ws_build"], stream=stream)
-            L.tc_orient(n, b["row_ptr"][: n + 1], b["col"], L.TC_ORDER_DEGREE,
-                        b["dag_ptr"][: n + 1], b["dag_col"], sizes[1:2], b["ws_orient"],
+            # output capacities of this batch (not of the lane): the orientation's tiles and
+            # scan are sized by them
+            q = max(p, 1)
+            L.tc_build_csr(n, b["src"][:p], b["dst"][:p], b["row_ptr"][: n + 1],
+                           b["col"][: 2 * q], sizes[0:1], b["ws_build"], stream=stream)
+            L.tc_orient(n, b["row_ptr"][: n + 1], b["col"][: 2 * q], L.TC_ORDER_DEGREE,
+                        b["dag_ptr"][: n + 1], b["dag_col"][:q], sizes[1:2], b["ws_orient"],
                         stream=stream)
             L.tc_count_batched(n, b["dag_ptr"][: n + 1], b["dag_col"], vtx_off, b["totals"][:G],
                                b["ws_count"], per_vertex=b["pv"][:n], tune=self.tune,

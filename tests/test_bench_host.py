@@ -115,7 +115,7 @@ def test_pmc_summary_scales_by_the_calibration_copy(fake_root, monkeypatch):
 def _profile_commands(path):
     if path.endswith(".json"):
         with open(path) as f:
-            return json.load(f)["commands"]
+            return [c for c in json.load(f)["commands"] if c.startswith("rocprofv3 -")]
     with open(path) as f:
         return [ln[1:].strip() for ln in f
                 if ln.startswith("#") and ln[1:].strip().startswith("rocprofv3 -")]
@@ -161,3 +161,11 @@ def test_default_workload_is_scale24_with_a_stored_oracle_count():
     g = bench.golden_for(bench.DEFAULT_WORKLOAD)
     assert g is not None and g["triangles"] > 2**32 and g["sum_t"] == 3 * g["triangles"]
     assert bench.golden_for("rmat-s20-ef16") is None
+
+
+def test_calibration_copy_is_the_repeated_one():
+    """A one-off larger copy (a clone of a bigger array) is not taken for the calibration
+    copy, which the benchmark runs three times."""
+    assert bench.calibration_copies([6.3e6, 5.243e5, 5.242e5, 5.244e5, 10.0]) == [
+        5.243e5, 5.242e5, 5.244e5]
+    assert bench.calibration_copies([7.0, 100.0, 99.0]) == [100.0, 99.0]
