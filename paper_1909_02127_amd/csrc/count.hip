@@ -56,7 +56,7 @@ constexpr int kSmallSide = 128;  // slots per cuckoo half for kSmallMax keys (lo
 constexpr int kStash = 32;
 constexpr int kMaxKicks = 48;
 constexpr int kUnroll = 4;       // 64-wide loads in flight per wave while streaming N+(v)
-constexpr int kShortMax = 64;    // middles with d+(v) < kShortMax may be walked as one concatenation
+constexpr int kShortMax = 128;   // middles with d+(v) < kShortMax may be walked as one concatenation
 constexpr int kShortMinLists = 4;  // ... when a batch of 64 middles holds at least this many
 constexpr int kWin = 2;          // 64-wide windows per step of that walk
 constexpr int32_t kEmpty = -1;
@@ -595,7 +595,7 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
     wave_sync();
     if (marks) ws.mark[start - base] = -1;
     int32_t w[kWin], mid[kWin];
-    int64_t at[kWin];
+    OffT at[kWin];  // column index; int32 offsets keep the address arithmetic 32-bit
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       const int32_t pos = base + k * kWave + lane;
@@ -603,8 +603,11 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
       mid[k] = K == kKindList ? __shfl(v, sk, kWave) : 0;
       // the segment's list is the last non-empty one starting at or before pos,
       // so for pos < total, start(sk) <= pos < start(sk) + len(sk)
-      at[k] = (int64_t)pos + (int64_t)__shfl(delta, sk, kWave);
-      w[k] = pos < total ? col[at[k]] : kNoKey;
+      at[k] = (OffT)pos + __shfl(delta, sk, kWave);
+      if (sizeof(OffT) == 4)
+        w[k] = pos < total ? list_at(col, (uint32_t)at[k]) : kNoKey;
+      else
+        w[k] = pos < total ? col[at[k]] : kNoKey;
     }
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
