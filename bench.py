@@ -299,6 +299,8 @@ def cpu_baseline(workload, s_host, d_host, n, m, frac: float | None = None):
     frac * n (ids are permuted by the generator, so that is a uniform sample of sources;
     frac = 1 for graphs of up to 2^22 vertices, 1/8 beyond) and its time is scaled by
     n / sources to the whole graph."""
+    import numpy as np
+
     import oracle
     if frac is None:
         frac = 1.0 if n <= (1 << 22) else 1 / 8
@@ -314,6 +316,13 @@ def cpu_baseline(workload, s_host, d_host, n, m, frac: float | None = None):
     t3 = time.perf_counter()
     t_count = (t3 - t2) * n / k
     whole = k >= n
+    # the same count on one core, over a smaller prefix (an eighth of the sample)
+    k1 = max(1, k // 8)
+    t4 = time.perf_counter()
+    oracle.count(dp, dc, per_vertex=True, threads=1, sources=k1)
+    t_count1 = (time.perf_counter() - t4) * n / k1
+    # restore the OpenMP thread count (an empty graph: nothing is counted)
+    oracle.count(np.zeros(2, dtype=np.int64), np.zeros(0, dtype=np.int32), threads=threads)
     return {
         "value": m / (t1 - t0 + t2 - t1 + t_count) / 1e9,
         "unit": "GTEPS",
@@ -325,6 +334,9 @@ def cpu_baseline(workload, s_host, d_host, n, m, frac: float | None = None):
                    f"{t3 - t2:.2f}s, scaled to {t_count:.2f}s for all") +
                    f" ({threads} OpenMP threads)"),
         "count_only_gteps": m / t_count / 1e9,
+        "count_only_gteps_1core": m / t_count1 / 1e9,
+        "count_1core_sample": f"the sources below {k1} of {n}, {time.perf_counter() - t4:.2f}s on one "
+                              f"thread, scaled to {t_count1:.1f}s for all",
         "total": int(total) if whole else None,
     }
 
