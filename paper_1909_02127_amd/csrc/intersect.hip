@@ -12,7 +12,8 @@
 // steps, 64 consecutive chunks per wave, and every wave takes one contiguous
 // run of those spans.  A lane finds its edge by a search of P, its place in
 // that edge's merge by the merge-path diagonal search, and merges one element
-// per step, moving on to the next edge with a non-empty stretch at a
+// per step from its chunk's elements, staged first in LDS (all loads in
+// flight at once), moving on to the next edge with a non-empty stretch at a
 // stretch's end.  Ties take A = N+(u) first, and a match is counted when A[i]
 // is taken while B = N+(v)'s head equals it, so each common neighbour is found
 // exactly once, in the chunk that takes A[i].
@@ -29,7 +30,7 @@ namespace tc {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSteps = 32;                        // merge steps per lane and span chunk
+constexpr int kSteps = 16;                        // merge steps per lane and span chunk
 constexpr int64_t kSpan = (int64_t)kWave * kSteps;  // merge steps per wave and span
 constexpr int32_t kPastEnd = INT32_MAX;            // head of an exhausted list (ids < 2^31 - 1)
 
@@ -111,23 +112,26 @@ __device__ __forceinline__ int64_t gallop_upper(const int64_t* __restrict__ P, i
   return upper_bound(P, prev, at < hi ? at : hi, x);
 }
 
-// One list element, or kPastEnd past its end.
-__device__ __forceinline__ int32_t head(const int32_t* __restrict__ col, int64_t beg, int64_t i,
-                                        int64_t len) {
-  return i < len ? col[beg + i] : kPastEnd;
+// Element i of the column array by a 32-bit offset from its (uniform) base.
+__device__ __forceinline__ int32_t list_at(const int32_t* __restrict__ col, uint32_t i) {
+  return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(col) + (uint64_t)i * 4u);
 }
 
-template <bool Support, typename OffT>
-__global__ __launch_bounds__(kBlock) void merge_kernel(int64_t cap, const OffT* __restrict__ rp,
+template <bool Support, bool Narrow, typename OffT>
+__global__ __launch_bounds__(kBlock, 4) void merge_kernel(int64_t cap, const OffT* __restrict__ rp,
                                                      const int32_t* __restrict__ col,
                                                      const int32_t* __restrict__ src_of,
                                                      const int64_t* __restrict__ P,
                                                      const int64_t* __restrict__ m_out,
                                                      uint64_t* __restrict__ total,
                                                      uint32_t* __restrict__ sup) {
+  __shared__ int32_t stage_all[(kBlock / kWave) * 2 * (kSteps + 1) * kWave];
   if (*m_out < 0) return;
   const int64_t S = P[cap];
   const int lane = lane_id();
+  // this lane's staging slots: slot t of A at sa[t * kWave], of B at sb[t * kWave]
+  int32_t* const sa = stage_all + (threadIdx.x / kWave) * 2 * (kSteps + 1) * kWave + lane;
+  int32_t* const sb = sa + (kSteps + 1) * kWave;
   const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
   const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   // this wave's contiguous run of spans
@@ -167,32 +171,55 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(int64_t cap, const OffT* 
         if (col[ab + mid] <= col[bb + k - mid - 1]) lo = mid + 1;
         else hi = mid;
       }
-      int64_t i = lo, j = k - lo;
-      int32_t av = head(col, ab, i, a);
-      int32_t bv = head(col, bb, j, b);
+      const int64_t i = lo, j = k - lo;
       const int64_t stop = pend < pe1 ? pend : pe1;
+      const int q = (int)(stop - p);  // merge steps of this edge in this chunk, 1..kSteps
+      // Stage the elements these q steps can take, A[i, i + q] and B[j, j + q] (past a
+      // list's end: kPastEnd), in this lane's LDS slots.  The loads take indices clamped
+      // to the list (a, b >= 1), so all of them are in flight together.
+      {
+        int32_t ra[kSteps + 1], rb[kSteps + 1];
+        if (Narrow) {
+          // column indices below 2^30: 32-bit offsets from the (uniform) column base
+          const uint32_t x0 = (uint32_t)(ab + i), xl = (uint32_t)(ab + a - 1);
+          const uint32_t y0 = (uint32_t)(bb + j), yl = (uint32_t)(bb + b - 1);
+#pragma unroll
+          for (int t = 0; t <= kSteps; ++t) {
+            ra[t] = list_at(col, x0 + t < xl ? x0 + t : xl);
+            rb[t] = list_at(col, y0 + t < yl ? y0 + t : yl);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t <= kSteps; ++t) {
+            const int64_t x = i + t, y = j + t;
+            ra[t] = col[ab + (x < a ? x : a - 1)];
+            rb[t] = col[bb + (y < b ? y : b - 1)];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t <= kSteps; ++t) {
+          sa[t * kWave] = i + t < a ? ra[t] : kPastEnd;
+          sb[t * kWave] = j + t < b ? rb[t] : kPastEnd;
+        }
+      }
+      int32_t ia = 0, ib = 0;
+      int32_t av = sa[0], bv = sb[0];
       uint32_t cuv = 0;
-      for (int64_t q = p; q < stop; ++q) {
+      for (int s = 0; s < q; ++s) {
         const bool take_a = av <= bv;
         if (take_a && av == bv) {
           ++cuv;
           if (Support) {
-            atomicAdd(&sup[ab + i], 1u);  // the edge (u, w)
-            atomicAdd(&sup[bb + j], 1u);  // the edge (v, w)
+            atomicAdd(&sup[ab + i + ia], 1u);  // the edge (u, w)
+            atomicAdd(&sup[bb + j + ib], 1u);  // the edge (v, w)
           }
         }
-        // one load per step: the next element of the list just taken from
-        const int64_t nbeg = take_a ? ab : bb;
-        const int64_t nidx = take_a ? i + 1 : j + 1;
-        const int64_t nlen = take_a ? a : b;
-        const int32_t x = head(col, nbeg, nidx, nlen);
-        if (take_a) {
-          i = nidx;
-          av = x;
-        } else {
-          j = nidx;
-          bv = x;
-        }
+        // one LDS read per step: the next element of the list just taken from
+        if (take_a) ++ia;
+        else ++ib;
+        const int32_t x = take_a ? sa[ia * kWave] : sb[ib * kWave];
+        if (take_a) av = x;
+        else bv = x;
       }
       hits += cuv;
       if (Support && cuv) atomicAdd(&sup[e], cuv);  // the edge (u, v)
@@ -235,17 +262,21 @@ tc_status intersect_impl(int64_t n, const OffT* rp, const int32_t* col, int64_t 
   if (e != hipSuccess) return check_hip(e, "segmented intersection scan");
   intersect_finish_scan_kernel<<<1, 1, 0, s>>>(L.partial, scan_num_tiles(cap), cap, L.P);
   if (sup) clear_u32_kernel<<<grid_for(cap, 256, 8192), 256, 0, s>>>(sup, m_out);
-  int per_cu = 0;
-  if (sup)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, merge_kernel<true, OffT>, kBlock, 0);
+  // 4 workgroups per CU (the launch bound), the most the LDS staging allows
+  const int grid = 4 * device_cu_count();
+  const bool narrow = cap < (int64_t(1) << 30);
+  if (sup && narrow)
+    merge_kernel<true, true, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                           total, sup);
+  else if (sup)
+    merge_kernel<true, false, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                            total, sup);
+  else if (narrow)
+    merge_kernel<false, true, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                            total, nullptr);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, merge_kernel<false, OffT>, kBlock, 0);
-  const int grid = std::max(per_cu, 1) * device_cu_count();
-  if (sup)
-    merge_kernel<true, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out, total, sup);
-  else
-    merge_kernel<false, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out, total,
-                                                      nullptr);
+    merge_kernel<false, false, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                             total, nullptr);
   return check_hip(hipGetLastError(), "tc_segmented_intersect launch");
 }
 

@@ -160,3 +160,29 @@ def test_intersect_rmat_scale20_full(tc):
     # oracle's own pins check against its diamond enumeration)
     w = want.astype(np.uint64)
     assert dia == int((w * (w - 1) // 2).sum())
+
+
+def test_intersect_wide_column_offsets(tc):
+    """An edge capacity of 2^30 or more makes the merge kernel address the column array with
+    64-bit offsets (below it, 32-bit offsets from the array's base); same counts."""
+    from paper_1909_02127_amd import _lib
+    s, d, n = graphgen.rmat(10, 16, 4)
+    p = _pipe(tc, n, s.numpy(), d.numpy())
+    T, want = _oracle_support(n, s.numpy(), d.numpy())
+    cap = (1 << 30) + 1
+    col = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    m = p.dag_col.numel()
+    col[:m].copy_(p.dag_col)
+    sup = torch.full((cap,), 7, dtype=torch.int32, device="cuda")
+    ws = torch.empty(_lib.tc_segmented_intersect_workspace(n, cap), dtype=torch.uint8,
+                     device="cuda")
+    total = torch.zeros(1, dtype=torch.int64, device="cuda")
+    m_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _lib.tc_segmented_intersect(n, p.dag_ptr, col, total, m_out, ws, support=sup)
+    torch.cuda.synchronize()
+    mm = int(m_out.item())
+    assert mm == int(p.dag_ptr[-1].item()) and int(total.item()) == T
+    np.testing.assert_array_equal(sup[:mm].cpu().numpy().view(np.uint32), want)
+    _lib.tc_segmented_intersect(n, p.dag_ptr, col, total, m_out, ws)
+    torch.cuda.synchronize()
+    assert int(total.item()) == T
