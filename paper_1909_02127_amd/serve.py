@@ -49,6 +49,7 @@ class Request:
     total: int | None = None
     per_vertex: np.ndarray | None = None
     error: str | None = None
+    large: bool = False  # admitted to the large lanes' queue
 
     @property
     def num_pairs(self) -> int:
@@ -95,6 +96,7 @@ def validate(req: Request) -> str | None:
 @dataclass
 class Stats:
     latencies: list = field(default_factory=list)
+    large_flags: list = field(default_factory=list)  # per latency: the request was large
     completed: int = 0
     rejected: int = 0
     failed: int = 0
@@ -107,7 +109,11 @@ class Stats:
 
     def summary(self, warmup: int = 0) -> dict:
         lat = np.array(self.latencies[warmup:], dtype=np.float64) * 1e3
+        big = np.array(self.large_flags[warmup:], dtype=bool)
         span = (self.last_done or 0.0) - (self.first_arrival or 0.0)
+
+        def pct(x, q):
+            return float(np.percentile(x, q)) if x.size else None
         return {
             "completed": self.completed,
             "rejected": self.rejected,
@@ -117,6 +123,11 @@ class Stats:
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_ms": float(lat.mean()) if lat.size else None,
+            # the two classes apart: the small lanes' requests and the large ones
+            "small_p50_ms": pct(lat[~big], 50) if big.size == lat.size else None,
+            "small_p99_ms": pct(lat[~big], 99) if big.size == lat.size else None,
+            "large_p50_ms": pct(lat[big], 50) if big.size == lat.size else None,
+            "large_p99_ms": pct(lat[big], 99) if big.size == lat.size else None,
             "graphs_per_s": self.completed / span if span > 0 else None,
             "max_in_use_bytes": self.max_in_use,
             "max_inflight_batches": self.max_inflight_batches,
@@ -162,6 +173,7 @@ class Engine:
         if self._small_cap is not None and self._small_cap.fits(req.num_pairs, req.n):
             self.small_q.append(req)
         elif any(ln.fits(req.num_pairs, req.n) for ln in self._large_caps):
+            req.large = True
             self.large_q.append(req)
         else:
             self._finish_now(req, "request is larger than every lane of the device pool", True)
@@ -218,6 +230,7 @@ class Engine:
                 else:
                     r.total, r.per_vertex = totals[k], per_vertex[k]
                     self.stats.latencies.append(now - r.arrival)
+                    self.stats.large_flags.append(r.large)
                     self.stats.completed += 1
                 self.finished.append(r)
             self.stats.last_done = now

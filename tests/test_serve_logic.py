@@ -2,6 +2,7 @@
 FIFO order within a queue, small requests never behind large ones, error isolation and
 rejection, with a fake executor whose answers come from the oracle."""
 import numpy as np
+import pytest
 
 import graphgen
 import oracle
@@ -152,3 +153,20 @@ def test_summary_percentiles():
     s = st.summary()
     assert s["completed"] == 30 and s["p50_ms"] <= s["p99_ms"]
     assert s["graphs_per_s"] > 0
+
+
+def test_summary_splits_small_and_large_requests():
+    """Latencies are also reported per class: requests the small lanes take and the large
+    ones (admitted to the large lanes' queue)."""
+    reqs = _requests(40, large_every=9)
+    eng = Engine(FakeExecutor(_lanes()), clock=FakeClock())
+    st = eng.run(reqs, idle_sleep=0)
+    s = st.summary()
+    n_large = sum(r.large for r in reqs)
+    assert n_large == sum(r.num_pairs > 4000 for r in reqs) > 0
+    assert len(st.large_flags) == len(st.latencies) == 40
+    assert s["small_p50_ms"] is not None and s["large_p99_ms"] is not None
+    lat = np.array(st.latencies) * 1e3
+    big = np.array(st.large_flags)
+    assert s["large_p99_ms"] == pytest.approx(np.percentile(lat[big], 99))
+    assert s["small_p50_ms"] == pytest.approx(np.percentile(lat[~big], 50))
