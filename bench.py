@@ -728,7 +728,9 @@ def serve_main(args, spec):
     budget = 64 << 30
     big_pairs = max(int(g[0].numel()) for g in large)
     big_n = max(g[2] for g in large)
-    lanes = plan_lanes(_lib, budget, small_lanes=3, small_pairs=24_000_000,
+    # four lanes, one stream each: HIP gives a process four hardware queues by default, and a
+    # stream that shares a queue with a large lane waits behind its graph in order
+    lanes = plan_lanes(_lib, budget, small_lanes=2, small_pairs=24_000_000,
                        small_vertices=6_000_000, small_graphs=256, large_lanes=2,
                        large_pairs=big_pairs, large_vertices=big_n)
     ex = DeviceExecutor(lanes)

@@ -97,6 +97,9 @@ def validate(req: Request) -> str | None:
 class Stats:
     latencies: list = field(default_factory=list)
     large_flags: list = field(default_factory=list)  # per latency: the request was large
+    intervals: list = field(default_factory=list)  # per batch: (launched, seen done) host times
+    launch_s: float = 0.0   # host time spent enqueueing batches (copies, kernel launches)
+    collect_s: float = 0.0  # host time spent reading batches' results
     completed: int = 0
     rejected: int = 0
     failed: int = 0
@@ -114,6 +117,16 @@ class Stats:
 
         def pct(x, q):
             return float(np.percentile(x, q)) if x.size else None
+
+        # the time at least one batch was on the device (launch to its completion being seen)
+        busy, end = 0.0, None
+        for a, b in sorted(self.intervals):
+            if end is None or a > end:
+                busy += b - a
+                end = b
+            elif b > end:
+                busy += b - end
+                end = b
         return {
             "completed": self.completed,
             "rejected": self.rejected,
@@ -131,6 +144,9 @@ class Stats:
             "graphs_per_s": self.completed / span if span > 0 else None,
             "max_in_use_bytes": self.max_in_use,
             "max_inflight_batches": self.max_inflight_batches,
+            "device_busy_frac": busy / span if span > 0 else None,
+            "host_launch_frac": self.launch_s / span if span > 0 else None,
+            "host_collect_frac": self.collect_s / span if span > 0 else None,
         }
 
 
@@ -145,7 +161,7 @@ class Engine:
         self.clock = clock
         self.small_q: collections.deque[Request] = collections.deque()
         self.large_q: collections.deque[Request] = collections.deque()
-        self.inflight: dict[int, tuple[object, list[Request]]] = {}  # lane -> (handle, reqs)
+        self.inflight: dict[int, tuple[object, list[Request], float]] = {}  # lane -> (handle, reqs, launched)
         self.stats = Stats()
         self.finished: list[Request] = []
         small = [ln for ln in self.lanes if not ln.large]
@@ -206,7 +222,8 @@ class Engine:
             for r in batch:
                 r.admitted = now
             handle = self.ex.launch(lane.index, batch)
-            self.inflight[lane.index] = (handle, batch)
+            self.stats.launch_s += self.clock() - now
+            self.inflight[lane.index] = (handle, batch, now)
             self.stats.batches += 1
             self.stats.large_batches += int(lane.large)
             self.stats.max_inflight_batches = max(self.stats.max_inflight_batches,
@@ -216,12 +233,15 @@ class Engine:
 
     def _poll(self) -> None:
         for li in list(self.inflight):
-            handle, reqs = self.inflight[li]
+            handle, reqs, launched = self.inflight[li]
             if not self.ex.ready(handle):
                 continue
+            t0 = self.clock()
             totals, per_vertex, error = self.ex.collect(handle)
             del self.inflight[li]
             now = self.clock()
+            self.stats.collect_s += now - t0
+            self.stats.intervals.append((launched, now))
             for k, r in enumerate(reqs):
                 r.done = now
                 if error is not None:
@@ -307,7 +327,10 @@ def plan_lanes(lib, budget_bytes: int, *, small_lanes: int = 3, small_pairs: int
 class DeviceExecutor:
     """Runs batches on the GPU through the C ABI, one resident lane per batch in flight."""
 
-    def __init__(self, lanes: list[Lane], device="cuda", *, tune=None):
+    def __init__(self, lanes: list[Lane], device="cuda", *, tune=None, large_tune=None):
+        """tune: tc_tune of the small lanes' counts; large_tune: of the large lanes' (None:
+        tune).  A large lane's count is one persistent launch over every CU; a smaller grid
+        (blocks_per_cu) leaves workgroup slots to the small lanes' batches meanwhile."""
         import torch
 
         from . import _lib
@@ -315,6 +338,7 @@ class DeviceExecutor:
         self.lib = _lib
         self.device = torch.device(device)
         self.tune = tune
+        self.large_tune = tune if large_tune is None else large_tune
         self.lanes = list(lanes)
         self.slots = [self._alloc(ln) for ln in self.lanes]
 
@@ -386,7 +410,8 @@ class DeviceExecutor:
                         b["dag_ptr"][: n + 1], b["dag_col"][:q], sizes[1:2], b["ws_orient"],
                         stream=stream)
             L.tc_count_batched(n, b["dag_ptr"][: n + 1], b["dag_col"], vtx_off, b["totals"][:G],
-                               b["ws_count"], per_vertex=b["pv"][:n], tune=self.tune,
+                               b["ws_count"], per_vertex=b["pv"][:n],
+                               tune=self.large_tune if self.lanes[lane_index].large else self.tune,
                                stream=stream)
             b["h_totals"][:G].copy_(b["totals"][:G], non_blocking=True)
             b["h_pv"][:n].copy_(b["pv"][:n], non_blocking=True)

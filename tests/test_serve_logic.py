@@ -170,3 +170,15 @@ def test_summary_splits_small_and_large_requests():
     big = np.array(st.large_flags)
     assert s["large_p99_ms"] == pytest.approx(np.percentile(lat[big], 99))
     assert s["small_p50_ms"] == pytest.approx(np.percentile(lat[~big], 50))
+
+
+def test_device_busy_fraction_merges_overlapping_batches():
+    from paper_1909_02127_amd.serve import Stats
+    st = Stats()
+    st.first_arrival, st.last_done = 0.0, 10.0
+    st.intervals = [(1.0, 3.0), (2.0, 4.0), (6.0, 7.0), (6.5, 6.8)]
+    assert st.summary()["device_busy_frac"] == pytest.approx(0.4)
+    reqs = _requests(30)
+    eng = Engine(FakeExecutor(_lanes()), clock=FakeClock())
+    s = eng.run(reqs, idle_sleep=0).summary()
+    assert 0.0 < s["device_busy_frac"] <= 1.0
