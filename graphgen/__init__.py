@@ -116,6 +116,13 @@ def uniform_u32(num: int, seed: int, stream: int, *, start: int = 0, device="cpu
     return mix_u32(idx, seed, stream)
 
 
+def vertex_labels(n: int, k: int, seed: int, *, device="cpu") -> torch.Tensor:
+    """A label in [0, k) for each of n vertices (int32), uniform, from counter-based words."""
+    if k < 1:
+        raise ValueError("k >= 1 labels")
+    return (uniform_u32(n, seed, stream=0x1AB, device=device) % k).to(torch.int32)
+
+
 def random_permutation(n: int, seed: int, *, device="cpu") -> torch.Tensor:
     """A seeded permutation of [0, n): argsort of counter-based keys (ties by index)."""
     keys = uniform_u32(n, seed, stream=0x5EED) * n + torch.arange(n, dtype=torch.int64)

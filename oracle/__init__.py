@@ -58,6 +58,8 @@ def _load():
         lib.oracle_count_k4.argtypes = [i64, p, p]
         lib.oracle_count_diamonds.restype = ctypes.c_uint64
         lib.oracle_count_diamonds.argtypes = [i64, i64, p, p]
+        lib.oracle_count_labelled.restype = ctypes.c_uint64
+        lib.oracle_count_labelled.argtypes = [i64, p, p, p, i32, i32, i32]
         lib.oracle_kcore.restype = i64
         lib.oracle_kcore.argtypes = [i64, p, p, i32, p]
         lib.oracle_edge_support.restype = i64
@@ -193,6 +195,27 @@ def diamonds(n: int, src, dst) -> int:
     """Diamonds from raw pairs: clean -> count."""
     row_ptr, col = clean(n, src, dst)
     return count_diamonds(row_ptr, col)
+
+
+def count_labelled(dag_ptr: np.ndarray, dag_col: np.ndarray, labels, query) -> int:
+    """Triangles of an oriented graph whose vertices' label multiset equals the query's
+    three labels."""
+    lib = _load()
+    dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
+    dag_col = _i32(dag_col)
+    labels = _i32(labels)
+    q = [int(x) for x in query]
+    if len(q) != 3:
+        raise ValueError("the query has three node labels")
+    return int(lib.oracle_count_labelled(dag_ptr.size - 1, _ptr(dag_ptr), _ptr(dag_col),
+                                         _ptr(labels), q[0], q[1], q[2]))
+
+
+def labelled(n: int, src, dst, labels, query, *, order: int = ORDER_DEGREE) -> int:
+    """Labelled triangles of a raw pair list (clean, orient, count)."""
+    rp, col = clean(n, src, dst)
+    dp, dc = orient(rp, col, order)
+    return count_labelled(dp, dc, labels, query)
 
 
 def kcore(row_ptr: np.ndarray, col: np.ndarray, k: int = 2) -> np.ndarray:

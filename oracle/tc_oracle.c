@@ -45,6 +45,10 @@
  *  - oracle_count_diamonds: the diamond query (two triangles sharing an edge),
  *    a query with two neighbourhood-equivalence classes (Def. 3), each with its
  *    own unique mapping order.
+ *  - oracle_count_labelled: the labelled triangle query (Sec. II-A: matching
+ *    with node label information): a triangle {a, b, c} of G matches the query
+ *    with node labels {l0, l1, l2} when the multiset of its vertices' labels
+ *    equals the query's; each matching triangle counts once (as a subgraph).
  *
  * Every function is pinned by the CPU test suite against brute force over
  * vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms and invariants.
@@ -426,6 +430,47 @@ uint64_t oracle_count_diamonds(int64_t n, int64_t sources, const int64_t* row_pt
         else { ++k; ++i; ++j; }
       }
       total += k * (k - 1) / 2;  /* k >= 2 only: 2-look-ahead on the candidates */
+    }
+  }
+  return total;
+}
+
+/*
+ * Labelled triangles: the triangles {a, b, c} of the oriented graph whose label
+ * multiset {L(a), L(b), L(c)} equals {q0, q1, q2}.  Every triangle is found once
+ * by the node iterator of oracle_count; its three labels are sorted and
+ * compared with the sorted query.  Single-threaded.
+ */
+static void sort3(int32_t* x, int32_t* y, int32_t* z) {
+  int32_t t;
+  if (*x > *y) { t = *x; *x = *y; *y = t; }
+  if (*y > *z) { t = *y; *y = *z; *z = t; }
+  if (*x > *y) { t = *x; *x = *y; *y = t; }
+}
+
+uint64_t oracle_count_labelled(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col,
+                               const int32_t* labels, int32_t q0, int32_t q1, int32_t q2) {
+  uint64_t total = 0;
+  sort3(&q0, &q1, &q2);
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
+      int64_t v = dag_col[e];
+      int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];
+      int64_t j = dag_ptr[v], jend = dag_ptr[v + 1];
+      while (i < iend && j < jend) {
+        int32_t a = dag_col[i], b = dag_col[j];
+        if (a < b) {
+          ++i;
+        } else if (b < a) {
+          ++j;
+        } else {
+          int32_t x = labels[u], y = labels[v], z = labels[a];
+          sort3(&x, &y, &z);
+          if (x == q0 && y == q1 && z == q2) ++total;
+          ++i;
+          ++j;
+        }
+      }
     }
   }
   return total;

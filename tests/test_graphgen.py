@@ -68,3 +68,12 @@ def test_poisson_arrivals():
     t = graphgen.poisson_arrivals(20000, qps=100.0, seed=5)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] / 20000 - 0.01) < 0.0005
+
+
+def test_vertex_labels_in_range_and_seeded():
+    a = graphgen.vertex_labels(5000, 4, 3)
+    assert a.dtype == torch.int32 and int(a.min()) >= 0 and int(a.max()) < 4
+    assert torch.equal(a, graphgen.vertex_labels(5000, 4, 3))
+    assert not torch.equal(a, graphgen.vertex_labels(5000, 4, 4))
+    counts = torch.bincount(a.long(), minlength=4)
+    assert int(counts.min()) > 1000  # roughly uniform

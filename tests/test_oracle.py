@@ -578,3 +578,62 @@ def test_diamonds_small_rmat_against_edge_support(seed):
     # the bounded sample of the benchmark's baseline: all lower ends = the whole count
     assert oracle.count_diamonds(rp, col, sources=n) == want
     assert oracle.count_diamonds(rp, col, sources=0) == 0
+
+
+# ---- labelled triangles ---------------------------------------------------------------
+
+def _labels(n, k, seed):
+    return np.random.default_rng(seed).integers(0, k, max(n, 1)).astype(np.int32)[:n]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_labelled_brute_force_random_tiny(seed):
+    """Every vertex triple checked for the three edges and the label multiset."""
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(3, 30))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.2, 0.5, 0.9])), seed)
+    n, s, d = pins.noisy(n, s, d, seed)
+    k = int(rng.integers(1, 4))
+    lab = _labels(n, k, seed)
+    tris = pins.brute_force_sets(n, s, d)
+    for q in [(0, 0, 0), (0, 0, 1), (0, 1, 2), (1, 1, 2), (2, 1, 0), (0, 1, 1)]:
+        want = sum(sorted(int(lab[x]) for x in t) == sorted(q) for t in tris)
+        for order in (oracle.ORDER_DEGREE, oracle.ORDER_ID):
+            assert oracle.labelled(n, s, d, lab, q, order=order) == want, (q, order)
+
+
+def test_labelled_closed_forms():
+    """K_n with label classes of sizes a, b, c: C(a,3) triangles labelled AAA, C(a,2) b AAB,
+    a b c ABC; one label everywhere gives every triangle."""
+    from math import comb
+    a, b, c = 5, 4, 3
+    n, s, d = pins.complete(a + b + c)
+    lab = np.array([0] * a + [1] * b + [2] * c, dtype=np.int32)
+    perm = np.random.default_rng(1).permutation(n)
+    lab = lab[perm]  # labels need not follow the ids
+    assert oracle.labelled(n, s, d, lab, (0, 0, 0)) == comb(a, 3)
+    assert oracle.labelled(n, s, d, lab, (0, 1, 0)) == comb(a, 2) * b
+    assert oracle.labelled(n, s, d, lab, (1, 2, 2)) == b * comb(c, 2)
+    assert oracle.labelled(n, s, d, lab, (2, 1, 0)) == a * b * c
+    assert oracle.labelled(n, s, d, lab, (3, 0, 0)) == 0
+    assert oracle.labelled(n, s, d, np.zeros(n, np.int32), (0, 0, 0)) == comb(n, 3)
+    # a wheel whose hub has its own label: every triangle is hub + two rim vertices
+    k = 9
+    s = [0] * k + list(range(1, k + 1))
+    d = list(range(1, k + 1)) + [i % k + 1 for i in range(1, k + 1)]
+    lab = np.array([5] + [7] * k, dtype=np.int32)
+    assert oracle.labelled(k + 1, s, d, lab, (5, 7, 7)) == k
+    assert oracle.labelled(k + 1, s, d, lab, (7, 7, 7)) == 0
+
+
+def test_labelled_multisets_partition_the_triangles():
+    """Summed over every label multiset, the labelled counts give the unlabelled total."""
+    import itertools
+    s, d, n = graphgen.rmat(9, 8, 5)
+    s, d = s.numpy(), d.numpy()
+    k = 3
+    lab = _labels(n, k, 5)
+    T = oracle.triangles(n, s, d)
+    parts = sum(oracle.labelled(n, s, d, lab, q)
+                for q in itertools.combinations_with_replacement(range(k), 3))
+    assert parts == T > 0
