@@ -51,6 +51,10 @@ WORKLOADS = {
     "intersect-rmat-s20-ef16": dict(kind="intersect", scale=20, ef=16, seed=20, offset_bytes=4),
     # the diamond query (two triangles sharing an edge) on the scale-20 graph
     "diamond-rmat-s20-ef16": dict(kind="diamond", scale=20, ef=16, seed=20, offset_bytes=4),
+    # labelled triangle queries, one of each shape ({a,a,a}, {a,a,b}, {a,b,c}), on the
+    # scale-20 graph with four uniform vertex labels
+    "labelled-rmat-s20-ef16": dict(kind="labelled", scale=20, ef=16, seed=20, offset_bytes=4,
+                                   labels=4),
 }
 
 
@@ -122,7 +126,8 @@ def counter_traffic(workload: str):
 
 def _profile_kernel(workload: str) -> str:
     """The dominant kernel a workload's profile summaries are named for."""
-    return "k4_kernel" if WORKLOADS[workload]["kind"] == "k4" else "count_kernel"
+    kind = WORKLOADS[workload]["kind"]
+    return {"k4": "k4_kernel", "intersect": "merge_kernel"}.get(kind, "count_kernel")
 
 
 def _short_kernel_name(name: str) -> str:
@@ -1095,6 +1100,108 @@ def diamond_main(args, spec):
     print(json.dumps(out), flush=True)
 
 
+LABELLED_QUERIES = ((0, 0, 0), (1, 1, 2), (0, 1, 3))
+
+
+def label_filter(dag_ptr, dag_col, n: int, labels, query):
+    """The DAG edges whose label pair is a sub-multiset of the query (the filter of
+    tc_count_labelled), as a CSR, and the filter's own algorithmic bytes: the labels of every
+    source, the row bounds, out-lists and neighbour labels of the sources whose label is in
+    the query, and the filtered DAG written."""
+    import torch
+    o = dag_ptr.element_size()
+    a, b, c = sorted(query)
+    dp = (dag_ptr[1:] - dag_ptr[:-1]).to(torch.int64)
+    rows = torch.repeat_interleave(torch.arange(n, device=dag_ptr.device), dp)
+    lu = labels[rows]
+    lv = labels[dag_col[: rows.numel()].to(torch.int64)]
+    lo, hi = torch.minimum(lu, lv), torch.maximum(lu, lv)
+    fits = ((lo == a) & ((hi == b) | (hi == c))) | ((lo == b) & (hi == c))
+    cand = (labels == a) | (labels == b) | (labels == c)
+    e_cand = int(dp[cand].sum().item())
+    kept_rows = rows[fits]
+    cnt = torch.bincount(kept_rows, minlength=n)
+    fptr = torch.zeros(n + 1, dtype=dag_ptr.dtype, device=dag_ptr.device)
+    fptr[1:] = torch.cumsum(cnt, 0).to(dag_ptr.dtype)
+    fcol = dag_col[: rows.numel()][fits].contiguous()
+    m_kept = int(fcol.numel())
+    b_filter = 4 * n + 2 * o * int(cand.sum().item()) + 8 * e_cand + o * (n + 1) + 4 * m_kept
+    return fptr, fcol, m_kept, b_filter
+
+
+def labelled_main(args, spec):
+    """tc_count_labelled on the resident DAG with seeded vertex labels: one query of each
+    shape per step, each count checked against the oracle."""
+    import torch
+    import graphgen
+    import paper_1909_02127_amd as tc
+
+    dev = torch.device("cuda:0")
+    s, d, n = make_graph(dict(spec, kind="rmat"), dev)
+    ob = spec["offset_bytes"]
+    lab = graphgen.vertex_labels(n, spec["labels"], spec["seed"], device=dev)
+    pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, device=dev)
+    pipe.enqueue(s, d)
+    res = pipe.result()
+    per_q, counts, kept = {}, {}, {}
+    for q in LABELLED_QUERIES:
+        per_q[q] = _time_ms(lambda q=q: pipe.labelled(lab, q), args.steps, args.warmup)
+        pipe.labelled(lab, q)
+        counts[q] = pipe.labelled_count()
+        kept[q] = int(pipe.labelled_kept.item())
+    ms = sum(per_q.values())
+    # algorithmic bytes: each filter pass plus the count of the DAG it writes
+    b = 0
+    for q in LABELLED_QUERIES:
+        passes = [q]
+        x = sorted(q)
+        if (x[0] == x[1]) != (x[1] == x[2]):
+            t = x[0] if x[0] == x[1] else x[2]
+            passes.append((t, t, t))
+        for pq in passes:
+            fptr, fcol, _, bf = label_filter(pipe.dag_ptr, pipe.dag_col, n, lab, pq)
+            b += bf + algorithmic_bytes(fptr, fcol, n, ob, per_vertex=False)["bytes"]
+            del fptr, fcol
+    achieved = b / (ms / 1e3) / 1e9
+    ok = None
+    cb = None
+    if not args.no_check or not args.no_cpu_baseline:
+        import oracle
+        hs, hd, hl = s.cpu().numpy(), d.cpu().numpy(), lab.cpu().numpy()
+        rp, col = oracle.clean(n, hs, hd)
+        dp, dc = oracle.orient(rp, col)
+        del rp, col
+        t0 = time.perf_counter()
+        want = {q: oracle.count_labelled(dp, dc, hl, q) for q in LABELLED_QUERIES}
+        dt = time.perf_counter() - t0
+        ok = want == counts
+        if not args.no_cpu_baseline:
+            cb = {"value": len(LABELLED_QUERIES) * res.m / dt / 1e9, "unit": "GTEPS", "cores": 1,
+                  "kind": "oracle",
+                  "sample": f"the oracle's labelled count of the {len(LABELLED_QUERIES)} queries "
+                            f"on the whole oriented graph, {dt:.1f}s"}
+    out = {
+        "metric": "labelled triangle queries: GTEPS (m per query time, bit-exact vs oracle)",
+        "value": len(LABELLED_QUERIES) * res.m / (ms / 1e3) / 1e9,
+        "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": res.m, "labels": spec["labels"],
+                   "offset_bytes": ob, "order": "degree", "parallelism": "single-gpu"},
+        "queries": [{"query": list(q), "ms": per_q[q], "matches": counts[q],
+                     "kept_edges": kept[q]} for q in LABELLED_QUERIES],
+        "triangles": res.total,
+        "oracle_match": ok,
+        "roofline": {"bound": "hbm", "kernel": "label filter + count_kernel on the filtered DAG",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b},
+    }
+    if cb is not None:
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
 def ablation_main(args, spec):
     """Time the fused count and the paper's materialised two-iteration advance (with and
     without the NE filter) in both orders on one graph; all counts must agree."""
@@ -1276,6 +1383,8 @@ def main():
         return intersect_main(args, spec)
     if spec["kind"] == "diamond":
         return diamond_main(args, spec)
+    if spec["kind"] == "labelled":
+        return labelled_main(args, spec)
     out = graph_line(args, args.workload, dev, cpu=not args.no_cpu_baseline)
     if args.workload == DEFAULT_WORKLOAD and args.secondary:
         # the scale-20 graph as well: its own timed steps, roofline and oracle check

@@ -390,6 +390,40 @@ tc_status tc_count_diamonds(const tc_csr* dag, int64_t edge_capacity, uint64_t* 
                             void* stream);
 
 /*
+ * tc_count_labelled - number of matches of a labelled triangle query: the
+ * triangles {x, y, z} of the data graph whose vertex labels, as a multiset,
+ * equal the query labels {a, b, c} (a match maps every query node onto a vertex
+ * of the same label, Sec. I; queries with node labels are the extension that
+ * Sec. II-A names).  Each such triangle is counted once, as tc_count counts
+ * the unlabelled ones.
+ * Alg. 1's candidate filtering (Filter+Compute) with labels: a DAG edge is
+ * kept when its two labels form one of the query's edge label pairs (a
+ * sub-multiset of {a, b, c}); the kept edges, compacted in row order, form a
+ * DAG on the same vertices, which tc_count then counts.  For three equal or
+ * three distinct query labels that count is the answer; for {a, a, b} the
+ * count of {a, a, a} (also closed by kept edges only) is subtracted.
+ *
+ *   dag           oriented CSR (as written by tc_orient, either order)
+ *   edge_capacity upper bound on m = dag row_ptr[n] (e.g. the DAG column
+ *                 capacity given to tc_orient); sizes the workspace; at most
+ *                 INT32_MAX with 4-byte offsets
+ *   labels        device int32[n]: the label of every vertex (any values)
+ *   a, b, c       the query labels, in any order
+ *   total         device uint64[1] (written): the number of matches, 0 on a
+ *                 capacity error
+ *   kept_out      device int64[1] or NULL (written): the DAG edges whose labels
+ *                 fit the query, or -TC_ERR_CAPACITY when m > edge_capacity
+ *                 (then nothing is counted)
+ *   tune          launch parameters of the count, or NULL (as for tc_count)
+ *   ws, ws_bytes  workspace: the filtered DAG (offsets and 4 bytes per edge of
+ *                 capacity), 1 byte per edge of capacity for the filter flags,
+ *                 24 bytes per vertex, and tc_count's workspace.
+ */
+tc_status tc_count_labelled(const tc_csr* dag, int64_t edge_capacity, const int32_t* labels,
+                            int32_t a, int32_t b, int32_t c, uint64_t* total, int64_t* kept_out,
+                            const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
+
+/*
  * tc_ne_filter - the candidate filter of Alg. 1: a data vertex can stand for a
  * query node only if its neighbourhood encoding (NE = degree, Sec. III-C)
  * covers the node's; every node of the triangle query has degree 2.  Iterated:

@@ -100,6 +100,8 @@ def _load() -> ctypes.CDLL:
     lib.tc_segmented_intersect.argtypes = [csr, i64, p, p, p, p, sz, p]
     lib.tc_count_diamonds.restype = i32
     lib.tc_count_diamonds.argtypes = [csr, i64, p, p, tune, p, sz, p]
+    lib.tc_count_labelled.restype = i32
+    lib.tc_count_labelled.argtypes = [csr, i64, p, i32, i32, i32, p, p, tune, p, sz, p]
     lib.tc_list_triangles.restype = i32
     lib.tc_list_triangles.argtypes = [csr, p, i64, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
@@ -385,6 +387,30 @@ def tc_count_diamonds(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_diamonds, ws, ctypes.byref(csr), dag_col.numel(), _ptr(total),
              _ptr(m_out), _tune_ref(tune), stream=stream)
+
+
+def tc_count_labelled_workspace(n: int, edge_capacity: int, offset_bytes: int = 4) -> int:
+    csr = tc_csr(n, offset_bytes, None, None)
+    return _ws_query(LIB.tc_count_labelled, ctypes.byref(csr), edge_capacity, None, 0, 0, 0, None,
+                     None, None)
+
+
+def tc_count_labelled(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                      labels: torch.Tensor, query, total: torch.Tensor, ws: torch.Tensor, *,
+                      kept_out: torch.Tensor | None = None, tune=None, stream=None) -> None:
+    """Triangles whose vertex labels equal the query's three labels (as a multiset) into
+    total (int64[1]); kept_out (int64[1]) receives the DAG edges whose labels fit the
+    query, or -TC_ERR_CAPACITY.  The edge capacity is dag_col.numel()."""
+    if labels.dtype != torch.int32 or labels.numel() < n:
+        raise ValueError("labels must be int32 with one entry per vertex")
+    q = [int(x) for x in query]
+    if len(q) != 3:
+        raise ValueError("the query has three labels")
+    if kept_out is not None and (kept_out.dtype != torch.int64 or kept_out.numel() != 1):
+        raise ValueError("kept_out must be int64[1]")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count_labelled, ws, ctypes.byref(csr), dag_col.numel(), _ptr(labels), *q,
+             _ptr(total), _ptr(kept_out), _tune_ref(tune), stream=stream)
 
 
 def tc_list_triangles_workspace(n: int) -> int:

@@ -1,0 +1,291 @@
+// label.hip - tc_count_labelled: triangles whose vertex labels match a
+// labelled triangle query.
+//
+// A match of a labelled query must map every query node to a data vertex of the
+// same label (Sec. I: structure and node labels are matched; Sec. II-A: the
+// method extends to queries with node labels).  Alg. 1 starts by filtering the
+// candidate set (Filter+Compute); with labels, a data edge (u, v) can match a
+// query edge only when the pair of labels {L(u), L(v)} is one of the query's
+// three edge label pairs, i.e. a sub-multiset of the query labels {a, b, c}.
+// The filter keeps exactly those oriented edges, compacted into a DAG of the
+// same vertex set, and the count then runs unchanged on it:
+//   - a triangle of the filtered graph has all three edges kept; for a query
+//     with three equal or three distinct labels that already forces its label
+//     multiset to be the query's, so its count is the answer;
+//   - for {a, a, b} (a != b) the filtered graph also keeps the triangles of
+//     {a, a, a} (every edge is {a, a}), so the count of {a, a, a}, filtered
+//     and counted the same way, is subtracted.
+// In the neighbourhood-equivalence terms of Def. 3, the query's classes are its
+// groups of equal labels; the orientation of the DAG orders the members of
+// each class, and vertices of distinct labels are told apart by the labels, so
+// every labelled match is counted once.
+#include "tc_device.h"
+#include "tc_host.h"
+#include "tc_scan.h"
+
+#include <algorithm>
+
+namespace tc {
+namespace {
+
+// The query labels in ascending order.
+struct Query {
+  int32_t q0, q1, q2;
+};
+
+__device__ __forceinline__ bool label_in(const Query& q, int32_t x) {
+  return x == q.q0 || x == q.q1 || x == q.q2;
+}
+
+// {x, y} is a sub-multiset of {q0, q1, q2}: the sorted pair equals the query
+// with one label removed.
+__device__ __forceinline__ bool pair_fits(const Query& q, int32_t x, int32_t y) {
+  const int32_t lo = x < y ? x : y;
+  const int32_t hi = x < y ? y : x;
+  return (lo == q.q0 && (hi == q.q1 || hi == q.q2)) || (lo == q.q1 && hi == q.q2);
+}
+
+// Rows handled together by one wave: kGroup lanes per row, so that the short
+// out-lists of a sparse graph do not leave most of the wave idle.
+constexpr int kGroup = 16;
+constexpr int kRowsPerWave = kWave / kGroup;
+
+// Reports whether the DAG fits the caller's edge capacity; every later kernel
+// reads this status and does nothing (or writes an empty DAG) when it fails.
+template <typename OffT>
+__global__ void label_status_kernel(const OffT* __restrict__ rp, int64_t n, int64_t cap,
+                                    int64_t* __restrict__ status, uint64_t* __restrict__ totals) {
+  const int64_t m = (int64_t)rp[n];
+  *status = m > cap ? -(int64_t)TC_ERR_CAPACITY : m;
+  totals[0] = 0;
+  totals[1] = 0;
+}
+
+// Pass 1: kept out-degree of every source, and the keep flag of each of its
+// edges.  A source whose label is not in the query keeps nothing and its row is
+// not read.
+template <typename OffT>
+__global__ __launch_bounds__(256) void label_degree_kernel(
+    int64_t n, const OffT* __restrict__ rp, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ labels, Query q, const int64_t* __restrict__ status,
+    uint8_t* __restrict__ keep, int64_t* __restrict__ deg) {
+  const int lane = lane_id();
+  const int g = lane / kGroup, gl = lane % kGroup;
+  const bool bad = *status < 0;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kRowsPerWave;
+       r0 < n; r0 += nwaves * kRowsPerWave) {
+    const int64_t u = r0 + g;
+    int64_t beg = 0, d = 0;
+    int32_t lu = 0;
+    if (u < n && !bad) {
+      lu = labels[u];
+      if (label_in(q, lu)) {
+        beg = (int64_t)rp[u];
+        d = (int64_t)rp[u + 1] - beg;
+      }
+    }
+    int64_t dmax = d;
+    for (int off = kGroup; off < kWave; off <<= 1) {
+      const int64_t o = __shfl_xor(dmax, off, kWave);
+      dmax = o > dmax ? o : dmax;
+    }
+    int64_t kept = 0;
+    for (int64_t i0 = 0; i0 < dmax; i0 += kGroup) {
+      const int64_t i = i0 + gl;
+      bool k = false;
+      if (i < d) {
+        k = pair_fits(q, lu, labels[col[beg + i]]);
+        keep[beg + i] = (uint8_t)k;
+      }
+      const uint64_t b = ballot(k);
+      kept += popc((b >> (g * kGroup)) & 0xFFFFull);
+    }
+    if (u < n && gl == 0) deg[u] = kept;
+  }
+}
+
+struct DegLoad {
+  const int64_t* deg;
+  __device__ int64_t operator()(int64_t i) const { return deg[i]; }
+};
+struct OffStore {
+  int64_t* off;
+  __device__ void operator()(int64_t i, int64_t x) const { off[i] = x; }
+};
+
+// Pass 2: the kept edges of every row, in their order, at the row's new
+// offset; the new row offsets.  When the capacity check failed, or the kept
+// edges exceed the capacity, every row is written empty (the count then sees
+// a graph with no edges).
+template <typename OffT>
+__global__ __launch_bounds__(256) void label_compact_kernel(
+    int64_t n, const OffT* __restrict__ rp, const int32_t* __restrict__ col,
+    const uint8_t* __restrict__ keep, const int64_t* __restrict__ off,
+    const int64_t* __restrict__ partial, int64_t tiles, int64_t cap,
+    const int64_t* __restrict__ status, OffT* __restrict__ frp, int32_t* __restrict__ fcol) {
+  const int lane = lane_id();
+  const int g = lane / kGroup, gl = lane % kGroup;
+  const int64_t kept_total = tiles > 0 ? partial[tiles] : 0;
+  const bool empty = *status < 0 || kept_total > cap;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t first = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kRowsPerWave;
+  if (first == 0 && lane == 0) frp[n] = (OffT)(empty ? 0 : kept_total);
+  for (int64_t r0 = first; r0 < n; r0 += nwaves * kRowsPerWave) {
+    const int64_t u = r0 + g;
+    int64_t beg = 0, d = 0, at = 0;
+    if (u < n) {
+      at = empty ? 0 : off[u];
+      if (gl == 0) frp[u] = (OffT)at;
+      const int64_t next = empty ? 0 : (u + 1 < n ? off[u + 1] : kept_total);
+      if (next > at) {  // the row keeps something: read it
+        beg = (int64_t)rp[u];
+        d = (int64_t)rp[u + 1] - beg;
+      }
+    }
+    int64_t dmax = d;
+    for (int o = kGroup; o < kWave; o <<= 1) {
+      const int64_t x = __shfl_xor(dmax, o, kWave);
+      dmax = x > dmax ? x : dmax;
+    }
+    for (int64_t i0 = 0; i0 < dmax; i0 += kGroup) {
+      const int64_t i = i0 + gl;
+      const bool k = i < d && keep[beg + i];
+      const uint64_t b = (ballot(k) >> (g * kGroup)) & 0xFFFFull;
+      if (k) fcol[at + popc(b & ((1ull << gl) - 1))] = col[beg + i];
+      at += popc(b);
+    }
+  }
+}
+
+// total = t[0] - t[1] (the second count is 0 unless the query is {a, a, b}),
+// 0 on a capacity error; kept_out = the filtered edges of the query, or the
+// error.
+__global__ void label_finish_kernel(const uint64_t* __restrict__ t,
+                                    const int64_t* __restrict__ status, const int64_t* __restrict__ partial,
+                                    int64_t tiles, int64_t cap, uint64_t* __restrict__ total,
+                                    int64_t* __restrict__ kept_out) {
+  const int64_t kept = tiles > 0 ? partial[tiles] : 0;
+  const bool err = *status < 0 || kept > cap;
+  *total = err ? 0 : t[0] - t[1];
+  if (kept_out) *kept_out = *status < 0 ? *status : (kept > cap ? -(int64_t)TC_ERR_CAPACITY : kept);
+}
+
+struct LabelLayout {
+  int64_t* status;
+  uint64_t* t;       // the two counts
+  uint8_t* keep;     // per-edge flag
+  int64_t* deg;      // kept out-degrees
+  int64_t* off;      // their exclusive prefix
+  int64_t* partial;  // scan partials (the last one is the kept total)
+  int64_t* partial2;
+  void* frp;         // filtered DAG row offsets (the input's offset type)
+  int32_t* fcol;     // filtered DAG columns
+  void* cws;         // tc_count workspace
+  size_t cws_bytes;
+  size_t bytes;
+};
+
+LabelLayout carve_label(void* ws, int64_t n, int64_t cap, int offset_bytes, size_t count_bytes) {
+  Carver c(ws);
+  LabelLayout L;
+  L.status = c.take<int64_t>(1);
+  L.t = c.take<uint64_t>(2);
+  L.keep = c.take<uint8_t>(cap);
+  L.deg = c.take<int64_t>(n);
+  L.off = c.take<int64_t>(n);
+  L.partial = c.take<int64_t>(scan_partial_len(n));
+  L.partial2 = c.take<int64_t>(scan_partial_len(n));
+  L.frp = c.take<char>((n + 1) * offset_bytes);
+  L.fcol = c.take<int32_t>(cap);
+  L.cws = c.take<char>((int64_t)count_bytes);
+  L.cws_bytes = count_bytes;
+  L.bytes = c.used();
+  return L;
+}
+
+// One filter of the DAG by the query's label pairs, then one count of the
+// filtered DAG into *t.  `partial` receives the scan partials (its last entry
+// is the number of kept edges).
+template <typename OffT>
+tc_status filter_and_count(const tc_csr* dag, const int32_t* labels, const Query& q, int64_t cap,
+                           const LabelLayout& L, int64_t* partial, uint64_t* t,
+                           const tc_tune* tune, hipStream_t s) {
+  const int64_t n = dag->n;
+  const OffT* rp = static_cast<const OffT*>(dag->row_ptr);
+  OffT* frp = static_cast<OffT*>(L.frp);
+  const int waves_per_block = 256 / kWave;
+  const int grid = grid_for((n + kRowsPerWave - 1) / kRowsPerWave, waves_per_block, 1 << 16);
+  if (n > 0)
+    label_degree_kernel<OffT><<<grid, 256, 0, s>>>(n, rp, dag->col, labels, q, L.status, L.keep,
+                                                   L.deg);
+  hipError_t e = scan_exclusive<OpSum>(n, DegLoad{L.deg}, OffStore{L.off}, partial, s);
+  if (e != hipSuccess) return check_hip(e, "label filter scan");
+  const int64_t tiles = scan_num_tiles(n);
+  label_compact_kernel<OffT><<<n > 0 ? grid : 1, 256, 0, s>>>(n, rp, dag->col, L.keep, L.off,
+                                                             partial, tiles, cap, L.status, frp,
+                                                             L.fcol);
+  if ((e = hipGetLastError()) != hipSuccess) return check_hip(e, "label filter launch");
+  tc_csr f{n, dag->offset_bytes, L.frp, L.fcol};
+  size_t bytes = L.cws_bytes;
+  return tc_count(&f, t, tune, L.cws, &bytes, s);
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_count_labelled(const tc_csr* dag, int64_t edge_capacity,
+                                       const int32_t* labels, int32_t a, int32_t b, int32_t c,
+                                       uint64_t* total, int64_t* kept_out, const tc_tune* tune,
+                                       void* ws, size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  if (!dag) return fail(TC_ERR_INVALID_ARG, "dag is NULL");
+  const int64_t n = dag->n;
+  if (n < 0) return fail(TC_ERR_INVALID_ARG, "negative n");
+  if (n > INT32_MAX) return fail(TC_ERR_UNSUPPORTED, "n=%lld needs ids beyond int32", (long long)n);
+  if (dag->offset_bytes != 4 && dag->offset_bytes != 8)
+    return fail(TC_ERR_INVALID_ARG, "offset_bytes must be 4 or 8, got %d", dag->offset_bytes);
+  if (edge_capacity < 0) return fail(TC_ERR_INVALID_ARG, "negative edge_capacity");
+  if (edge_capacity > ((int64_t)1 << 40))
+    return fail(TC_ERR_UNSUPPORTED, "edge_capacity=%lld is beyond 2^40", (long long)edge_capacity);
+  if (dag->offset_bytes == 4 && edge_capacity > INT32_MAX)
+    return fail(TC_ERR_INVALID_ARG, "edge_capacity=%lld does not fit 4-byte offsets",
+                (long long)edge_capacity);
+  // the count's workspace (also validates the tune)
+  size_t count_bytes = 0;
+  tc_csr probe{n, dag->offset_bytes, nullptr, nullptr};
+  tc_status st = tc_count(&probe, nullptr, tune, nullptr, &count_bytes, nullptr);
+  if (st != TC_OK) return st;
+  const LabelLayout need = carve_label(nullptr, n, edge_capacity, dag->offset_bytes, count_bytes);
+  if (workspace_query(ws, ws_bytes, need.bytes, &st)) return st;
+  if (!dag->row_ptr || !total || (n > 0 && !labels))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const LabelLayout L = carve_label(ws, n, edge_capacity, dag->offset_bytes, count_bytes);
+  int32_t x[3] = {a, b, c};
+  std::sort(x, x + 3);
+  const Query q{x[0], x[1], x[2]};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool two_classes = (x[0] == x[1]) != (x[1] == x[2]);  // {a, a, b} or {a, b, b}
+  const int32_t twice = x[0] == x[1] ? x[0] : x[2];            // the label that appears twice
+  const Query q_same{twice, twice, twice};
+  const bool w4 = dag->offset_bytes == 4;
+  if (w4)
+    label_status_kernel<int32_t><<<1, 1, 0, s>>>(static_cast<const int32_t*>(dag->row_ptr), n,
+                                                 edge_capacity, L.status, L.t);
+  else
+    label_status_kernel<int64_t><<<1, 1, 0, s>>>(static_cast<const int64_t*>(dag->row_ptr), n,
+                                                 edge_capacity, L.status, L.t);
+  st = w4 ? filter_and_count<int32_t>(dag, labels, q, edge_capacity, L, L.partial, &L.t[0], tune, s)
+          : filter_and_count<int64_t>(dag, labels, q, edge_capacity, L, L.partial, &L.t[0], tune, s);
+  if (st != TC_OK) return st;
+  if (two_classes) {
+    st = w4 ? filter_and_count<int32_t>(dag, labels, q_same, edge_capacity, L, L.partial2, &L.t[1],
+                                        tune, s)
+            : filter_and_count<int64_t>(dag, labels, q_same, edge_capacity, L, L.partial2, &L.t[1],
+                                        tune, s);
+    if (st != TC_OK) return st;
+  }
+  label_finish_kernel<<<1, 1, 0, s>>>(L.t, L.status, L.partial, scan_num_tiles(n), edge_capacity,
+                                      total, kept_out);
+  return check_hip(hipGetLastError(), "tc_count_labelled launch") == TC_OK ? ok() : TC_ERR_HIP;
+}

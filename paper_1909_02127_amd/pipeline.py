@@ -58,6 +58,9 @@ class Pipeline:
         self.ws_diamonds = None
         self.diamond_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.list_count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws_labelled = None
+        self.labelled_total = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.labelled_kept = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_count = _bytes(max(_lib.tc_count_workspace(n),
                                    _lib.tc_count_per_vertex_workspace(n)), dev)
 
@@ -128,6 +131,26 @@ class Pipeline:
                 _lib.tc_count_diamonds_workspace(self.n, self.dag_col.numel()), self.device)
         _lib.tc_count_diamonds(self.n, self.dag_ptr, self.dag_col, self.diamond_total,
                                self.support_m, self.ws_diamonds, tune=tune, stream=stream)
+
+    def labelled(self, labels: torch.Tensor, query, stream=None, tune=None) -> None:
+        """Enqueue tc_count_labelled on the current DAG: the triangles whose vertex labels
+        equal `query` (three labels, any order) into self.labelled_total, the DAG edges
+        whose labels fit the query into self.labelled_kept (read with labelled_count())."""
+        tune = self.tune if tune is None else tune
+        if self.ws_labelled is None:
+            self.ws_labelled = _bytes(_lib.tc_count_labelled_workspace(
+                self.n, self.dag_col.numel(), self.dag_ptr.element_size()), self.device)
+        _lib.tc_count_labelled(self.n, self.dag_ptr, self.dag_col, labels, query,
+                               self.labelled_total, self.ws_labelled,
+                               kept_out=self.labelled_kept, tune=tune, stream=stream)
+
+    def labelled_count(self) -> int:
+        """Synchronise and read the result of labelled()."""
+        torch.cuda.synchronize(self.device)
+        kept = int(self.labelled_kept.item())
+        if kept < 0:
+            raise TcError(-kept, "reported by tc_count_labelled on the device")
+        return int(self.labelled_total.item()) & ((1 << 64) - 1)
 
     def diamond_count(self) -> int:
         """Synchronise and read the result of diamonds()."""
