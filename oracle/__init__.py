@@ -60,6 +60,8 @@ def _load():
         lib.oracle_count_diamonds.argtypes = [i64, i64, p, p]
         lib.oracle_count_labelled.restype = ctypes.c_uint64
         lib.oracle_count_labelled.argtypes = [i64, p, p, p, i32, i32, i32]
+        lib.oracle_count_directed.restype = i64
+        lib.oracle_count_directed.argtypes = [i64, p, p, i64, p, p, i32, i32, i32, i32]
         lib.oracle_kcore.restype = i64
         lib.oracle_kcore.argtypes = [i64, p, p, i32, p]
         lib.oracle_edge_support.restype = i64
@@ -216,6 +218,35 @@ def labelled(n: int, src, dst, labels, query, *, order: int = ORDER_DEGREE) -> i
     rp, col = clean(n, src, dst)
     dp, dc = orient(rp, col, order)
     return count_labelled(dp, dc, labels, query)
+
+
+def count_directed(dag_ptr: np.ndarray, dag_col: np.ndarray, src, dst, pattern, *,
+                   induced: bool = False) -> int:
+    """Matches of a directed triangle query in the arcs src[i] -> dst[i], whose underlying
+    undirected graph the DAG orients.  pattern = (p01, p02, p12): for each pair of query
+    nodes, bit 1 = the lower has an arc to the higher, bit 2 = the reverse."""
+    lib = _load()
+    dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
+    dag_col = _i32(dag_col)
+    s, d = _i32(src), _i32(dst)
+    if s.size != d.size:
+        raise ValueError("src and dst differ in length")
+    p = [int(x) for x in pattern]
+    if len(p) != 3:
+        raise ValueError("the pattern has three node pairs")
+    r = int(lib.oracle_count_directed(dag_ptr.size - 1, _ptr(dag_ptr), _ptr(dag_col), s.size,
+                                      _ptr(s), _ptr(d), p[0], p[1], p[2], int(bool(induced))))
+    if r < 0:
+        raise OracleError(f"oracle_count_directed failed ({r})")
+    return r
+
+
+def directed(n: int, src, dst, pattern, *, induced: bool = False,
+             order: int = ORDER_DEGREE) -> int:
+    """Directed triangle query on a raw arc list (clean, orient, match)."""
+    rp, col = clean(n, src, dst)
+    dp, dc = orient(rp, col, order)
+    return count_directed(dp, dc, src, dst, pattern, induced=induced)
 
 
 def kcore(row_ptr: np.ndarray, col: np.ndarray, k: int = 2) -> np.ndarray:

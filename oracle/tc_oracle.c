@@ -49,6 +49,14 @@
  *    with node label information): a triangle {a, b, c} of G matches the query
  *    with node labels {l0, l1, l2} when the multiset of its vertices' labels
  *    equals the query's; each matching triangle counts once (as a subgraph).
+ *  - oracle_count_directed: the directed triangle query (Sec. II-A: the method
+ *    extends to directed graphs): the data graph is a set of arcs, its
+ *    triangles those of the underlying undirected graph; a match maps the
+ *    query's three nodes one-to-one onto a triangle so that every query arc
+ *    lands on an arc of the same direction (or, induced, so that the arcs
+ *    between two matched vertices are exactly the images of the query's).
+ *    Matches count as subgraphs: embeddings divided by the query's
+ *    automorphisms.
  *
  * Every function is pinned by the CPU test suite against brute force over
  * vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms and invariants.
@@ -474,4 +482,96 @@ uint64_t oracle_count_labelled(int64_t n, const int64_t* dag_ptr, const int32_t*
     }
   }
   return total;
+}
+
+/*
+ * oracle_count_directed - the directed triangle query.
+ *
+ * Arcs: the pairs (src[i] -> dst[i]) with src[i] != dst[i], duplicates allowed;
+ * dag_ptr / dag_col orient the underlying undirected graph (as oracle_orient
+ * writes it) and enumerate its triangles.  The query is a directed graph on the
+ * nodes 0, 1, 2 with every pair connected: p01, p02, p12 hold bit 1 when the
+ * lower node has an arc to the higher, bit 2 when the higher has one to the
+ * lower (each in 1..3).  An embedding is a one-to-one map f of the query nodes
+ * onto the three vertices of a triangle such that for every ordered pair
+ * (i, j) of query nodes the query arc i -> j implies the arc f(i) -> f(j)
+ * (induced = 0), or the two are present together (induced = 1).  The result
+ * is the number of embeddings over all triangles divided by the number of
+ * permutations of the query nodes that map its arcs onto its arcs.
+ * Returns -2 if a pair holds an id outside [0, n), -3 for a code outside
+ * 1..3, -1 on allocation failure.  Single-threaded.
+ */
+static int arc_of(int32_t p01, int32_t p02, int32_t p12, int i, int j) {
+  int32_t code = (i == 0 && j == 1) || (i == 1 && j == 0) ? p01
+               : (i == 0 && j == 2) || (i == 2 && j == 0) ? p02 : p12;
+  return i < j ? (code & 1) != 0 : (code & 2) != 0;
+}
+
+static int has_arc(const uint64_t* keys, int64_t nk, int64_t x, int64_t y) {
+  uint64_t want = ((uint64_t)x << 32) | (uint64_t)y;
+  int64_t lo = 0, hi = nk;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (keys[mid] < want) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < nk && keys[lo] == want;
+}
+
+int64_t oracle_count_directed(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col,
+                              int64_t num_pairs, const int32_t* src, const int32_t* dst,
+                              int32_t p01, int32_t p02, int32_t p12, int32_t induced) {
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  if (p01 < 1 || p01 > 3 || p02 < 1 || p02 > 3 || p12 < 1 || p12 > 3) return -3;
+  for (int64_t i = 0; i < num_pairs; ++i)
+    if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return -2;
+  uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(num_pairs > 0 ? num_pairs : 1));
+  if (!keys) return -1;
+  int64_t nk = 0;
+  for (int64_t i = 0; i < num_pairs; ++i)
+    if (src[i] != dst[i]) keys[nk++] = ((uint64_t)(uint32_t)src[i] << 32) | (uint32_t)dst[i];
+  qsort(keys, (size_t)nk, sizeof(uint64_t), cmp_u64);
+  /* the query's automorphisms */
+  int64_t aut = 0;
+  for (int s = 0; s < 6; ++s) {
+    int same = 1;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        if (i != j && arc_of(p01, p02, p12, i, j) != arc_of(p01, p02, p12, perms[s][i], perms[s][j]))
+          same = 0;
+    aut += same;
+  }
+  int64_t embeddings = 0;
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
+      int64_t v = dag_col[e];
+      int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];
+      int64_t j = dag_ptr[v], jend = dag_ptr[v + 1];
+      while (i < iend && j < jend) {
+        int32_t a = dag_col[i], b = dag_col[j];
+        if (a < b) {
+          ++i;
+        } else if (b < a) {
+          ++j;
+        } else {
+          int64_t t[3] = {u, v, a};
+          for (int s = 0; s < 6; ++s) {
+            int ok = 1;
+            for (int x = 0; x < 3 && ok; ++x)
+              for (int y = 0; y < 3 && ok; ++y) {
+                if (x == y) continue;
+                int q = arc_of(p01, p02, p12, x, y);
+                int g = has_arc(keys, nk, t[perms[s][x]], t[perms[s][y]]);
+                if (induced ? q != g : (q && !g)) ok = 0;
+              }
+            embeddings += ok;
+          }
+          ++i;
+          ++j;
+        }
+      }
+    }
+  }
+  free(keys);
+  return embeddings / aut;
 }

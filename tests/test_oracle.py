@@ -637,3 +637,155 @@ def test_labelled_multisets_partition_the_triangles():
     parts = sum(oracle.labelled(n, s, d, lab, q)
                 for q in itertools.combinations_with_replacement(range(k), 3))
     assert parts == T > 0
+
+
+# ---- directed triangles ---------------------------------------------------------------
+
+# directed queries by their arcs on the nodes 0, 1, 2
+_CYCLE = {(0, 1), (1, 2), (2, 0)}
+_FFL = {(0, 1), (1, 2), (0, 2)}  # transitive (feed-forward) triangle
+_ALL_ARCS = {(i, j) for i in range(3) for j in range(3) if i != j}
+
+
+def _codes(arcs):
+    """(p01, p02, p12): bit 1 = the lower node points to the higher, bit 2 = the reverse."""
+    return tuple(int((i, j) in arcs) | 2 * int((j, i) in arcs) for i, j in ((0, 1), (0, 2), (1, 2)))
+
+
+def _arcs(codes):
+    out = set()
+    for (i, j), c in zip(((0, 1), (0, 2), (1, 2)), codes):
+        if c & 1:
+            out.add((i, j))
+        if c & 2:
+            out.add((j, i))
+    return out
+
+
+def _perms3():
+    import itertools
+    return list(itertools.permutations(range(3)))
+
+
+def _brute_directed(n, s, d, arcs_q, induced):
+    """Every ordered triple of distinct vertices as the image of nodes 0, 1, 2, checked arc
+    by arc; divided by the permutations of the query that keep its arcs."""
+    A = {(int(a), int(b)) for a, b in zip(s, d) if a != b}
+    emb = 0
+    for x in range(n):
+        for y in range(n):
+            for z in range(n):
+                if len({x, y, z}) < 3:
+                    continue
+                f = (x, y, z)
+                ok = True
+                for i in range(3):
+                    for j in range(3):
+                        if i == j:
+                            continue
+                        q, g = (i, j) in arcs_q, (f[i], f[j]) in A
+                        if (q != g) if induced else (q and not g):
+                            ok = False
+                emb += ok
+    aut = sum(all(((p[i], p[j]) in arcs_q) == ((i, j) in arcs_q)
+                  for i in range(3) for j in range(3) if i != j) for p in _perms3())
+    assert emb % aut == 0
+    return emb // aut
+
+
+def _random_digraph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.random((n, n)) < p
+    np.fill_diagonal(a, False)
+    s, d = np.nonzero(a)
+    # duplicates and self-loops, which add no arc
+    extra = rng.integers(0, max(n, 1), size=(2, 3))
+    s = np.concatenate([s, s[:2], extra[0], extra[0]])
+    d = np.concatenate([d, d[:2], extra[0], extra[1]])
+    return s.astype(np.int32), d.astype(np.int32)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_directed_brute_force_random_tiny(seed):
+    """All 27 directed triangle queries (every pair of query nodes joined by one arc either
+    way or by both), induced and not, against brute force over ordered vertex triples."""
+    import itertools
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(3, 11))
+    s, d = _random_digraph(n, float(rng.choice([0.3, 0.5, 0.8])), seed)
+    for codes in itertools.product((1, 2, 3), repeat=3):
+        arcs_q = _arcs(codes)
+        for induced in (False, True):
+            want = _brute_directed(n, s, d, arcs_q, induced)
+            order = oracle.ORDER_DEGREE if (seed + codes[0]) % 2 else oracle.ORDER_ID
+            assert oracle.directed(n, s, d, codes, induced=induced, order=order) == want, \
+                (codes, induced)
+
+
+def test_directed_closed_forms():
+    """Tournaments: a triangle is transitive iff one vertex points to both others, so there
+    are sum_v C(out(v), 2) transitive triangles and C(n,3) minus that cyclic ones.  The
+    complete symmetric digraph: every triangle holds 2 cycles and 6 transitive triangles,
+    but as an induced subgraph is only the all-arcs query."""
+    from math import comb
+    for seed, n in ((1, 5), (2, 9), (3, 14)):
+        rng = np.random.default_rng(seed)
+        s, d = [], []
+        for i in range(n):
+            for j in range(i + 1, n):
+                if rng.random() < 0.5:
+                    s.append(i); d.append(j)
+                else:
+                    s.append(j); d.append(i)
+        perm = rng.permutation(n)
+        s, d = perm[np.array(s)], perm[np.array(d)]
+        out = np.bincount(s, minlength=n)
+        trans = sum(comb(int(o), 2) for o in out)
+        for induced in (False, True):
+            assert oracle.directed(n, s, d, _codes(_FFL), induced=induced) == trans
+            assert oracle.directed(n, s, d, _codes(_CYCLE), induced=induced) == comb(n, 3) - trans
+            assert oracle.directed(n, s, d, _codes(_ALL_ARCS), induced=induced) == 0
+    n = 7
+    s = np.array([i for i in range(n) for j in range(n) if i != j])
+    d = np.array([j for i in range(n) for j in range(n) if i != j])
+    assert oracle.directed(n, s, d, _codes(_CYCLE)) == 2 * comb(n, 3)
+    assert oracle.directed(n, s, d, _codes(_FFL)) == 6 * comb(n, 3)
+    assert oracle.directed(n, s, d, _codes(_ALL_ARCS)) == comb(n, 3)
+    assert oracle.directed(n, s, d, _codes(_CYCLE), induced=True) == 0
+    assert oracle.directed(n, s, d, _codes(_ALL_ARCS), induced=True) == comb(n, 3)
+    # a directed cycle of length 3 and a longer one (no triangle)
+    assert oracle.directed(3, [0, 1, 2], [1, 2, 0], _codes(_CYCLE)) == 1
+    assert oracle.directed(3, [0, 1, 2], [1, 2, 0], _codes(_FFL)) == 0
+    assert oracle.directed(5, [0, 1, 2, 3, 4], [1, 2, 3, 4, 0], _codes(_CYCLE)) == 0
+
+
+def test_directed_triad_classes_partition_the_triangles():
+    """Every triangle of the underlying graph is an induced match of exactly one of the 7
+    classes of three-node digraphs with every pair joined; reversing every arc of the graph
+    and of the query changes nothing."""
+    import itertools
+    s, d, n = graphgen.rmat(9, 8, 6)
+    s, d = s.numpy(), d.numpy()
+    # half the pairs also get the reverse arc
+    both = np.arange(s.size) % 2 == 0
+    s2 = np.concatenate([s, d[both]])
+    d2 = np.concatenate([d, s[both]])
+    T = oracle.triangles(n, s2, d2)
+    classes = {}
+    for codes in itertools.product((1, 2, 3), repeat=3):
+        arcs = _arcs(codes)
+        key = min(tuple(sorted((p[i], p[j]) for i, j in arcs)) for p in _perms3())
+        classes.setdefault(key, codes)
+    assert len(classes) == 7
+    counts = {k: oracle.directed(n, s2, d2, c, induced=True) for k, c in classes.items()}
+    assert sum(counts.values()) == T > 0
+    assert min(counts.values()) > 0
+    swap = {1: 2, 2: 1, 3: 3}
+    for c in list(classes.values())[:4]:
+        rc = tuple(swap[x] for x in c)
+        for induced in (False, True):
+            assert oracle.directed(n, d2, s2, rc, induced=induced) == \
+                oracle.directed(n, s2, d2, c, induced=induced)
+    # every arc reciprocal: the all-arcs query counts the undirected triangles
+    s3, d3 = np.concatenate([s, d]), np.concatenate([d, s])
+    assert oracle.directed(n, s3, d3, (3, 3, 3)) == oracle.triangles(n, s, d)
