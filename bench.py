@@ -55,6 +55,9 @@ WORKLOADS = {
     # scale-20 graph with four uniform vertex labels
     "labelled-rmat-s20-ef16": dict(kind="labelled", scale=20, ef=16, seed=20, offset_bytes=4,
                                    labels=4),
+    # directed triangle queries (the 3-cycle and the transitive triangle) on the scale-20
+    # R-MAT pairs read as arcs
+    "directed-rmat-s20-ef16": dict(kind="directed", scale=20, ef=16, seed=20, offset_bytes=4),
 }
 
 
@@ -1202,6 +1205,87 @@ def labelled_main(args, spec):
     print(json.dumps(out), flush=True)
 
 
+DIRECTED_QUERIES = {"cycle": (1, 2, 1), "transitive": (1, 1, 1)}
+
+
+def directed_main(args, spec):
+    """tc_count_directed on the resident DAG and arc directions: the 3-cycle and the
+    transitive triangle per step.  Checked by the seven induced classes summing to the
+    triangle count (the oracle takes minutes per query at this size; the GPU tests compare
+    it with the GPU at smaller scales)."""
+    import itertools
+    import torch
+    import paper_1909_02127_amd as tc
+
+    dev = torch.device("cuda:0")
+    s, d, n = make_graph(dict(spec, kind="rmat"), dev)
+    ob = spec["offset_bytes"]
+    pipe = tc.Pipeline(n, s.numel(), offset_bytes=ob, device=dev)
+    pipe.enqueue(s, d)
+    res = pipe.result()
+    ms_dir = _time_ms(lambda: pipe.edge_directions(s, d), args.steps, args.warmup)
+    per_q, counts = {}, {}
+    for name, q in DIRECTED_QUERIES.items():
+        per_q[name] = _time_ms(lambda q=q: pipe.directed(q), args.steps, args.warmup)
+        pipe.directed(q)
+        counts[name] = pipe.directed_count()
+    ms = sum(per_q.values())
+    ok = None
+    if not args.no_check:
+        classes = {}
+        for codes in itertools.product((1, 2, 3), repeat=3):
+            arcs = {(i, j) for (i, j), c in zip(((0, 1), (0, 2), (1, 2)), codes) if c & 1}
+            arcs |= {(j, i) for (i, j), c in zip(((0, 1), (0, 2), (1, 2)), codes) if c & 2}
+            key = min(tuple(sorted((p[i], p[j]) for i, j in arcs))
+                      for p in itertools.permutations(range(3)))
+            classes.setdefault(key, codes)
+        tot = 0
+        for q in classes.values():
+            pipe.directed(q, induced=True)
+            tot += pipe.directed_count()
+        ok = tot == res.total
+    cb = None
+    if not args.no_cpu_baseline:
+        import oracle
+        hs, hd = s.cpu().numpy(), d.cpu().numpy()
+        rp, col = oracle.clean(n, hs, hd)
+        dp, dc = oracle.orient(rp, col)
+        del rp, col
+        k = n // 64
+        t0 = time.perf_counter()
+        want = oracle.count_directed(dp, dc, hs, hd, DIRECTED_QUERIES["cycle"], sources=k)
+        dt = (time.perf_counter() - t0) * n / k
+        cb = {"value": res.m / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+              "sample": f"the oracle's 3-cycle query over the triangles whose source id is "
+                        f"below {k} of {n} ({want} matches), {dt * k / n:.1f}s, scaled to "
+                        f"{dt:.1f}s for all"}
+    mb = merge_bytes(pipe.dag_ptr, pipe.dag_col, n, ob)
+    # plus one direction byte per live edge and two per match
+    b = len(DIRECTED_QUERIES) * (mb["bytes"] + mb["live_edges"] + 2 * res.total)
+    achieved = b / (ms / 1e3) / 1e9
+    out = {
+        "metric": "directed triangle queries: GTEPS (m per query time)",
+        "value": len(DIRECTED_QUERIES) * res.m / (ms / 1e3) / 1e9,
+        "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": res.m, "offset_bytes": ob,
+                   "order": "degree", "parallelism": "single-gpu"},
+        "queries": [{"query": name, "codes": list(DIRECTED_QUERIES[name]), "ms": per_q[name],
+                     "matches": counts[name]} for name in DIRECTED_QUERIES],
+        "edge_directions_ms": ms_dir,
+        "triangles": res.total,
+        "check": ok,
+        "roofline": {"bound": "hbm", "kernel": "tc_count_directed (whole call)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b},
+    }
+    if cb is not None:
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
 def ablation_main(args, spec):
     """Time the fused count and the paper's materialised two-iteration advance (with and
     without the NE filter) in both orders on one graph; all counts must agree."""
@@ -1385,6 +1469,8 @@ def main():
         return diamond_main(args, spec)
     if spec["kind"] == "labelled":
         return labelled_main(args, spec)
+    if spec["kind"] == "directed":
+        return directed_main(args, spec)
     out = graph_line(args, args.workload, dev, cpu=not args.no_cpu_baseline)
     if args.workload == DEFAULT_WORKLOAD and args.secondary:
         # the scale-20 graph as well: its own timed steps, roofline and oracle check

@@ -424,6 +424,64 @@ tc_status tc_count_labelled(const tc_csr* dag, int64_t edge_capacity, const int3
                             const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
 
 /*
+ * tc_edge_directions - the arc directions of a directed data graph on the DAG
+ * of its underlying undirected graph (Sec. II-A: the method extends to directed
+ * graphs; tc_build_csr and tc_orient keep the undirected edges, this records
+ * which way each one points).
+ *
+ *   dag           oriented CSR built from the same pairs (tc_build_csr of src,
+ *                 dst, then tc_orient)
+ *   edge_capacity upper bound on m = dag row_ptr[n]
+ *   num_pairs     arcs src[i] -> dst[i], device int32[num_pairs] each;
+ *                 duplicates allowed, self-loops ignored
+ *   dir           device uint8[edge_capacity rounded up to a multiple of 4],
+ *                 4-byte aligned (written): dir[e], aligned with dag->col, has
+ *                 bit 0 set when the data graph has the arc from e's row vertex
+ *                 to dag->col[e], bit 1 when it has the reverse arc
+ *   m_out         device int64[1] (written): m, or negative: -TC_ERR_CAPACITY
+ *                 when m > edge_capacity (nothing else written),
+ *                 -TC_ERR_ID_OUT_OF_RANGE for an id outside [0, n), or
+ *                 -TC_ERR_INVALID_ARG for an arc whose pair is not a DAG edge
+ * One thread per arc finds the edge by binary search of the two rows.  No
+ * workspace.
+ */
+tc_status tc_edge_directions(const tc_csr* dag, int64_t edge_capacity, int64_t num_pairs,
+                             const int32_t* src, const int32_t* dst, uint8_t* dir,
+                             int64_t* m_out, void* stream);
+
+/*
+ * tc_count_directed - matches of a directed triangle query: a digraph on the
+ * query nodes 0, 1, 2 with every pair joined by one arc or by both (the seven
+ * such digraphs up to isomorphism include the 3-cycle and the transitive
+ * triangle).  A match maps the query nodes one-to-one onto a triangle of the
+ * underlying graph so that every query arc lands on an arc of the same
+ * direction (induced = 0), or so that the arcs between every two matched
+ * vertices are exactly the images of the query's (induced = 1); matches are
+ * counted as subgraphs (maps divided by the query's automorphisms), as the
+ * undirected count divides |M| by |Q| (Alg. 1).
+ * The enumeration is tc_segmented_intersect's merge over every DAG edge; each
+ * common out-neighbour w of (u, v) reads the directions of (u, v), (u, w) and
+ * (v, w) and adds the matches on that triangle from a 64-entry table built on
+ * the host from the query.
+ *
+ *   dag           oriented CSR; rows ascending
+ *   edge_capacity upper bound on m (sizes the workspace)
+ *   dir           device uint8[edge_capacity] as tc_edge_directions writes it
+ *   p01, p02, p12 the query's node pairs 0-1, 0-2, 1-2, each 1 (lower -> higher),
+ *                 2 (higher -> lower) or 3 (both)
+ *   induced       0 or 1
+ *   total         device uint64[1] (written): the number of matches, 0 on a
+ *                 capacity error
+ *   m_out         device int64[1] (written): m, or -TC_ERR_CAPACITY when m >
+ *                 edge_capacity
+ *   ws, ws_bytes  workspace, as tc_segmented_intersect's.
+ */
+tc_status tc_count_directed(const tc_csr* dag, int64_t edge_capacity, const uint8_t* dir,
+                            int32_t p01, int32_t p02, int32_t p12, int32_t induced,
+                            uint64_t* total, int64_t* m_out, void* ws, size_t* ws_bytes,
+                            void* stream);
+
+/*
  * tc_ne_filter - the candidate filter of Alg. 1: a data vertex can stand for a
  * query node only if its neighbourhood encoding (NE = degree, Sec. III-C)
  * covers the node's; every node of the triangle query has degree 2.  Iterated:

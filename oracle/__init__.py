@@ -61,7 +61,7 @@ def _load():
         lib.oracle_count_labelled.restype = ctypes.c_uint64
         lib.oracle_count_labelled.argtypes = [i64, p, p, p, i32, i32, i32]
         lib.oracle_count_directed.restype = i64
-        lib.oracle_count_directed.argtypes = [i64, p, p, i64, p, p, i32, i32, i32, i32]
+        lib.oracle_count_directed.argtypes = [i64, p, p, i64, p, p, i32, i32, i32, i32, i64]
         lib.oracle_kcore.restype = i64
         lib.oracle_kcore.argtypes = [i64, p, p, i32, p]
         lib.oracle_edge_support.restype = i64
@@ -221,10 +221,11 @@ def labelled(n: int, src, dst, labels, query, *, order: int = ORDER_DEGREE) -> i
 
 
 def count_directed(dag_ptr: np.ndarray, dag_col: np.ndarray, src, dst, pattern, *,
-                   induced: bool = False) -> int:
+                   induced: bool = False, sources=None) -> int:
     """Matches of a directed triangle query in the arcs src[i] -> dst[i], whose underlying
     undirected graph the DAG orients.  pattern = (p01, p02, p12): for each pair of query
-    nodes, bit 1 = the lower has an arc to the higher, bit 2 = the reverse."""
+    nodes, bit 1 = the lower has an arc to the higher, bit 2 = the reverse.  With
+    `sources`, only the triangles whose DAG source has an id below it count."""
     lib = _load()
     dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
     dag_col = _i32(dag_col)
@@ -235,7 +236,8 @@ def count_directed(dag_ptr: np.ndarray, dag_col: np.ndarray, src, dst, pattern, 
     if len(p) != 3:
         raise ValueError("the pattern has three node pairs")
     r = int(lib.oracle_count_directed(dag_ptr.size - 1, _ptr(dag_ptr), _ptr(dag_col), s.size,
-                                      _ptr(s), _ptr(d), p[0], p[1], p[2], int(bool(induced))))
+                                      _ptr(s), _ptr(d), p[0], p[1], p[2], int(bool(induced)),
+                                      _sources(dag_ptr, sources)))
     if r < 0:
         raise OracleError(f"oracle_count_directed failed ({r})")
     return r

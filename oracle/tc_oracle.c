@@ -497,7 +497,9 @@ uint64_t oracle_count_labelled(int64_t n, const int64_t* dag_ptr, const int32_t*
  * (i, j) of query nodes the query arc i -> j implies the arc f(i) -> f(j)
  * (induced = 0), or the two are present together (induced = 1).  The result
  * is the number of embeddings over all triangles divided by the number of
- * permutations of the query nodes that map its arcs onto its arcs.
+ * permutations of the query nodes that map its arcs onto its arcs.  Only the
+ * triangles whose DAG source (first vertex) has an id below `sources` count
+ * (sources = n: all of them).
  * Returns -2 if a pair holds an id outside [0, n), -3 for a code outside
  * 1..3, -1 on allocation failure.  Single-threaded.
  */
@@ -520,7 +522,8 @@ static int has_arc(const uint64_t* keys, int64_t nk, int64_t x, int64_t y) {
 
 int64_t oracle_count_directed(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col,
                               int64_t num_pairs, const int32_t* src, const int32_t* dst,
-                              int32_t p01, int32_t p02, int32_t p12, int32_t induced) {
+                              int32_t p01, int32_t p02, int32_t p12, int32_t induced,
+                              int64_t sources) {
   static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
   if (p01 < 1 || p01 > 3 || p02 < 1 || p02 > 3 || p12 < 1 || p12 > 3) return -3;
   for (int64_t i = 0; i < num_pairs; ++i)
@@ -542,7 +545,7 @@ int64_t oracle_count_directed(int64_t n, const int64_t* dag_ptr, const int32_t* 
     aut += same;
   }
   int64_t embeddings = 0;
-  for (int64_t u = 0; u < n; ++u) {
+  for (int64_t u = 0; u < sources; ++u) {
     for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
       int64_t v = dag_col[e];
       int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];

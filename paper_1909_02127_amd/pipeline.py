@@ -59,6 +59,9 @@ class Pipeline:
         self.diamond_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.list_count = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_labelled = None
+        self.direction = None
+        self.direction_m = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.directed_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.labelled_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.labelled_kept = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_count = _bytes(max(_lib.tc_count_workspace(n),
@@ -151,6 +154,39 @@ class Pipeline:
         if kept < 0:
             raise TcError(-kept, "reported by tc_count_labelled on the device")
         return int(self.labelled_total.item()) & ((1 << 64) - 1)
+
+    def edge_directions(self, src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+        """Enqueue tc_edge_directions: the arcs src[i] -> dst[i] (the pairs given to build)
+        recorded on the current DAG's edges, for directed()."""
+        cap = self.dag_col.numel()
+        if self.direction is None:
+            self.direction = torch.zeros((cap + 3) // 4 * 4, dtype=torch.uint8,
+                                         device=self.device)
+        _lib.tc_edge_directions(self.n, self.dag_ptr, self.dag_col, src, dst, self.direction,
+                                self.direction_m, stream=stream)
+
+    def directed(self, pattern, *, induced: bool = False, stream=None) -> None:
+        """Enqueue tc_count_directed on the current DAG and the directions recorded by
+        edge_directions(): result in self.directed_total (read with directed_count())."""
+        if self.direction is None:
+            raise RuntimeError("edge_directions() must run first")
+        if self.ws_intersect is None:
+            self.ws_intersect = _bytes(
+                _lib.tc_segmented_intersect_workspace(self.n, self.dag_col.numel()), self.device)
+        _lib.tc_count_directed(self.n, self.dag_ptr, self.dag_col, self.direction, pattern,
+                               self.directed_total, self.support_m, self.ws_intersect,
+                               induced=induced, stream=stream)
+
+    def directed_count(self) -> int:
+        """Synchronise and read the result of directed() (and the status of the directions)."""
+        torch.cuda.synchronize(self.device)
+        dm = int(self.direction_m.item())
+        if dm < 0:
+            raise TcError(-dm, "reported by tc_edge_directions on the device")
+        m = int(self.support_m.item())
+        if m < 0:
+            raise TcError(-m, "reported by tc_count_directed on the device")
+        return int(self.directed_total.item()) & ((1 << 64) - 1)
 
     def diamond_count(self) -> int:
         """Synchronise and read the result of diamonds()."""

@@ -789,3 +789,19 @@ def test_directed_triad_classes_partition_the_triangles():
     # every arc reciprocal: the all-arcs query counts the undirected triangles
     s3, d3 = np.concatenate([s, d]), np.concatenate([d, s])
     assert oracle.directed(n, s3, d3, (3, 3, 3)) == oracle.triangles(n, s, d)
+
+
+def test_directed_sources_sample():
+    """The benchmark's bounded sample: the triangles whose DAG source lies below k; all
+    sources give the whole count, none give 0, and the sample grows with k."""
+    s, d, n = graphgen.rmat(8, 8, 3)
+    s, d = s.numpy(), d.numpy()
+    rp, col = oracle.clean(n, s, d)
+    dp, dc = oracle.orient(rp, col)
+    full = oracle.count_directed(dp, dc, s, d, _codes(_CYCLE))
+    assert full > 0
+    assert oracle.count_directed(dp, dc, s, d, _codes(_CYCLE), sources=n) == full
+    assert oracle.count_directed(dp, dc, s, d, _codes(_CYCLE), sources=0) == 0
+    parts = [oracle.count_directed(dp, dc, s, d, _codes(_CYCLE), sources=k)
+             for k in range(0, n + 1, max(1, n // 8))]
+    assert parts == sorted(parts)
