@@ -1259,9 +1259,10 @@ def directed_main(args, spec):
               "sample": f"the oracle's 3-cycle query over the triangles whose source id is "
                         f"below {k} of {n} ({want} matches), {dt * k / n:.1f}s, scaled to "
                         f"{dt:.1f}s for all"}
-    mb = merge_bytes(pipe.dag_ptr, pipe.dag_col, n, ob)
-    # plus one direction byte per live edge and two per match
-    b = len(DIRECTED_QUERIES) * (mb["bytes"] + mb["live_edges"] + 2 * res.total)
+    # the count's bytes, plus the direction bytes: each edge's once as a middle (u, v) and
+    # once beside its key in the source's table, and (v, w) once per closed wedge
+    alg = algorithmic_bytes(pipe.dag_ptr, pipe.dag_col, n, ob, per_vertex=False)
+    b = len(DIRECTED_QUERIES) * (alg["bytes"] + 2 * res.m + res.total)
     achieved = b / (ms / 1e3) / 1e9
     out = {
         "metric": "directed triangle queries: GTEPS (m per query time)",
@@ -1277,7 +1278,7 @@ def directed_main(args, spec):
         "edge_directions_ms": ms_dir,
         "triangles": res.total,
         "check": ok,
-        "roofline": {"bound": "hbm", "kernel": "tc_count_directed (whole call)",
+        "roofline": {"bound": "hbm", "kernel": "count_kernel (directed kind)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": b},
     }

@@ -459,27 +459,24 @@ tc_status tc_edge_directions(const tc_csr* dag, int64_t edge_capacity, int64_t n
  * vertices are exactly the images of the query's (induced = 1); matches are
  * counted as subgraphs (maps divided by the query's automorphisms), as the
  * undirected count divides |M| by |Q| (Alg. 1).
- * The enumeration is tc_segmented_intersect's merge over every DAG edge; each
- * common out-neighbour w of (u, v) reads the directions of (u, v), (u, w) and
- * (v, w) and adds the matches on that triangle from a 64-entry table built on
- * the host from the query.
+ * The enumeration is tc_count's (Alg. 1's advance and non-tree-edge check,
+ * each triangle found once as u -> v -> w): every closed wedge adds the
+ * query's matches on its triangle, looked up in a 64-entry table (built on the
+ * host from the query) by the direction codes of (u, v), (u, w) and (v, w).
+ * The code of (u, w) is kept beside w in the LDS table of N+(u).
  *
- *   dag           oriented CSR; rows ascending
- *   edge_capacity upper bound on m (sizes the workspace)
- *   dir           device uint8[edge_capacity] as tc_edge_directions writes it
+ *   dag           oriented CSR (as written by tc_orient, either order)
+ *   dir           device uint8[m] as tc_edge_directions writes it for this DAG
  *   p01, p02, p12 the query's node pairs 0-1, 0-2, 1-2, each 1 (lower -> higher),
  *                 2 (higher -> lower) or 3 (both)
  *   induced       0 or 1
- *   total         device uint64[1] (written): the number of matches, 0 on a
- *                 capacity error
- *   m_out         device int64[1] (written): m, or -TC_ERR_CAPACITY when m >
- *                 edge_capacity
- *   ws, ws_bytes  workspace, as tc_segmented_intersect's.
+ *   total         device uint64[1] (written): the number of matches
+ *   tune          launch parameters or NULL (as for tc_count)
+ *   ws, ws_bytes  workspace; as tc_count's.
  */
-tc_status tc_count_directed(const tc_csr* dag, int64_t edge_capacity, const uint8_t* dir,
-                            int32_t p01, int32_t p02, int32_t p12, int32_t induced,
-                            uint64_t* total, int64_t* m_out, void* ws, size_t* ws_bytes,
-                            void* stream);
+tc_status tc_count_directed(const tc_csr* dag, const uint8_t* dir, int32_t p01, int32_t p02,
+                            int32_t p12, int32_t induced, uint64_t* total, const tc_tune* tune,
+                            void* ws, size_t* ws_bytes, void* stream);
 
 /*
  * tc_ne_filter - the candidate filter of Alg. 1: a data vertex can stand for a

@@ -105,7 +105,7 @@ def _load() -> ctypes.CDLL:
     lib.tc_edge_directions.restype = i32
     lib.tc_edge_directions.argtypes = [csr, i64, i64, p, p, p, p, p]
     lib.tc_count_directed.restype = i32
-    lib.tc_count_directed.argtypes = [csr, i64, p, i32, i32, i32, i32, p, p, p, sz, p]
+    lib.tc_count_directed.argtypes = [csr, p, i32, i32, i32, i32, p, tune, p, sz, p]
     lib.tc_list_triangles.restype = i32
     lib.tc_list_triangles.argtypes = [csr, p, i64, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
@@ -436,28 +436,25 @@ def tc_edge_directions(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
                                   _ptr(direction), _ptr(m_out), _stream(stream)))
 
 
-def tc_count_directed_workspace(n: int, edge_capacity: int) -> int:
+def tc_count_directed_workspace(n: int) -> int:
     csr = tc_csr(n, 4, None, None)
-    return _ws_query(LIB.tc_count_directed, ctypes.byref(csr), edge_capacity, None, 1, 1, 1, 0,
-                     None, None)
+    return _ws_query(LIB.tc_count_directed, ctypes.byref(csr), None, 1, 1, 1, 0, None, None)
 
 
 def tc_count_directed(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
-                      direction: torch.Tensor, pattern, total: torch.Tensor, m_out: torch.Tensor,
-                      ws: torch.Tensor, *, induced: bool = False, stream=None) -> None:
+                      direction: torch.Tensor, pattern, total: torch.Tensor, ws: torch.Tensor, *,
+                      induced: bool = False, tune=None, stream=None) -> None:
     """Matches of the directed triangle query pattern = (p01, p02, p12) (each 1: lower ->
-    higher node, 2: the reverse, 3: both) into total (int64[1]); m_out (int64[1]) receives
-    m or -TC_ERR_CAPACITY.  The edge capacity is dag_col.numel()."""
+    higher node, 2: the reverse, 3: both) into total (int64[1]), on the DAG and the arc
+    directions tc_edge_directions wrote for it."""
     p = [int(x) for x in pattern]
     if len(p) != 3:
         raise ValueError("the pattern has three node pairs")
     if direction.dtype != torch.uint8 or direction.numel() < dag_col.numel():
         raise ValueError("direction must be uint8 with one entry per dag_col entry")
-    if m_out.dtype != torch.int64 or m_out.numel() != 1:
-        raise ValueError("m_out must be int64[1]")
     csr = make_csr(n, dag_row_ptr, dag_col)
-    _ws_call(LIB.tc_count_directed, ws, ctypes.byref(csr), dag_col.numel(), _ptr(direction), *p,
-             int(bool(induced)), _ptr(total), _ptr(m_out), stream=stream)
+    _ws_call(LIB.tc_count_directed, ws, ctypes.byref(csr), _ptr(direction), *p,
+             int(bool(induced)), _ptr(total), _tune_ref(tune), stream=stream)
 
 
 def tc_list_triangles_workspace(n: int) -> int:

@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", f"-I{ROOT / 'include'}", f"-I{CSRC}"]
 
 SOURCES = ["api.cpp", "build_csr.hip", "orient.hip", "count.hip", "bfs.hip", "clique4.hip",
-           "pack.hip", "intersect.hip", "work.hip", "label.hip"]
+           "pack.hip", "intersect.hip", "work.hip", "label.hip", "directed.hip"]
 
 
 def _compile(src: str) -> Path:

@@ -68,9 +68,15 @@ constexpr int kKindTotal = 0;      // the total (and optionally per-graph / per-
 constexpr int kKindPerVertex = 1;  // plus t(v) for every vertex
 constexpr int kKindList = 2;       // every triangle as a (u, v, w) row
 constexpr int kKindSupport = 3;    // triangles on every oriented edge
+constexpr int kKindDirected = 4;   // matches of a directed query (weighted hits)
 // Kinds that count hits per LDS slot (the (u, w) pairs of a source).
 __host__ __device__ constexpr bool counted(int kind) {
   return kind == kKindPerVertex || kind == kKindSupport;
+}
+// Kinds whose table keeps a word per slot: the hit counters, or (directed) the
+// arc directions of the edge (u, key).
+__host__ __device__ constexpr bool slot_words(int kind) {
+  return counted(kind) || kind == kKindDirected;
 }
 
 // Probe modes, fixed per table slice after it is built.
@@ -413,6 +419,8 @@ struct ListCtx {
   uint32_t* sup;
   int64_t ubeg;
   uint64_t* tv;  // per-vertex counts (kModeGlobal adds t(w) per hit)
+  const uint8_t* dir;   // directed kind: arc directions per DAG edge
+  const uint32_t* tab;  // directed kind: matches per triangle by its direction codes (LDS)
 };
 
 // Writes the wedges u -> v -> w of the lanes set in `hits` as rows (u, v, w).
@@ -449,6 +457,47 @@ __device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ keys,
   return lo < n && keys[lo] == w ? lo : -1;
 }
 
+// Directed kind: the direction code of the edge (u, w) when w is a key of the
+// slice (stored beside the key when the table was built), else -1.
+template <int Mode, bool Wide>
+__device__ __forceinline__ int32_t probe_code(const Table& t, const Slice& sl, int32_t w,
+                                              const ListCtx& lc) {
+  if (Mode == kModeGlobal) {
+    const int32_t pos = find_sorted(sl.gkeys, sl.keys, w);
+    return pos >= 0 ? (int32_t)lc.dir[lc.ubeg + pos] : -1;
+  }
+  if (Mode == kModeSorted) {
+    int lo = 0, len = sl.keys;
+    while (len > 0) {
+      const int half = len >> 1;
+      if (t.slot[lo + half] < w) {
+        lo += half + 1;
+        len -= half + 1;
+      } else {
+        len = half;
+      }
+    }
+    return lo < sl.keys && t.slot[lo] == w ? (int32_t)t.cnt[lo] : -1;
+  }
+  const uint32_t p = hash_product(hash_input<Wide>(w));
+  const uint32_t sa = slot_a_of(p, sl.shift);
+  const uint32_t sb = (uint32_t)sl.side + slot_b_of(p, sl.shift);
+  if (t.slot[sa] == w) return (int32_t)t.cnt[sa];
+  if (t.slot[sb] == w) return (int32_t)t.cnt[sb];
+  if (Mode == kModeStash) {
+    for (int i = 0; i < sl.stash_n; ++i)
+      if (t.stash[i] == w) return (int32_t)t.stash_cnt[i];
+  }
+  return -1;
+}
+
+// The matches of a directed query on the triangle u -> v -> w: the table entry
+// of its three direction codes, 16 c(u, v) + 4 c(u, w) + c(v, w); 0 on a miss.
+__device__ __forceinline__ uint32_t directed_hits(const ListCtx& lc, uint32_t cuv16, int32_t cuw,
+                                                  int64_t vw_edge) {
+  return cuw >= 0 ? lc.tab[cuv16 + 4u * (uint32_t)cuw + lc.dir[vw_edge]] : 0u;
+}
+
 // The wave's hits among the wedges u -> v -> w[lane], with the per-hit work of
 // each kind: LDS slot counters, or (kModeGlobal, which has no table) the
 // per-vertex count t(w) and the support of (u, w) directly.  With Seg (counted
@@ -474,7 +523,7 @@ __device__ __forceinline__ uint64_t probe_mask(const Table& t, const Slice& sl, 
 template <int K, int Mode, bool Wide>
 __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, int len,
                                               const Table& t, const Slice& sl, int32_t v,
-                                              const ListCtx& lc, int64_t jb) {
+                                              const ListCtx& lc, int64_t jb, uint32_t cuv16) {
   const int lane = lane_id();
   uint32_t hv = 0;
   int base = 0;
@@ -485,6 +534,11 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
     for (int k = 0; k < kUnroll; ++k) w[k] = p[k * kWave];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
+      if (K == kKindDirected) {
+        hv += directed_hits(lc, cuv16, probe_code<Mode, Wide>(t, sl, w[k], lc),
+                            jb + base + k * kWave + lane);
+        continue;
+      }
       const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
       hv += popc(b);
       if (K == kKindList) emit(lc, b, v, w[k]);
@@ -504,6 +558,11 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       if (base + k * kWave < len) {
+        if (K == kKindDirected) {
+          hv += directed_hits(lc, cuv16, probe_code<Mode, Wide>(t, sl, w[k], lc),
+                              jb + base + k * kWave + lane);
+          continue;
+        }
         const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
         hv += popc(b);
         if (K == kKindList) emit(lc, b, v, w[k]);
@@ -569,7 +628,8 @@ template <int K, int Mode, bool Wide, typename OffT>
 __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
                                                const int32_t* __restrict__ col, const Table& t,
                                                const Slice& sl, const WaveScratch& ws,
-                                               const ListCtx& lc, uint32_t* seg_hits) {
+                                               const ListCtx& lc, uint32_t* seg_hits,
+                                               uint32_t cuv16) {
   constexpr bool CNT = counted(K);
   const int lane = lane_id();
   const int32_t incl = wave_inclusive_sum32(len);
@@ -595,12 +655,14 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
     wave_sync();
     if (marks) ws.mark[start - base] = -1;
     int32_t w[kWin], mid[kWin];
+    uint32_t c16[kWin];
     OffT at[kWin];  // column index; int32 offsets keep the address arithmetic 32-bit
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       const int32_t pos = base + k * kWave + lane;
       const int32_t sk = seg[k] < 0 ? 0 : seg[k];
       mid[k] = K == kKindList ? __shfl(v, sk, kWave) : 0;
+      c16[k] = K == kKindDirected ? (uint32_t)__shfl((int32_t)cuv16, sk, kWave) : 0u;
       // the segment's list is the last non-empty one starting at or before pos,
       // so for pos < total, start(sk) <= pos < start(sk) + len(sk)
       at[k] = (OffT)pos + __shfl(delta, sk, kWave);
@@ -612,6 +674,11 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       if (base + k * kWave < total) {
+        if (K == kKindDirected) {
+          hv += directed_hits(lc, c16[k], probe_code<Mode, Wide>(t, sl, w[k], lc),
+                              (int64_t)at[k]);
+          continue;
+        }
         // a hit adds to its segment's counter inside the probe (counted kinds)
         const uint64_t b = probe_mask<K, Mode, Wide, CNT>(t, sl, w[k], lc,
                                                           &ws.shits[seg[k] < 0 ? 0 : seg[k]]);
@@ -659,10 +726,12 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
     const int64_t i = first + j * stride;
     int32_t v = 0;
     OffT vb = 0, ve = 0;
+    uint32_t cuv16 = 0;  // directed kind: 16 x the direction code of (u, v)
     if (j < mine) {
       v = nbrs[i];
       vb = row_ptr[v];
       ve = row_ptr[v + 1];
+      if (K == kKindDirected) cuv16 = 16u * lc.dir[lc.ubeg + i];
     }
     const int64_t len = (int64_t)(ve - vb);
     // Only the main probe mode walks short lists together (keeps the rare modes small).
@@ -682,7 +751,8 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
         je = read_lane64((int64_t)ve, j);
       }
       const int32_t vj = read_lane(v, j);
-      const uint32_t hv = scan_list<K, Mode, Wide>(col + jb, (int)(je - jb), t, sl, vj, lc, jb);
+      const uint32_t cj = K == kKindDirected ? (uint32_t)read_lane((int32_t)cuv16, j) : 0u;
+      const uint32_t hv = scan_list<K, Mode, Wide>(col + jb, (int)(je - jb), t, sl, vj, lc, jb, cj);
       src_hits += hv;
       if (counted(K) && lane == j) cv = hv;
     }
@@ -690,7 +760,7 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
       const bool is_short = len > 0 && len < kShortMax;
       uint32_t cs = 0;
       src_hits += scan_short<K, Mode, Wide, OffT>(v, vb, is_short ? (int32_t)len : 0, col, t, sl,
-                                                  ws, lc, &cs);
+                                                  ws, lc, &cs, cuv16);
       cv += cs;
     }
     // the (u, v) counts of the batch's middles, all lanes at once
@@ -713,6 +783,8 @@ struct ListArgs {
   const int64_t* off;
   int64_t cap;
   uint32_t* sup;
+  const uint8_t* dir;   // directed kind: arc directions per DAG edge
+  const uint32_t* tab;  // directed kind: set by the kernel (its LDS copy of the table)
 };
 
 // Count of key w in the slice's table (the per-slot counters).
@@ -747,7 +819,7 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
   const int gr = group_rank<Waves>();
   const int32_t* nbrs = col + beg;
   uint64_t wave_hits = 0;
-  ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u, la.sup, beg, tv};
+  ListCtx lc{la.out, 0, la.cap, t.meta + 3, (int32_t)u, la.sup, beg, tv, la.dir, la.tab};
   if (K == kKindList) {
     lc.base = la.off[u];
     if (gr == 0) t.meta[3] = 0;  // ordered before any hit by the next barrier
@@ -808,6 +880,29 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
       for (int i = gr; i < sl.keys; i += Waves * kWave) t.slot[i] = nbrs[c0 + i];
       group_sync<Waves>();
     }
+    if (K == kKindDirected) {
+      // the direction code of (u, key) beside every key of the slice
+      for (int p = gr; p < sl.keys; p += Waves * kWave) {
+        const uint32_t code = la.dir[beg + c0 + p];
+        if (mode == kModeSorted) {
+          t.cnt[p] = code;  // slot p holds the slice's p-th key
+          continue;
+        }
+        const int32_t w = nbrs[c0 + p];
+        const uint32_t hp = hash_product(hash_input<Wide>(w));
+        const uint32_t s1 = slot_a_of(hp, sl.shift);
+        const uint32_t s2 = (uint32_t)sl.side + slot_b_of(hp, sl.shift);
+        if (t.slot[s1] == w) {
+          t.cnt[s1] = code;
+        } else if (t.slot[s2] == w) {
+          t.cnt[s2] = code;
+        } else {
+          for (int i = 0; i < sl.stash_n; ++i)
+            if (t.stash[i] == w) t.stash_cnt[i] = code;
+        }
+      }
+      group_sync<Waves>();
+    }
     uint64_t src_hits;
     if (mode == kModeCuckoo)
       src_hits = scan_middles<Waves, K, kModeCuckoo, Wide, OffT>(nbrs, d, row_ptr, col, tv, t, sl, ws, lc, pt);
@@ -848,6 +943,12 @@ __device__ uint64_t process_source(int64_t u, int64_t beg, int64_t d,
 }
 
 // Runtime parameters of one count launch.
+// Matches of a directed query on one triangle u -> v -> w of the DAG, by the
+// direction codes of its edges: entry 16 c(u, v) + 4 c(u, w) + c(v, w).
+struct DirCodes {
+  uint8_t v[64];
+};
+
 struct CountArgs {
   SplitEntry* split;   // split table (kSplitCap entries)
   int32_t split_shift;  // log2 of the wedges per part of a split source; 0: never split
@@ -858,6 +959,7 @@ struct CountArgs {
   ListArgs list;
   int max_kicks;
   int force_sorted;
+  DirCodes codes;  // directed kind only
 };
 
 // Persistent count kernel: workgroup-mode sources first (largest class first,
@@ -871,9 +973,16 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
                                                        CountState* __restrict__ st,
                                                        uint64_t* __restrict__ total,
                                                        uint64_t* __restrict__ tv, CountArgs args) {
-  constexpr bool PV = counted(K);  // table layout with per-slot counters
+  constexpr bool PV = slot_words(K);  // table layout with a word per slot
   __shared__ __align__(16) char smem[smem_total(PV)];
+  __shared__ uint32_t dtab[K == kKindDirected ? 64 : 1];
   if ((K == kKindList || K == kKindSupport) && *args.list_status < 0) return;
+  ListArgs la = args.list;
+  if (K == kKindDirected) {
+    if (threadIdx.x < 64) dtab[threadIdx.x] = args.codes.v[threadIdx.x];
+    __syncthreads();
+    la.tab = dtab;
+  }
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   WaveScratch ws;
@@ -1043,8 +1152,7 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
     }
     const Part pt{sched[kSchedPart], sched[kSchedParts]};
     const uint64_t h = process_source<kWavesPerBlock, K, Wide, OffT>(
-        u, beg, d, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, args.list,
-        pt);
+        u, beg, d, row_ptr, col, tv, big, ws, kChunk, args.max_kicks, args.force_sorted, la, pt);
     hits += h;
     credit(u, h);
     if (args.src_cnt && h && lane == 0)
@@ -1085,7 +1193,7 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
       }
       const uint64_t h = process_source<1, K, Wide, OffT>(u, beg, d, row_ptr, col, tv, mine, ws,
                                                           kSmallMax, args.max_kicks,
-                                                          args.force_sorted, args.list, Part{0, 1});
+                                                          args.force_sorted, la, Part{0, 1});
       hits += h;
       credit(u, h);
       if (args.src_cnt && h && lane == 0)
@@ -1101,6 +1209,8 @@ __global__ __launch_bounds__(kBlock, 8) void count_kernel(const OffT* __restrict
   }
   if (pend_h && lane == 0)
     atomicAdd((unsigned long long*)&args.totals[pend_g], (unsigned long long)pend_h);
+  // the directed kind's sums are per lane
+  if (K == kKindDirected) hits = (uint64_t)wave_sum((int64_t)hits);
   if (lane == 0 && hits) atomicAdd((unsigned long long*)total, (unsigned long long)hits);
 }
 
@@ -1212,6 +1322,7 @@ CountArgs base_args(const Tune& tune) {
   args.max_kicks = tune.max_kicks;
   args.split_shift = tune.split_shift;
   args.split = nullptr;
+  args.codes = DirCodes{};
   return args;
 }
 
@@ -1402,15 +1513,77 @@ tc_status support_impl(int64_t n, const OffT* row_ptr, const int32_t* col, uint3
   return check_hip(hipGetLastError(), "tc_edge_support launch");
 }
 
+// ---- directed queries ----------------------------------------------------------
+
+// The table of a directed query with pair codes q = (p01, p02, p12): for every
+// combination of a triangle's direction codes, the one-to-one maps of the query
+// nodes onto (u, v, w) = (0, 1, 2) that carry each query arc onto an arc (or,
+// induced, whose arcs agree in both directions), divided by the query's
+// automorphisms (the maps onto one triangle fall into classes of that size).
+DirCodes directed_codes(const int32_t q[3], bool induced) {
+  // arc i -> j under the pair codes c (c[0]: 0-1, c[1]: 0-2, c[2]: 1-2; bit 0:
+  // lower -> higher, bit 1: higher -> lower)
+  auto arc = [](const int32_t c[3], int i, int j) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const int32_t code = c[lo == 0 ? hi - 1 : 2];
+    return ((code >> (i < j ? 0 : 1)) & 1) != 0;
+  };
+  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  int aut = 0;
+  for (const auto& f : perm) {
+    bool keeps = true;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        if (i != j && arc(q, i, j) != arc(q, f[i], f[j])) keeps = false;
+    aut += keeps;
+  }
+  DirCodes t{};
+  for (int c = 0; c < 64; ++c) {
+    const int32_t g[3] = {c >> 4, (c >> 2) & 3, c & 3};
+    int maps = 0;
+    for (const auto& f : perm) {
+      bool ok = true;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          if (i == j) continue;
+          const bool qa = arc(q, i, j), ga = arc(g, f[i], f[j]);
+          if (induced ? qa != ga : (qa && !ga)) ok = false;
+        }
+      maps += ok;
+    }
+    t.v[c] = (uint8_t)(maps / aut);
+  }
+  return t;
+}
+
+// One count launch of the directed kind: every wedge u -> v -> w closed by
+// (u, w) adds the table entry of its three direction codes.
+template <typename OffT>
+tc_status directed_impl(int64_t n, const OffT* row_ptr, const int32_t* col, const uint8_t* dir,
+                        const DirCodes& codes, uint64_t* total, const Tune& tune,
+                        const CountLayout& L, hipStream_t s) {
+  init_state_kernel<<<1, 256, 0, s>>>(L.st, L.split, total);
+  if (n > 0) {
+    launch_bins<OffT>(n, row_ptr, L.st, L.list, tune.small_max, s);
+    CountArgs args = base_args(tune);
+    args.codes = codes;
+    args.list.dir = dir;
+    launch_count<kKindDirected, OffT>(n, row_ptr, col, L, total, nullptr, args, tune, s);
+  }
+  return check_hip(hipGetLastError(), "tc_count_directed launch");
+}
+
 // ---- diamonds: two triangles sharing an edge ---------------------------------
 
 __global__ void diamond_init_kernel(uint64_t* total) { *total = 0; }
 
 // Sum over the edges of C(s, 2), s = the edge's support (m from m_out; nothing
-// when it reports an error).
-__global__ void diamond_reduce_kernel(const uint32_t* __restrict__ sup,
-                                      const int64_t* __restrict__ m_out,
-                                      uint64_t* __restrict__ total) {
+// when it reports an error).  A few workgroups per CU, one atomic each: one per
+// wave over thousands of workgroups queued on the total's cache line.
+__global__ __launch_bounds__(256) void diamond_reduce_kernel(const uint32_t* __restrict__ sup,
+                                                             const int64_t* __restrict__ m_out,
+                                                             uint64_t* __restrict__ total) {
+  __shared__ uint64_t part[256 / kWave];
   const int64_t m = *m_out;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   uint64_t acc = 0;
@@ -1419,7 +1592,13 @@ __global__ void diamond_reduce_kernel(const uint32_t* __restrict__ sup,
     acc += c * (c - 1) / 2;  // 0 for c = 0 and c = 1
   }
   const uint64_t w = (uint64_t)wave_sum((int64_t)acc);
-  if (lane_id() == 0 && w) atomicAdd((unsigned long long*)total, (unsigned long long)w);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t b = 0;
+    for (int i = 0; i < 256 / kWave; ++i) b += part[i];
+    if (b) atomicAdd((unsigned long long*)total, (unsigned long long)b);
+  }
 }
 
 struct DiamondLayout {
@@ -1517,6 +1696,36 @@ extern "C" tc_status tc_count_batched(const tc_csr* dag, int64_t num_graphs, con
                                    ws_bytes, stream);
 }
 
+extern "C" tc_status tc_count_directed(const tc_csr* dag, const uint8_t* dir, int32_t p01,
+                                       int32_t p02, int32_t p12, int32_t induced,
+                                       uint64_t* total, const tc_tune* tune, void* ws,
+                                       size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  tc_status st = check_dag(dag);
+  if (st != TC_OK) return st;
+  Tune t;
+  if ((st = read_tune(tune, &t)) != TC_OK) return st;
+  const int32_t q[3] = {p01, p02, p12};
+  for (int32_t c : q)
+    if (c < 1 || c > 3)
+      return fail(TC_ERR_INVALID_ARG, "pattern codes must be 1, 2 or 3 (every pair joined), got %d",
+                  c);
+  if (induced != 0 && induced != 1) return fail(TC_ERR_INVALID_ARG, "induced must be 0 or 1");
+  if (workspace_query(ws, ws_bytes, carve_count(nullptr, dag->n, false).bytes, &st)) return st;
+  if (!dag->row_ptr || !total || (dag->n > 0 && !dir))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const CountLayout L = carve_count(ws, dag->n, false);
+  const DirCodes codes = directed_codes(q, induced != 0);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dag->offset_bytes == 4)
+    st = directed_impl<int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col, dir,
+                                codes, total, t, L, s);
+  else
+    st = directed_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, dir,
+                                codes, total, t, L, s);
+  return st == TC_OK ? ok() : st;
+}
+
 extern "C" tc_status tc_count_diamonds(const tc_csr* dag, int64_t edge_capacity, uint64_t* total,
                                        int64_t* m_out, const tc_tune* tune, void* ws,
                                        size_t* ws_bytes, void* stream) {
@@ -1541,7 +1750,8 @@ extern "C" tc_status tc_count_diamonds(const tc_csr* dag, int64_t edge_capacity,
     st = support_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, L.sup,
                                edge_capacity, m_out, nullptr, t, L.c, s);
   if (st != TC_OK) return st;
-  diamond_reduce_kernel<<<grid_for(edge_capacity, 256, 8192), 256, 0, s>>>(L.sup, m_out, total);
+  diamond_reduce_kernel<<<grid_for(edge_capacity, 256, 4 * device_cu_count()), 256, 0, s>>>(
+      L.sup, m_out, total);
   return check_hip(hipGetLastError(), "tc_count_diamonds launch") == TC_OK ? ok() : TC_ERR_HIP;
 }
 

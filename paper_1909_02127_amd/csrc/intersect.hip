@@ -20,11 +20,6 @@
 //
 // Per-edge support adds one to (u, v), to (u, w) at A's position and to (v, w)
 // at B's position for every match.
-//
-// Directed queries (tc_count_directed) use the same merge: a match knows the
-// positions of its three edges, so it reads their arc directions and adds the
-// number of matches of the directed query on that triangle, from a 64-entry
-// table indexed by the three direction codes.
 #include "tc_device.h"
 #include "tc_host.h"
 #include "tc_scan.h"
@@ -38,18 +33,6 @@ constexpr int kBlock = 256;
 constexpr int kSteps = 16;                        // merge steps per lane and span chunk
 constexpr int64_t kSpan = (int64_t)kWave * kSteps;  // merge steps per wave and span
 constexpr int32_t kPastEnd = INT32_MAX;            // head of an exhausted list (ids < 2^31 - 1)
-
-// What a match adds: one to the total; also one to each of its three edges; or
-// the directed query's matches on its triangle.
-constexpr int kMergeCount = 0;
-constexpr int kMergeSupport = 1;
-constexpr int kMergeDirected = 2;
-
-// Matches of a directed query on one triangle (u, v, w) of the DAG, indexed by
-// the direction codes of (u, v), (u, w) and (v, w) as 16 c_uv + 4 c_uw + c_vw.
-struct DirTable {
-  uint8_t v[64];
-};
 
 // Source of every edge and the length of its stretch; stretches past m are 0.
 // One wave per source (rows are walked 64 entries at a time).
@@ -134,25 +117,16 @@ __device__ __forceinline__ int32_t list_at(const int32_t* __restrict__ col, uint
   return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(col) + (uint64_t)i * 4u);
 }
 
-template <int Mode, bool Narrow, typename OffT>
+template <bool Support, bool Narrow, typename OffT>
 __global__ __launch_bounds__(kBlock, 4) void merge_kernel(int64_t cap, const OffT* __restrict__ rp,
                                                      const int32_t* __restrict__ col,
                                                      const int32_t* __restrict__ src_of,
                                                      const int64_t* __restrict__ P,
                                                      const int64_t* __restrict__ m_out,
                                                      uint64_t* __restrict__ total,
-                                                     uint32_t* __restrict__ sup,
-                                                     const uint8_t* __restrict__ dir,
-                                                     DirTable table) {
-  constexpr bool Support = Mode == kMergeSupport;
-  constexpr bool Directed = Mode == kMergeDirected;
+                                                     uint32_t* __restrict__ sup) {
   __shared__ int32_t stage_all[(kBlock / kWave) * 2 * (kSteps + 1) * kWave];
-  __shared__ uint32_t tab[Directed ? 64 : 1];
   if (*m_out < 0) return;
-  if (Directed) {
-    if (threadIdx.x < 64) tab[threadIdx.x] = table.v[threadIdx.x];
-    __syncthreads();
-  }
   const int64_t S = P[cap];
   const int lane = lane_id();
   // this lane's staging slots: slot t of A at sa[t * kWave], of B at sb[t * kWave]
@@ -231,16 +205,10 @@ __global__ __launch_bounds__(kBlock, 4) void merge_kernel(int64_t cap, const Off
       int32_t ia = 0, ib = 0;
       int32_t av = sa[0], bv = sb[0];
       uint32_t cuv = 0;
-      const uint32_t code_uv = Directed ? 16u * dir[e] : 0u;
       for (int s = 0; s < q; ++s) {
         const bool take_a = av <= bv;
         if (take_a && av == bv) {
-          if (Directed) {
-            // the triangle's arcs: (u, w) at A's position, (v, w) at B's
-            cuv += tab[code_uv + 4u * dir[ab + i + ia] + dir[bb + j + ib]];
-          } else {
-            ++cuv;
-          }
+          ++cuv;
           if (Support) {
             atomicAdd(&sup[ab + i + ia], 1u);  // the edge (u, w)
             atomicAdd(&sup[bb + j + ib], 1u);  // the edge (v, w)
@@ -285,8 +253,7 @@ IntersectLayout carve_intersect(void* ws, int64_t cap) {
 
 template <typename OffT>
 tc_status intersect_impl(int64_t n, const OffT* rp, const int32_t* col, int64_t cap,
-                         uint64_t* total, uint32_t* sup, const uint8_t* dir,
-                         const DirTable* table, int64_t* m_out, const IntersectLayout& L,
+                         uint64_t* total, uint32_t* sup, int64_t* m_out, const IntersectLayout& L,
                          hipStream_t s) {
   intersect_init_kernel<<<1, 1, 0, s>>>(total);
   edge_work_kernel<OffT><<<grid_for(std::max<int64_t>(n, cap / 64), 256 / kWave, 8192), 256, 0, s>>>(
@@ -298,203 +265,23 @@ tc_status intersect_impl(int64_t n, const OffT* rp, const int32_t* col, int64_t 
   // 4 workgroups per CU (the launch bound), the most the LDS staging allows
   const int grid = 4 * device_cu_count();
   const bool narrow = cap < (int64_t(1) << 30);
-  const DirTable none{};
-  if (table && narrow)
-    merge_kernel<kMergeDirected, true, OffT><<<grid, kBlock, 0, s>>>(
-        cap, rp, col, L.src_of, L.P, m_out, total, nullptr, dir, *table);
-  else if (table)
-    merge_kernel<kMergeDirected, false, OffT><<<grid, kBlock, 0, s>>>(
-        cap, rp, col, L.src_of, L.P, m_out, total, nullptr, dir, *table);
-  else if (sup && narrow)
-    merge_kernel<kMergeSupport, true, OffT><<<grid, kBlock, 0, s>>>(
-        cap, rp, col, L.src_of, L.P, m_out, total, sup, nullptr, none);
+  if (sup && narrow)
+    merge_kernel<true, true, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                           total, sup);
   else if (sup)
-    merge_kernel<kMergeSupport, false, OffT><<<grid, kBlock, 0, s>>>(
-        cap, rp, col, L.src_of, L.P, m_out, total, sup, nullptr, none);
+    merge_kernel<true, false, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                            total, sup);
   else if (narrow)
-    merge_kernel<kMergeCount, true, OffT><<<grid, kBlock, 0, s>>>(
-        cap, rp, col, L.src_of, L.P, m_out, total, nullptr, nullptr, none);
+    merge_kernel<false, true, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                            total, nullptr);
   else
-    merge_kernel<kMergeCount, false, OffT><<<grid, kBlock, 0, s>>>(
-        cap, rp, col, L.src_of, L.P, m_out, total, nullptr, nullptr, none);
+    merge_kernel<false, false, OffT><<<grid, kBlock, 0, s>>>(cap, rp, col, L.src_of, L.P, m_out,
+                                                             total, nullptr);
   return check_hip(hipGetLastError(), "tc_segmented_intersect launch");
-}
-
-// ---- arc directions ------------------------------------------------------------
-
-// m_out = m, or -TC_ERR_CAPACITY when m > cap; the direction words of [0, m)
-// cleared.
-template <typename OffT>
-__global__ void dir_clear_kernel(const OffT* __restrict__ rp, int64_t n, int64_t cap,
-                                 uint32_t* __restrict__ words, int64_t* __restrict__ m_out) {
-  const int64_t m = (int64_t)rp[n];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *m_out = m > cap ? -(int64_t)TC_ERR_CAPACITY : m;
-  if (m > cap) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (m + 3) / 4; i += stride)
-    words[i] = 0u;
-}
-
-// Position of x in the ascending row col[beg, end), or -1.
-__device__ __forceinline__ int64_t row_find(const int32_t* __restrict__ col, int64_t beg,
-                                            int64_t end, int32_t x) {
-  int64_t lo = beg, hi = end;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (col[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo < end && col[lo] == x ? lo : -1;
-}
-
-// Every arc s -> d (s != d) sets one bit of the DAG edge between s and d: bit 0
-// when the edge is stored in s's row (the arc leaves the row's vertex), bit 1
-// when it is stored in d's row.  Bytes are set through their 32-bit words.
-template <typename OffT>
-__global__ __launch_bounds__(256) void dir_arcs_kernel(const OffT* __restrict__ rp, int64_t n,
-                                                       const int32_t* __restrict__ col,
-                                                       int64_t num_pairs,
-                                                       const int32_t* __restrict__ src,
-                                                       const int32_t* __restrict__ dst,
-                                                       uint32_t* __restrict__ words,
-                                                       int64_t* __restrict__ m_out) {
-  if (*m_out < 0) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < num_pairs; i += stride) {
-    const int32_t a = src[i], b = dst[i];
-    if (a < 0 || a >= n || b < 0 || b >= n) {
-      *m_out = -(int64_t)TC_ERR_ID_OUT_OF_RANGE;
-      continue;
-    }
-    if (a == b) continue;
-    int64_t pos = row_find(col, (int64_t)rp[a], (int64_t)rp[a + 1], b);
-    uint32_t bit = 1u;
-    if (pos < 0) {
-      pos = row_find(col, (int64_t)rp[b], (int64_t)rp[b + 1], a);
-      bit = 2u;
-    }
-    if (pos < 0) {
-      *m_out = -(int64_t)TC_ERR_INVALID_ARG;  // not an edge of this DAG
-      continue;
-    }
-    atomicOr(&words[pos >> 2], bit << ((pos & 3) * 8));
-  }
-}
-
-// The table of a directed query with pair codes q = (p01, p02, p12): for every
-// combination of the data triangle's codes, the one-to-one maps of the query
-// nodes onto (u, v, w) = (0, 1, 2) that carry each query arc onto an arc (or,
-// induced, whose arcs agree both ways), divided by the query's automorphisms
-// (the maps onto one triangle fall into classes of that size).
-DirTable directed_table(const int32_t q[3], bool induced) {
-  // arc i -> j in codes c (c[0]: pair 0-1, c[1]: 0-2, c[2]: 1-2; bit 0: lower -> higher)
-  auto arc = [](const int32_t c[3], int i, int j) {
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    const int32_t code = c[lo == 0 ? hi - 1 : 2];
-    return ((code >> (i < j ? 0 : 1)) & 1) != 0;
-  };
-  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-  int aut = 0;
-  for (const auto& f : perm) {
-    bool keeps = true;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        if (i != j && arc(q, i, j) != arc(q, f[i], f[j])) keeps = false;
-    aut += keeps;
-  }
-  DirTable t{};
-  for (int c = 0; c < 64; ++c) {
-    const int32_t g[3] = {c >> 4, (c >> 2) & 3, c & 3};
-    int maps = 0;
-    for (const auto& f : perm) {
-      bool ok = true;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          if (i == j) continue;
-          const bool qa = arc(q, i, j), ga = arc(g, f[i], f[j]);
-          if (induced ? qa != ga : (qa && !ga)) ok = false;
-        }
-      maps += ok;
-    }
-    t.v[c] = (uint8_t)(maps / aut);
-  }
-  return t;
-}
-
-tc_status check_intersect_dag(const tc_csr* dag, int64_t edge_capacity) {
-  if (!dag) return fail(TC_ERR_INVALID_ARG, "dag is NULL");
-  if (dag->n < 0) return fail(TC_ERR_INVALID_ARG, "negative n");
-  if (dag->n > INT32_MAX)
-    return fail(TC_ERR_UNSUPPORTED, "n=%lld needs ids beyond int32", (long long)dag->n);
-  if (dag->offset_bytes != 4 && dag->offset_bytes != 8)
-    return fail(TC_ERR_INVALID_ARG, "offset_bytes must be 4 or 8, got %d", dag->offset_bytes);
-  if (edge_capacity < 0) return fail(TC_ERR_INVALID_ARG, "negative edge_capacity");
-  if (edge_capacity > ((int64_t)1 << 40))
-    return fail(TC_ERR_UNSUPPORTED, "edge_capacity=%lld is beyond 2^40", (long long)edge_capacity);
-  return TC_OK;
 }
 
 }  // namespace
 }  // namespace tc
-
-extern "C" tc_status tc_edge_directions(const tc_csr* dag, int64_t edge_capacity,
-                                        int64_t num_pairs, const int32_t* src,
-                                        const int32_t* dst, uint8_t* dir, int64_t* m_out,
-                                        void* stream) {
-  using namespace tc;
-  tc_status st = check_intersect_dag(dag, edge_capacity);
-  if (st != TC_OK) return st;
-  if (num_pairs < 0) return fail(TC_ERR_INVALID_ARG, "negative num_pairs");
-  if (!dag->row_ptr || !m_out || (edge_capacity > 0 && !dir) || (num_pairs > 0 && (!src || !dst)))
-    return fail(TC_ERR_INVALID_ARG, "null device pointer");
-  if (reinterpret_cast<uintptr_t>(dir) % 4 != 0)
-    return fail(TC_ERR_INVALID_ARG, "dir must be 4-byte aligned");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  uint32_t* words = reinterpret_cast<uint32_t*>(dir);
-  const int cg = grid_for((edge_capacity + 3) / 4, 256, 8192);
-  const int ag = grid_for(num_pairs, 256, 16384);
-  if (dag->offset_bytes == 4) {
-    const int32_t* rp = static_cast<const int32_t*>(dag->row_ptr);
-    dir_clear_kernel<int32_t><<<cg, 256, 0, s>>>(rp, dag->n, edge_capacity, words, m_out);
-    if (num_pairs > 0)
-      dir_arcs_kernel<int32_t><<<ag, 256, 0, s>>>(rp, dag->n, dag->col, num_pairs, src, dst, words,
-                                                  m_out);
-  } else {
-    const int64_t* rp = static_cast<const int64_t*>(dag->row_ptr);
-    dir_clear_kernel<int64_t><<<cg, 256, 0, s>>>(rp, dag->n, edge_capacity, words, m_out);
-    if (num_pairs > 0)
-      dir_arcs_kernel<int64_t><<<ag, 256, 0, s>>>(rp, dag->n, dag->col, num_pairs, src, dst, words,
-                                                  m_out);
-  }
-  return check_hip(hipGetLastError(), "tc_edge_directions launch") == TC_OK ? ok() : TC_ERR_HIP;
-}
-
-extern "C" tc_status tc_count_directed(const tc_csr* dag, int64_t edge_capacity,
-                                       const uint8_t* dir, int32_t p01, int32_t p02, int32_t p12,
-                                       int32_t induced, uint64_t* total, int64_t* m_out, void* ws,
-                                       size_t* ws_bytes, void* stream) {
-  using namespace tc;
-  tc_status st = check_intersect_dag(dag, edge_capacity);
-  if (st != TC_OK) return st;
-  const int32_t q[3] = {p01, p02, p12};
-  for (int32_t c : q)
-    if (c < 1 || c > 3)
-      return fail(TC_ERR_INVALID_ARG, "pattern codes must be 1, 2 or 3 (every pair joined), got %d", c);
-  if (induced != 0 && induced != 1) return fail(TC_ERR_INVALID_ARG, "induced must be 0 or 1");
-  if (workspace_query(ws, ws_bytes, carve_intersect(nullptr, edge_capacity).bytes, &st)) return st;
-  if (!dag->row_ptr || !total || !m_out || (edge_capacity > 0 && !dir))
-    return fail(TC_ERR_INVALID_ARG, "null device pointer");
-  const IntersectLayout L = carve_intersect(ws, edge_capacity);
-  const DirTable table = directed_table(q, induced != 0);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dag->offset_bytes == 4)
-    st = intersect_impl<int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col,
-                                 edge_capacity, total, nullptr, dir, &table, m_out, L, s);
-  else
-    st = intersect_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col,
-                                 edge_capacity, total, nullptr, dir, &table, m_out, L, s);
-  return st == TC_OK ? ok() : st;
-}
 
 extern "C" tc_status tc_segmented_intersect(const tc_csr* dag, int64_t edge_capacity,
                                             uint64_t* total, uint32_t* support, int64_t* m_out,
@@ -516,11 +303,9 @@ extern "C" tc_status tc_segmented_intersect(const tc_csr* dag, int64_t edge_capa
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (dag->offset_bytes == 4)
     st = intersect_impl<int32_t>(n, static_cast<const int32_t*>(dag->row_ptr), dag->col,
-                                 edge_capacity, total, support, nullptr, nullptr, m_out, L,
-                                 s);
+                                 edge_capacity, total, support, m_out, L, s);
   else
     st = intersect_impl<int64_t>(n, static_cast<const int64_t*>(dag->row_ptr), dag->col,
-                                 edge_capacity, total, support, nullptr, nullptr, m_out, L,
-                                 s);
+                                 edge_capacity, total, support, m_out, L, s);
   return st == TC_OK ? ok() : st;
 }

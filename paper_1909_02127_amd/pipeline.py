@@ -165,27 +165,23 @@ class Pipeline:
         _lib.tc_edge_directions(self.n, self.dag_ptr, self.dag_col, src, dst, self.direction,
                                 self.direction_m, stream=stream)
 
-    def directed(self, pattern, *, induced: bool = False, stream=None) -> None:
+    def directed(self, pattern, *, induced: bool = False, stream=None, tune=None) -> None:
         """Enqueue tc_count_directed on the current DAG and the directions recorded by
         edge_directions(): result in self.directed_total (read with directed_count())."""
+        tune = self.tune if tune is None else tune
         if self.direction is None:
             raise RuntimeError("edge_directions() must run first")
-        if self.ws_intersect is None:
-            self.ws_intersect = _bytes(
-                _lib.tc_segmented_intersect_workspace(self.n, self.dag_col.numel()), self.device)
         _lib.tc_count_directed(self.n, self.dag_ptr, self.dag_col, self.direction, pattern,
-                               self.directed_total, self.support_m, self.ws_intersect,
-                               induced=induced, stream=stream)
+                               self.directed_total, self.ws_count, induced=induced, tune=tune,
+                               stream=stream)
 
     def directed_count(self) -> int:
-        """Synchronise and read the result of directed() (and the status of the directions)."""
+        """Synchronise and read the result of directed() (raises when the directions reported
+        an error)."""
         torch.cuda.synchronize(self.device)
         dm = int(self.direction_m.item())
         if dm < 0:
             raise TcError(-dm, "reported by tc_edge_directions on the device")
-        m = int(self.support_m.item())
-        if m < 0:
-            raise TcError(-m, "reported by tc_count_directed on the device")
         return int(self.directed_total.item()) & ((1 << 64) - 1)
 
     def diamond_count(self) -> int:

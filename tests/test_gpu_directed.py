@@ -188,13 +188,19 @@ def test_directed_errors_and_degenerate(tc):
     # codes outside 1..3 are refused on the host
     with pytest.raises(_lib.TcError):
         p.directed((0, 1, 1))
-    # a column capacity below m
-    ws = torch.empty(_lib.tc_count_directed_workspace(n, 2), dtype=torch.uint8, device="cuda")
+    # a workspace below the query's size is refused on the host
+    ws = torch.empty(_lib.tc_count_directed_workspace(n), dtype=torch.uint8, device="cuda")
     total = torch.full((1,), 5, dtype=torch.int64, device="cuda")
-    m_out = torch.zeros(1, dtype=torch.int64, device="cuda")
-    _lib.tc_count_directed(n, p.dag_ptr, p.dag_col[:2], p.direction, CYCLE, total, m_out, ws)
+    with pytest.raises(_lib.TcError):
+        _lib.tc_count_directed(n, p.dag_ptr, p.dag_col, p.direction, CYCLE, total, ws[:64])
+    _lib.tc_count_directed(n, p.dag_ptr, p.dag_col, p.direction, CYCLE, total, ws)
     torch.cuda.synchronize()
-    assert int(m_out.item()) == -_lib.TC_ERR_CAPACITY and int(total.item()) == 0
+    assert int(total.item()) == 1
+    # a column capacity below m when recording the directions
+    m_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _lib.tc_edge_directions(n, p.dag_ptr, p.dag_col[:2], _dev(s), _dev(d), p.direction, m_out)
+    torch.cuda.synchronize()
+    assert int(m_out.item()) == -_lib.TC_ERR_CAPACITY
     for n, s, d in [(1, [], []), (3, [0, 0], [0, 0]), (4, [0, 1], [1, 2]), (3, [0, 1, 0], [1, 2, 2])]:
         _check(tc, n, np.array(s, np.int32), np.array(d, np.int32), [CYCLE, FFL, ALL])
 
@@ -236,3 +242,32 @@ def test_directed_rmat_scale20_full(tc):
     assert p.directed_count() == T
     p.directed(CYCLE, induced=True)
     assert p.directed_count() == 0
+
+
+def test_directed_probe_modes_and_splits(tc):
+    """Every probe structure of the count kernel (cuckoo, stash, sorted, the in-memory
+    search of very long rows), both source paths and split sources give the oracle's
+    counts: the direction code of (u, w) follows its key wherever the key sits."""
+    from paper_1909_02127_amd import _lib
+    s, d, n = graphgen.rmat(11, 16, 5)
+    s, d = s.numpy(), d.numpy()
+    # a hub adjacent to everything: in id order its out-list is searched in memory
+    rng = np.random.default_rng(8)
+    hn = 4001
+    hs = np.concatenate([np.zeros(4000, np.int64), rng.integers(1, hn, 30000)])
+    hd = np.concatenate([np.arange(1, hn), rng.integers(1, hn, 30000)])
+    flip = rng.random(hs.size) < 0.5
+    hs, hd = np.where(flip, hd, hs).astype(np.int32), np.where(flip, hs, hd).astype(np.int32)
+    tunes = [_lib.make_tune(probe=_lib.TC_PROBE_SORTED), _lib.make_tune(max_kicks=1),
+             _lib.make_tune(small_max=1), _lib.make_tune(split_log2=8),
+             _lib.make_tune(small_max=96, split_log2=-1)]
+    for n_, s_, d_ in ((n, s, d), (hn, hs, hd)):
+        for order in (0, 1):
+            p = _pipe(tc, n_, s_, d_, order=order)
+            rp, col = oracle.clean(n_, s_, d_)
+            dp, dc = oracle.orient(rp, col, order)
+            want = {q: oracle.count_directed(dp, dc, s_, d_, q) for q in (CYCLE, FFL)}
+            for i, tune in enumerate(tunes):
+                for q in (CYCLE, FFL):
+                    p.directed(q, tune=tune)
+                    assert p.directed_count() == want[q], (n_, order, i, q)
