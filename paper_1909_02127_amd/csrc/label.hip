@@ -45,10 +45,60 @@ __device__ __forceinline__ bool pair_fits(const Query& q, int32_t x, int32_t y) 
   return (lo == q.q0 && (hi == q.q1 || hi == q.q2)) || (lo == q.q1 && hi == q.q2);
 }
 
-// Rows handled together by one wave: kGroup lanes per row, so that the short
-// out-lists of a sparse graph do not leave most of the wave idle.
-constexpr int kGroup = 16;
-constexpr int kRowsPerWave = kWave / kGroup;
+// One wave takes kRows consecutive rows at a time and walks their edges as one
+// contiguous range of the column array, 64 edges per step, the loads of
+// kSteps steps in flight together.  A lane finds its edge's row as the
+// short-list walk of the count does: every non-empty row marks its first
+// position of the step in LDS with (row << 6 | position), and a wave max-scan
+// hands each lane the last row that starts at or before it (and where that
+// row's part of the step begins).  The last lane of a row's part adds the
+// row's kept edges of the step from the ballot to the row's LDS counter.
+constexpr int kRows = 32;
+constexpr int kSteps = 4;
+static_assert(kRows < kWave, "row bounds are held one per lane");
+constexpr int32_t kNoMark = -1;
+
+// Lanes [lo, hi) of a 64-lane mask (0 <= lo <= hi <= 64).
+__device__ __forceinline__ uint64_t lane_range(int lo, int hi) {
+  const uint64_t upto_hi = hi >= kWave ? ~uint64_t(0) : (uint64_t(1) << hi) - 1;
+  const uint64_t upto_lo = (uint64_t(1) << lo) - 1;
+  return hi > lo ? upto_hi & ~upto_lo : 0;
+}
+
+// Per-wave LDS of the walk.
+struct WalkLds {
+  int32_t mark[kWave];   // kNoMark between steps
+  int32_t count[kRows];  // per row: kept edges (pass 1), edges written (pass 2)
+  int64_t at[kRows];     // pass 2: the rows' new offsets
+};
+
+// Rows and part starts of the steps s0 = e0 + k 64 (k < kSteps) of the edge
+// range [e_beg, e_end) whose rows start at bnd (lane r < kRows: row r's first
+// edge; nonempty: row r has an edge).  carry: the packed row of the last lane
+// of the previous step (its part continues at position 0), updated.
+__device__ __forceinline__ void walk_rows(WalkLds& L, int64_t bnd, bool nonempty, int64_t e0,
+                                          int64_t e_end, int32_t& carry, int32_t (&row)[kSteps],
+                                          int32_t (&seg0)[kSteps]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < kSteps; ++k) {
+    const int64_t s0 = e0 + k * kWave;
+    row[k] = 0;
+    seg0[k] = 0;
+    if (s0 >= e_end) continue;  // uniform
+    const int64_t rel = bnd - s0;
+    const bool marks = nonempty && rel >= 0 && rel < kWave;
+    if (marks) L.mark[rel] = (lane << 6) | (int32_t)rel;
+    wave_sync();
+    int32_t pk = wave_inclusive_max32(L.mark[lane]);
+    pk = pk > carry ? pk : carry;
+    wave_sync();
+    if (marks) L.mark[rel] = kNoMark;
+    carry = read_lane(pk, kWave - 1) & ~63;  // the same row, from position 0 of the next step
+    row[k] = pk >> 6;
+    seg0[k] = pk & 63;
+  }
+}
 
 // Reports whether the DAG fits the caller's edge capacity; every later kernel
 // reads this status and does nothing (or writes an empty DAG) when it fails.
@@ -61,47 +111,66 @@ __global__ void label_status_kernel(const OffT* __restrict__ rp, int64_t n, int6
   totals[1] = 0;
 }
 
-// Pass 1: kept out-degree of every source, and the keep flag of each of its
-// edges.  A source whose label is not in the query keeps nothing and its row is
-// not read.
+// Pass 1: kept out-degree of every source, and the keep flag of each edge of
+// the sources whose label is in the query (the rows of the others are not
+// read and keep nothing).
 template <typename OffT>
 __global__ __launch_bounds__(256) void label_degree_kernel(
     int64_t n, const OffT* __restrict__ rp, const int32_t* __restrict__ col,
     const int32_t* __restrict__ labels, Query q, const int64_t* __restrict__ status,
     uint8_t* __restrict__ keep, int64_t* __restrict__ deg) {
+  __shared__ WalkLds lds_all[256 / kWave];
+  WalkLds& L = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
-  const int g = lane / kGroup, gl = lane % kGroup;
+  L.mark[lane] = kNoMark;
+  wave_sync();
   const bool bad = *status < 0;
-  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kRowsPerWave;
-       r0 < n; r0 += nwaves * kRowsPerWave) {
-    const int64_t u = r0 + g;
-    int64_t beg = 0, d = 0;
-    int32_t lu = 0;
-    if (u < n && !bad) {
-      lu = labels[u];
-      if (label_in(q, lu)) {
-        beg = (int64_t)rp[u];
-        d = (int64_t)rp[u + 1] - beg;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kWave) * kRows;
+  for (int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kRows;
+       r0 < n; r0 += stride) {
+    // lanes 0..kRows: the rows' bounds (clamped at n); lanes < kRows: the rows' labels
+    const int64_t x = r0 + lane < n ? r0 + lane : n;
+    const int64_t bnd = lane <= kRows ? (int64_t)rp[x] : 0;
+    const bool row_ok = lane < kRows && r0 + lane < n;
+    const int32_t lab = row_ok ? labels[r0 + lane] : 0;
+    const uint64_t cand = ballot(row_ok && !bad && label_in(q, lab));
+    // cross-lane reads are made by every lane, outside any condition (a lane
+    // reading from one that skipped the instruction would get no value)
+    const int64_t bnd_next = __shfl_down(bnd, 1, kWave);
+    const bool nonempty = row_ok && bnd_next > bnd;
+    const int64_t e_beg = read_lane64(bnd, 0), e_end = read_lane64(bnd, kRows);
+    if (lane < kRows) L.count[lane] = 0;
+    wave_sync();
+    int32_t carry = kNoMark;
+    for (int64_t e0 = e_beg; cand && e0 < e_end; e0 += kSteps * kWave) {
+      int32_t row[kSteps], seg0[kSteps], v[kSteps], lv[kSteps];
+      bool act[kSteps];
+      walk_rows(L, bnd, nonempty, e0, e_end, carry, row, seg0);
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) {
+        const int64_t e = e0 + k * kWave + lane;
+        act[k] = e < e_end && ((cand >> row[k]) & 1);
+        v[k] = act[k] ? col[e] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) lv[k] = act[k] ? labels[v[k]] : 0;
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) {
+        const int64_t e = e0 + k * kWave + lane;
+        const int32_t lu = __shfl(lab, row[k], kWave);
+        const bool kp = act[k] && pair_fits(q, lu, lv[k]);
+        if (act[k]) keep[e] = (uint8_t)kp;
+        const uint64_t b = ballot(kp);
+        // the last lane of each row's part of the step adds the part's kept edges
+        const bool in = e < e_end;
+        const int32_t row_next = __shfl_down(row[k], 1, kWave);
+        const bool next_same = lane + 1 < kWave && e + 1 < e_end && row_next == row[k];
+        if (in && !next_same) L.count[row[k]] += (int32_t)popc(b & lane_range(seg0[k], lane + 1));
+        wave_sync();
       }
     }
-    int64_t dmax = d;
-    for (int off = kGroup; off < kWave; off <<= 1) {
-      const int64_t o = __shfl_xor(dmax, off, kWave);
-      dmax = o > dmax ? o : dmax;
-    }
-    int64_t kept = 0;
-    for (int64_t i0 = 0; i0 < dmax; i0 += kGroup) {
-      const int64_t i = i0 + gl;
-      bool k = false;
-      if (i < d) {
-        k = pair_fits(q, lu, labels[col[beg + i]]);
-        keep[beg + i] = (uint8_t)k;
-      }
-      const uint64_t b = ballot(k);
-      kept += popc((b >> (g * kGroup)) & 0xFFFFull);
-    }
-    if (u < n && gl == 0) deg[u] = kept;
+    if (row_ok) deg[r0 + lane] = L.count[lane];
+    wave_sync();
   }
 }
 
@@ -115,45 +184,71 @@ struct OffStore {
 };
 
 // Pass 2: the kept edges of every row, in their order, at the row's new
-// offset; the new row offsets.  When the capacity check failed, or the kept
-// edges exceed the capacity, every row is written empty (the count then sees
-// a graph with no edges).
+// offset; the new row offsets.  Only rows that keep something are read (their
+// keep flags were written by pass 1).  When the capacity check failed, or the
+// kept edges exceed the capacity, every row is written empty (the count then
+// sees a graph with no edges).
 template <typename OffT>
 __global__ __launch_bounds__(256) void label_compact_kernel(
     int64_t n, const OffT* __restrict__ rp, const int32_t* __restrict__ col,
     const uint8_t* __restrict__ keep, const int64_t* __restrict__ off,
     const int64_t* __restrict__ partial, int64_t tiles, int64_t cap,
     const int64_t* __restrict__ status, OffT* __restrict__ frp, int32_t* __restrict__ fcol) {
+  __shared__ WalkLds lds_all[256 / kWave];
+  WalkLds& L = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
-  const int g = lane / kGroup, gl = lane % kGroup;
+  L.mark[lane] = kNoMark;
+  wave_sync();
   const int64_t kept_total = tiles > 0 ? partial[tiles] : 0;
   const bool empty = *status < 0 || kept_total > cap;
-  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int64_t first = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kRowsPerWave;
-  if (first == 0 && lane == 0) frp[n] = (OffT)(empty ? 0 : kept_total);
-  for (int64_t r0 = first; r0 < n; r0 += nwaves * kRowsPerWave) {
-    const int64_t u = r0 + g;
-    int64_t beg = 0, d = 0, at = 0;
-    if (u < n) {
-      at = empty ? 0 : off[u];
-      if (gl == 0) frp[u] = (OffT)at;
-      const int64_t next = empty ? 0 : (u + 1 < n ? off[u + 1] : kept_total);
-      if (next > at) {  // the row keeps something: read it
-        beg = (int64_t)rp[u];
-        d = (int64_t)rp[u + 1] - beg;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kWave) * kRows;
+  int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kRows;
+  if (r0 == 0 && lane == 0) frp[n] = (OffT)(empty ? 0 : kept_total);
+  for (; r0 < n; r0 += stride) {
+    const int64_t x = r0 + lane < n ? r0 + lane : n;
+    const int64_t bnd = lane <= kRows ? (int64_t)rp[x] : 0;
+    const bool row_ok = lane < kRows && r0 + lane < n;
+    // lanes 0..kRows: the rows' new offsets (the one past the last row: the next row's)
+    const int64_t at = lane <= kRows && !empty ? (x < n ? off[x] : kept_total) : 0;
+    if (row_ok) frp[r0 + lane] = (OffT)at;
+    const int64_t at_next = __shfl_down(at, 1, kWave);
+    const uint64_t rows = ballot(row_ok && at_next > at);  // rows that keep something
+    // cross-lane reads are made by every lane, outside any condition (a lane
+    // reading from one that skipped the instruction would get no value)
+    const int64_t bnd_next = __shfl_down(bnd, 1, kWave);
+    const bool nonempty = row_ok && bnd_next > bnd;
+    const int64_t e_beg = read_lane64(bnd, 0), e_end = read_lane64(bnd, kRows);
+    if (lane < kRows) {
+      L.count[lane] = 0;
+      L.at[lane] = at;
+    }
+    wave_sync();
+    int32_t carry = kNoMark;
+    for (int64_t e0 = e_beg; rows && e0 < e_end; e0 += kSteps * kWave) {
+      int32_t row[kSteps], seg0[kSteps], v[kSteps];
+      bool kp[kSteps];
+      walk_rows(L, bnd, nonempty, e0, e_end, carry, row, seg0);
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) {
+        const int64_t e = e0 + k * kWave + lane;
+        kp[k] = e < e_end && ((rows >> row[k]) & 1) && keep[e];
       }
-    }
-    int64_t dmax = d;
-    for (int o = kGroup; o < kWave; o <<= 1) {
-      const int64_t x = __shfl_xor(dmax, o, kWave);
-      dmax = x > dmax ? x : dmax;
-    }
-    for (int64_t i0 = 0; i0 < dmax; i0 += kGroup) {
-      const int64_t i = i0 + gl;
-      const bool k = i < d && keep[beg + i];
-      const uint64_t b = (ballot(k) >> (g * kGroup)) & 0xFFFFull;
-      if (k) fcol[at + popc(b & ((1ull << gl) - 1))] = col[beg + i];
-      at += popc(b);
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) v[k] = kp[k] ? col[e0 + k * kWave + lane] : 0;
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) {
+        const int64_t e = e0 + k * kWave + lane;
+        const uint64_t b = ballot(kp[k]);
+        // rank in the row: the row's kept edges of earlier steps, then this part's
+        if (kp[k])
+          fcol[L.at[row[k]] + L.count[row[k]] + popc(b & lane_range(seg0[k], lane))] = v[k];
+        const bool in = e < e_end;
+        const int32_t row_next = __shfl_down(row[k], 1, kWave);
+        const bool next_same = lane + 1 < kWave && e + 1 < e_end && row_next == row[k];
+        wave_sync();
+        if (in && !next_same) L.count[row[k]] += (int32_t)popc(b & lane_range(seg0[k], lane + 1));
+        wave_sync();
+      }
     }
   }
 }
@@ -214,8 +309,10 @@ tc_status filter_and_count(const tc_csr* dag, const int32_t* labels, const Query
   const int64_t n = dag->n;
   const OffT* rp = static_cast<const OffT*>(dag->row_ptr);
   OffT* frp = static_cast<OffT*>(L.frp);
+  // persistent: every wave resident at once (8 workgroups of 4 waves per CU), each
+  // taking many row groups
   const int waves_per_block = 256 / kWave;
-  const int grid = grid_for((n + kRowsPerWave - 1) / kRowsPerWave, waves_per_block, 1 << 16);
+  const int grid = grid_for((n + kRows - 1) / kRows, waves_per_block, 8 * device_cu_count());
   if (n > 0)
     label_degree_kernel<OffT><<<grid, 256, 0, s>>>(n, rp, dag->col, labels, q, L.status, L.keep,
                                                    L.deg);
