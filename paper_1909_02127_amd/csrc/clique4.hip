@@ -7,12 +7,14 @@
 // d+(v) >= 2, a third node d+(w) >= 1.
 //
 // A workgroup takes runs of kGrab sources from a global cursor, one source at a
-// time; N+(u) (sorted) sits in LDS when it has at most kLdsKeys ids.  Its four
-// waves take the v round robin.  For each (u, v) a wave streams N+(v), finds
-// each w in N+(u) by binary search and keeps its position in a per-wave list
-// (S = the kept w, ascending); then it walks the N+(w) of 64 kept w at a time as
-// one concatenation (one round trip for their row bounds) and counts the x that
-// are in S, by binary search in S.  Longer sources keep N+(u) in memory: w and
+// time; N+(u) sits in LDS when it has at most kLdsKeys ids: in a cuckoo table
+// up to kHashKeys ids, else sorted.  Its four waves take the v round robin.  For
+// each (u, v) a wave streams N+(v), finds each w in N+(u) and keeps it in a
+// per-wave list (S = the kept w); then it walks the N+(w) of 64 kept w at a time
+// as one concatenation (one round trip for their row bounds) and counts the x
+// that are in S.  With the table, S is also a per-wave bit beside each slot, so
+// x is tested by its table probe and that bit; with the sorted copy, by binary
+// search in S.  Longer sources keep N+(u) in memory: w and
 // x are then tested by binary search in the sorted rows of u and v, and the
 // kept w go through a bounded list in chunks.
 #include "tc_device.h"
@@ -85,6 +87,17 @@ __device__ __forceinline__ bool in_kept(const int32_t* tkeys, const uint16_t* lp
   return lo < ns && tkeys[lpos[lo]] == x;
 }
 
+// Whether x is in the wave's S: x is a key of the table and its slot carries
+// the wave's bit.
+__device__ __forceinline__ bool in_wave_set(const int32_t* tkeys, const uint32_t* sbits, int side,
+                                            int shift, uint32_t my_bit, int32_t x) {
+  const uint32_t hp = hash_product(hash_input<true>(x));
+  const uint32_t sa = slot_a_of(hp, shift);
+  const uint32_t sb = (uint32_t)side + slot_b_of(hp, shift);
+  const int32_t s = tkeys[sa] == x ? (int32_t)sa : (tkeys[sb] == x ? (int32_t)sb : -1);
+  return s >= 0 && ((sbits[s >> 3] >> ((s & 7) * 4)) & my_bit) != 0;
+}
+
 template <typename OffT>
 __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col,
@@ -96,6 +109,9 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
   __shared__ int32_t list[kWavesPerBlock][kListCap];
   static_assert(kLdsKeys <= 65536 && kLdsKeys * 2 <= kListCap * 4, "kept positions fit the list");
   __shared__ int32_t segs[kWavesPerBlock][kWave];
+  // table path: bit `wave` of a slot's 4-bit field is set while the slot's key is
+  // in that wave's S (eight slots per 32-bit word, set and cleared atomically)
+  __shared__ uint32_t sbits[kLdsKeys / 8];
   __shared__ int32_t next_s;
   __shared__ int32_t kfail;
   const int lane = lane_id();
@@ -124,6 +140,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
         const int side = 1 << b, shift = 32 - b;
         if (hashed) {
           for (int i = threadIdx.x; i < 2 * side; i += kBlock) tkeys[i] = -1;
+          for (int i = threadIdx.x; i < (2 * side + 7) / 8; i += kBlock) sbits[i] = 0u;
           if (threadIdx.x == 0) kfail = 0;
           __syncthreads();
           for (int i = threadIdx.x; i < du; i += kBlock) {
@@ -144,6 +161,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
         if (in_lds && !hashed)
           for (int i = threadIdx.x; i < du; i += kBlock) tkeys[i] = urow[i];
         __syncthreads();
+        const uint32_t my_bit = 1u << wave;
         for (int32_t iv = wave; iv < du; iv += kWavesPerBlock) {
           const int32_t v = (in_lds && !hashed) ? tkeys[iv] : urow[iv];
           const int64_t vb = row_ptr[v];
@@ -158,19 +176,22 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             if (j < dv) {
               w = col[vb + j];
               if (hashed) {
+                // pos: w's slot in the table
                 const uint32_t hp = hash_product(hash_input<true>(w));
-                pos = (tkeys[slot_a_of(hp, shift)] == w ||
-                       tkeys[(uint32_t)side + slot_b_of(hp, shift)] == w) ? 0 : -1;
+                const uint32_t sa = slot_a_of(hp, shift);
+                const uint32_t sb = (uint32_t)side + slot_b_of(hp, shift);
+                pos = tkeys[sa] == w ? (int32_t)sa : (tkeys[sb] == w ? (int32_t)sb : -1);
+                if (pos >= 0) atomicOr(&sbits[pos >> 3], my_bit << ((pos & 7) * 4));
               } else {
                 pos = in_lds ? find_pos(tkeys, du, w) : find_pos(urow, du, w);
               }
             }
             const uint64_t hit = ballot(pos >= 0);
             if (pos >= 0) {
-              if (in_lds && !hashed) {
-                lpos[ns + rank_below(hit)] = (uint16_t)pos;
+              if (in_lds) {
+                lpos[ns + rank_below(hit)] = (uint16_t)pos;  // a slot, or a sorted position
               } else {
-                lst[ns + rank_below(hit)] = w;  // hashed: S as ascending ids
+                lst[ns + rank_below(hit)] = w;
               }
             }
             ns += popc(hit);
@@ -196,7 +217,13 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
               ns = 0;
             }
           }
-          if (!in_lds || ns < 2) continue;
+          if (!in_lds) continue;
+          if (ns < 2) {
+            if (hashed && ns == 1 && lane == 0)
+              atomicAnd(&sbits[lpos[0] >> 3], ~(my_bit << ((lpos[0] & 7) * 4)));
+            wave_sync();
+            continue;
+          }
           wave_sync();
           // The x in N+(w) that are kept w themselves, for the kept w 64 at a
           // time: lane a takes w = kept[a0 + a] (one round trip for the row bounds of
@@ -208,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
             int64_t wb = 0;
             int32_t dw = 0;
             if (a0 + lane < ns) {
-              const int32_t ww = hashed ? lst[a0 + lane] : tkeys[lpos[a0 + lane]];
+              const int32_t ww = tkeys[lpos[a0 + lane]];
               wb = row_ptr[ww];
               dw = (int32_t)((int64_t)row_ptr[ww + 1] - wb);
             }
@@ -221,7 +248,8 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
                   bool ok = false;
                   if (xb + lane < d1) {
                     const int32_t x = col[b1 + xb + lane];
-                    ok = hashed ? find_pos(lst, ns, x) >= 0 : in_kept(tkeys, lpos, ns, x);
+                    ok = hashed ? in_wave_set(tkeys, sbits, side, shift, my_bit, x)
+                                : in_kept(tkeys, lpos, ns, x);
                   }
                   found += popc(ballot(ok));
                 }
@@ -249,10 +277,16 @@ __global__ __launch_bounds__(kBlock) void k4_kernel(int64_t n, const OffT* __res
               bool ok = false;
               if (base + lane < total_x) {  // then start(src) <= base + lane < start(src) + dw(src)
                 const int32_t x = col[at];
-                ok = hashed ? find_pos(lst, ns, x) >= 0 : in_kept(tkeys, lpos, ns, x);
+                ok = hashed ? in_wave_set(tkeys, sbits, side, shift, my_bit, x)
+                            : in_kept(tkeys, lpos, ns, x);
               }
               found += popc(ballot(ok));
             }
+          }
+          if (hashed) {
+            // this wave's bits back to 0 for its next middle
+            for (int32_t a = lane; a < ns; a += kWave)
+              atomicAnd(&sbits[lpos[a] >> 3], ~(my_bit << ((lpos[a] & 7) * 4)));
           }
           wave_sync();  // the list is rewritten by this wave's next middle
         }
