@@ -8,13 +8,14 @@
 // Load balance is a segmented merge path over the whole graph.  Edge e = (u, v)
 // owns a stretch of the merge space of length d+(u) + d+(v) (0 when d+(u) < 2
 // or d+(v) = 0: the look-ahead of Sec. III-C), and an exclusive scan P lays the
-// stretches end to end.  The merge space is cut into chunks of kSteps merge
+// stretches end to end.  The merge space is cut into chunks of kLaneSteps merge
 // steps, 64 consecutive chunks per wave, and every wave takes one contiguous
 // run of those spans.  A lane finds its edge by a search of P, its place in
 // that edge's merge by the merge-path diagonal search, and merges one element
-// per step from its chunk's elements, staged first in LDS (all loads in
-// flight at once), moving on to the next edge with a non-empty stretch at a
-// stretch's end.  Ties take A = N+(u) first, and a match is counted when A[i]
+// per step from elements staged in LDS kSteps at a time (each round's loads in
+// flight at once; a round continues from the heads the last one left, so the
+// search is paid once per edge and chunk), moving on to the next edge with a
+// non-empty stretch at a stretch's end.  Ties take A = N+(u) first, and a match is counted when A[i]
 // is taken while B = N+(v)'s head equals it, so each common neighbour is found
 // exactly once, in the chunk that takes A[i].
 //
@@ -30,8 +31,10 @@ namespace tc {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSteps = 16;                        // merge steps per lane and span chunk
-constexpr int64_t kSpan = (int64_t)kWave * kSteps;  // merge steps per wave and span
+constexpr int kSteps = 8;   // merge steps per staging round
+constexpr int kRounds = 8;   // staging rounds per lane chunk
+constexpr int64_t kLaneSteps = (int64_t)kSteps * kRounds;  // merge steps per lane and span
+constexpr int64_t kSpan = (int64_t)kWave * kLaneSteps;      // merge steps per wave and span
 constexpr int32_t kPastEnd = INT32_MAX;            // head of an exhausted list (ids < 2^31 - 1)
 
 // Source of every edge and the length of its stretch; stretches past m are 0.
@@ -149,9 +152,9 @@ __global__ __launch_bounds__(kBlock, 4) void merge_kernel(int64_t cap, const Off
     e_lo = (first ? upper_bound(P, 0, cap + 1, base) : gallop_upper(P, e_lo, cap + 1, base)) - 1;
     first = false;
     const int64_t e_hi = gallop_upper(P, e_lo, cap + 1, last) - 1;
-    int64_t p = base + (int64_t)lane * kSteps;
+    int64_t p = base + (int64_t)lane * kLaneSteps;
     if (p > last) continue;
-    const int64_t pend = p + kSteps <= last + 1 ? p + kSteps : last + 1;
+    const int64_t pend = p + kLaneSteps <= last + 1 ? p + kLaneSteps : last + 1;
     int64_t e = upper_bound(P, e_lo, e_hi + 2, p) - 1;
     while (true) {
       const int64_t pe = P[e];
@@ -171,59 +174,65 @@ __global__ __launch_bounds__(kBlock, 4) void merge_kernel(int64_t cap, const Off
         if (col[ab + mid] <= col[bb + k - mid - 1]) lo = mid + 1;
         else hi = mid;
       }
-      const int64_t i = lo, j = k - lo;
+      int64_t i = lo, j = k - lo;
       const int64_t stop = pend < pe1 ? pend : pe1;
-      const int q = (int)(stop - p);  // merge steps of this edge in this chunk, 1..kSteps
-      // Stage the elements these q steps can take, A[i, i + q] and B[j, j + q] (past a
-      // list's end: kPastEnd), in this lane's LDS slots.  The loads take indices clamped
-      // to the list (a, b >= 1), so all of them are in flight together.
-      {
-        int32_t ra[kSteps + 1], rb[kSteps + 1];
-        if (Narrow) {
-          // column indices below 2^30: 32-bit offsets from the (uniform) column base
-          const uint32_t x0 = (uint32_t)(ab + i), xl = (uint32_t)(ab + a - 1);
-          const uint32_t y0 = (uint32_t)(bb + j), yl = (uint32_t)(bb + b - 1);
-#pragma unroll
-          for (int t = 0; t <= kSteps; ++t) {
-            ra[t] = list_at(col, x0 + t < xl ? x0 + t : xl);
-            rb[t] = list_at(col, y0 + t < yl ? y0 + t : yl);
-          }
-        } else {
-#pragma unroll
-          for (int t = 0; t <= kSteps; ++t) {
-            const int64_t x = i + t, y = j + t;
-            ra[t] = col[ab + (x < a ? x : a - 1)];
-            rb[t] = col[bb + (y < b ? y : b - 1)];
-          }
-        }
-#pragma unroll
-        for (int t = 0; t <= kSteps; ++t) {
-          sa[t * kWave] = i + t < a ? ra[t] : kPastEnd;
-          sb[t * kWave] = j + t < b ? rb[t] : kPastEnd;
-        }
-      }
-      int32_t ia = 0, ib = 0;
-      int32_t av = sa[0], bv = sb[0];
       uint32_t cuv = 0;
-      for (int s = 0; s < q; ++s) {
-        const bool take_a = av <= bv;
-        if (take_a && av == bv) {
-          ++cuv;
-          if (Support) {
-            atomicAdd(&sup[ab + i + ia], 1u);  // the edge (u, w)
-            atomicAdd(&sup[bb + j + ib], 1u);  // the edge (v, w)
+      // The steps [p, stop) of this edge, kSteps per round: a round stages the elements
+      // its q steps can take, A[i, i + q] and B[j, j + q] (past a list's end: kPastEnd), in
+      // this lane's LDS slots, then merges from there; the next round continues from the
+      // heads the last one left, with no second search.  The loads take indices clamped
+      // to the list (a, b >= 1), so all of a round's loads are in flight together.
+      while (p < stop) {
+        const int q = (int)(stop - p < kSteps ? stop - p : kSteps);  // 1..kSteps
+        {
+          int32_t ra[kSteps + 1], rb[kSteps + 1];
+          if (Narrow) {
+            // column indices below 2^30: 32-bit offsets from the (uniform) column base
+            const uint32_t x0 = (uint32_t)(ab + i), xl = (uint32_t)(ab + a - 1);
+            const uint32_t y0 = (uint32_t)(bb + j), yl = (uint32_t)(bb + b - 1);
+#pragma unroll
+            for (int t = 0; t <= kSteps; ++t) {
+              ra[t] = list_at(col, x0 + t < xl ? x0 + t : xl);
+              rb[t] = list_at(col, y0 + t < yl ? y0 + t : yl);
+            }
+          } else {
+#pragma unroll
+            for (int t = 0; t <= kSteps; ++t) {
+              const int64_t x = i + t, y = j + t;
+              ra[t] = col[ab + (x < a ? x : a - 1)];
+              rb[t] = col[bb + (y < b ? y : b - 1)];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t <= kSteps; ++t) {
+            sa[t * kWave] = i + t < a ? ra[t] : kPastEnd;
+            sb[t * kWave] = j + t < b ? rb[t] : kPastEnd;
           }
         }
-        // one LDS read per step: the next element of the list just taken from
-        if (take_a) ++ia;
-        else ++ib;
-        const int32_t x = take_a ? sa[ia * kWave] : sb[ib * kWave];
-        if (take_a) av = x;
-        else bv = x;
+        int32_t ia = 0, ib = 0;
+        int32_t av = sa[0], bv = sb[0];
+        for (int st = 0; st < q; ++st) {
+          const bool take_a = av <= bv;
+          if (take_a && av == bv) {
+            ++cuv;
+            if (Support) {
+              atomicAdd(&sup[ab + i + ia], 1u);  // the edge (u, w)
+              atomicAdd(&sup[bb + j + ib], 1u);  // the edge (v, w)
+            }
+          }
+          // one LDS read per step: the next element of the list just taken from
+          if (take_a) ++ia;
+          else ++ib;
+          const int32_t x = take_a ? sa[ia * kWave] : sb[ib * kWave];
+          if (take_a) av = x;
+          else bv = x;
+        }
+        i += ia;
+        j += ib;
+        p += q;
       }
       hits += cuv;
       if (Support && cuv) atomicAdd(&sup[e], cuv);  // the edge (u, v)
-      p = stop;
       if (p >= pend) break;
       e = gallop_upper(P, e + 1, e_hi + 2, p) - 1;
     }

@@ -36,7 +36,10 @@ def upper_bound(P, lo, hi, x):
     return lo
 
 
-def merge_emulate(rp, col, C):
+def merge_emulate(rp, col, C, R=None):
+    """Chunks of C steps per lane; with R, an edge's steps inside a chunk go in rounds of R
+    that restage both lists from the heads the previous round left (the kernel's LDS
+    rounds), reading the R + 1 elements from each head clamped to its list."""
     rp = [int(x) for x in rp]
     col = [int(x) for x in col]
     n = len(rp) - 1
@@ -85,7 +88,16 @@ def merge_emulate(rp, col, C):
                 bv = rd(bb, j, b) if j < b else BIG
                 steps = min(pend, P[e + 1]) - p
                 cuv = 0
-                for _ in range(steps):
+                for t in range(steps):
+                    if R and t % R == 0:
+                        # a new round: stage A[i, i + R] and B[j, j + R] from the heads
+                        for x in range(R + 1):
+                            if a:
+                                rd(ab, min(i + x, a - 1), a)
+                            if b:
+                                rd(bb, min(j + x, b - 1), b)
+                        av = rd(ab, i, a) if i < a else BIG
+                        bv = rd(bb, j, b) if j < b else BIG
                     if av <= bv:
                         if av == bv:
                             hits += 1
@@ -119,6 +131,10 @@ def _check(n, s, d, chunks=(1, 3, 8, 64)):
         h, s_ = merge_emulate(dp, dc, C)
         assert h == T, C
         np.testing.assert_array_equal(s_, sup)
+    # the kernel's layout: 64-step chunks merged in rounds of 8
+    h, s_ = merge_emulate(dp, dc, 64, R=8)
+    assert h == T
+    np.testing.assert_array_equal(s_, sup)
 
 
 @pytest.mark.parametrize("seed", range(6))
