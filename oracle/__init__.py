@@ -60,6 +60,8 @@ def _load():
         lib.oracle_count_diamonds.argtypes = [i64, i64, p, p]
         lib.oracle_count_labelled.restype = ctypes.c_uint64
         lib.oracle_count_labelled.argtypes = [i64, p, p, p, i32, i32, i32]
+        lib.oracle_count_edge_labelled.restype = i64
+        lib.oracle_count_edge_labelled.argtypes = [i64, p, p, i64, p, p, p, i32, i32, i32]
         lib.oracle_count_directed.restype = i64
         lib.oracle_count_directed.argtypes = [i64, p, p, i64, p, p, i32, i32, i32, i32, i64]
         lib.oracle_kcore.restype = i64
@@ -249,6 +251,33 @@ def directed(n: int, src, dst, pattern, *, induced: bool = False,
     rp, col = clean(n, src, dst)
     dp, dc = orient(rp, col, order)
     return count_directed(dp, dc, src, dst, pattern, induced=induced)
+
+
+def count_edge_labelled(dag_ptr: np.ndarray, dag_col: np.ndarray, src, dst, labels,
+                        query) -> int:
+    """Triangles whose edges carry the query's edge labels (q01, q02, q12), matched as
+    subgraphs; pair i has label labels[i], an edge given several times the largest."""
+    lib = _load()
+    dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
+    dag_col = _i32(dag_col)
+    s, d, lab = _i32(src), _i32(dst), _i32(labels)
+    if not s.size == d.size == lab.size:
+        raise ValueError("src, dst and labels differ in length")
+    q = [int(x) for x in query]
+    if len(q) != 3:
+        raise ValueError("the query has three edges")
+    r = int(lib.oracle_count_edge_labelled(dag_ptr.size - 1, _ptr(dag_ptr), _ptr(dag_col), s.size,
+                                           _ptr(s), _ptr(d), _ptr(lab), q[0], q[1], q[2]))
+    if r < 0:
+        raise OracleError(f"oracle_count_edge_labelled failed ({r})")
+    return r
+
+
+def edge_labelled(n: int, src, dst, labels, query, *, order: int = ORDER_DEGREE) -> int:
+    """Edge-labelled triangle query on a raw labelled pair list (clean, orient, match)."""
+    rp, col = clean(n, src, dst)
+    dp, dc = orient(rp, col, order)
+    return count_edge_labelled(dp, dc, src, dst, labels, query)
 
 
 def kcore(row_ptr: np.ndarray, col: np.ndarray, k: int = 2) -> np.ndarray:

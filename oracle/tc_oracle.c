@@ -57,6 +57,12 @@
  *    between two matched vertices are exactly the images of the query's).
  *    Matches count as subgraphs: embeddings divided by the query's
  *    automorphisms.
+ *  - oracle_count_edge_labelled: the triangle query with edge labels (Sec.
+ *    II-A: matching with edge label information): the data graph's undirected
+ *    edges carry labels (an edge given several times takes the largest of its
+ *    labels); a match maps the query's nodes one-to-one onto a triangle so that
+ *    each query edge lands on a data edge of the same label.  Counted as
+ *    subgraphs: maps divided by the query's label-preserving automorphisms.
  *
  * Every function is pinned by the CPU test suite against brute force over
  * vertex triples, trace(A^3)/6 and diag(A^3)/2, closed forms and invariants.
@@ -576,5 +582,127 @@ int64_t oracle_count_directed(int64_t n, const int64_t* dag_ptr, const int32_t* 
     }
   }
   free(keys);
+  return embeddings / aut;
+}
+
+/*
+ * oracle_count_edge_labelled - the triangle query with edge labels.
+ *
+ * Pairs (src[i], dst[i]) with labels lab[i] (src != dst; duplicates and both
+ * directions allowed): the undirected edge {a, b} has the largest label of its
+ * pairs.  dag_ptr / dag_col orient the undirected graph (as oracle_orient
+ * writes it) and enumerate its triangles.  The query's edges 0-1, 0-2, 1-2
+ * carry the labels q01, q02, q12.  An embedding is a one-to-one map f of the
+ * query nodes onto a triangle's vertices with label{f(i), f(j)} = q_ij for each
+ * query edge; the result is the number of embeddings divided by the number of
+ * permutations of the query nodes that keep every edge's label.
+ * Returns -2 if a pair holds an id outside [0, n), -1 on allocation failure.
+ * Single-threaded.
+ */
+static int32_t query_label(int32_t q01, int32_t q02, int32_t q12, int i, int j) {
+  int lo = i < j ? i : j, hi = i < j ? j : i;
+  return lo == 0 ? (hi == 1 ? q01 : q02) : q12;
+}
+
+/* label of edge {x, y} from the sorted (min << 32 | max) keys, or -1 */
+static int32_t edge_label_of(const uint64_t* keys, const int32_t* labs, int64_t nk, int64_t x,
+                             int64_t y) {
+  int64_t a = x < y ? x : y, b = x < y ? y : x;
+  uint64_t want = ((uint64_t)a << 32) | (uint64_t)b;
+  int64_t lo = 0, hi = nk;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (keys[mid] < want) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < nk && keys[lo] == want ? labs[lo] : -1;
+}
+
+typedef struct {
+  uint64_t key;
+  int32_t lab;
+} keyed_label;
+
+static int cmp_keyed(const void* a, const void* b) {
+  const keyed_label* x = (const keyed_label*)a;
+  const keyed_label* y = (const keyed_label*)b;
+  if (x->key != y->key) return (x->key > y->key) - (x->key < y->key);
+  return (x->lab > y->lab) - (x->lab < y->lab);
+}
+
+int64_t oracle_count_edge_labelled(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col,
+                                   int64_t num_pairs, const int32_t* src, const int32_t* dst,
+                                   const int32_t* lab, int32_t q01, int32_t q02, int32_t q12) {
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (int64_t i = 0; i < num_pairs; ++i)
+    if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return -2;
+  keyed_label* kl = (keyed_label*)malloc(sizeof(keyed_label) * (size_t)(num_pairs > 0 ? num_pairs : 1));
+  if (!kl) return -1;
+  int64_t k = 0;
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    int64_t a = src[i], b = dst[i];
+    if (a == b) continue;
+    if (a > b) { int64_t t = a; a = b; b = t; }
+    kl[k].key = ((uint64_t)a << 32) | (uint64_t)b;
+    kl[k].lab = lab[i];
+    ++k;
+  }
+  qsort(kl, (size_t)k, sizeof(keyed_label), cmp_keyed);
+  /* one entry per edge: the last of its run holds the largest label */
+  uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(k > 0 ? k : 1));
+  int32_t* labs = (int32_t*)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
+  if (!keys || !labs) {
+    free(kl); free(keys); free(labs);
+    return -1;
+  }
+  int64_t nk = 0;
+  for (int64_t i = 0; i < k; ++i) {
+    if (i + 1 < k && kl[i + 1].key == kl[i].key) continue;
+    keys[nk] = kl[i].key;
+    labs[nk] = kl[i].lab;
+    ++nk;
+  }
+  free(kl);
+  int64_t aut = 0;
+  for (int s = 0; s < 6; ++s) {
+    int same = 1;
+    for (int i = 0; i < 3; ++i)
+      for (int j = i + 1; j < 3; ++j)
+        if (query_label(q01, q02, q12, i, j) !=
+            query_label(q01, q02, q12, perms[s][i], perms[s][j]))
+          same = 0;
+    aut += same;
+  }
+  int64_t embeddings = 0;
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
+      int64_t v = dag_col[e];
+      int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];
+      int64_t j = dag_ptr[v], jend = dag_ptr[v + 1];
+      while (i < iend && j < jend) {
+        int32_t a = dag_col[i], b = dag_col[j];
+        if (a < b) {
+          ++i;
+        } else if (b < a) {
+          ++j;
+        } else {
+          int64_t t[3] = {u, v, a};
+          for (int s = 0; s < 6; ++s) {
+            int ok = 1;
+            for (int x = 0; x < 3 && ok; ++x)
+              for (int y = x + 1; y < 3 && ok; ++y)
+                if (edge_label_of(keys, labs, nk, t[perms[s][x]], t[perms[s][y]]) !=
+                    query_label(q01, q02, q12, x, y))
+                  ok = 0;
+            embeddings += ok;
+          }
+          ++i;
+          ++j;
+        }
+      }
+    }
+  }
+  free(keys);
+  free(labs);
   return embeddings / aut;
 }

@@ -805,3 +805,82 @@ def test_directed_sources_sample():
     parts = [oracle.count_directed(dp, dc, s, d, _codes(_CYCLE), sources=k)
              for k in range(0, n + 1, max(1, n // 8))]
     assert parts == sorted(parts)
+
+
+# ---- edge-labelled triangles ---------------------------------------------------------
+
+def _brute_edge_labelled(n, s, d, lab, q):
+    """Every ordered triple of distinct vertices as the image of query nodes 0, 1, 2, with
+    the label of each undirected edge the largest over its pairs; divided by the query's
+    label-preserving node permutations."""
+    import itertools
+    L = {}
+    for a, b, x in zip(s, d, lab):
+        a, b, x = int(a), int(b), int(x)
+        if a != b:
+            key = (min(a, b), max(a, b))
+            L[key] = max(L.get(key, x), x)
+    qlab = {(0, 1): q[0], (0, 2): q[1], (1, 2): q[2]}
+    emb = 0
+    for f in itertools.permutations(range(n), 3):
+        ok = True
+        for (i, j), want in qlab.items():
+            key = (min(f[i], f[j]), max(f[i], f[j]))
+            if L.get(key) != want:
+                ok = False
+        emb += ok
+    aut = sum(all(qlab[(min(p[i], p[j]), max(p[i], p[j]))] == qlab[(i, j)] for (i, j) in qlab)
+              for p in itertools.permutations(range(3)))
+    assert emb % aut == 0
+    return emb // aut
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_edge_labelled_brute_force_random_tiny(seed):
+    """All 27 queries over three edge labels, on random graphs whose pairs repeat with
+    different labels (the largest counts), against brute force over ordered vertex triples."""
+    import itertools
+    rng = np.random.default_rng(1100 + seed)
+    n = int(rng.integers(3, 12))
+    n, s, d = pins.random_simple(n, float(rng.choice([0.3, 0.6, 0.9])), seed)
+    n, s, d = pins.noisy(n, s, d, seed)
+    s, d = np.asarray(s), np.asarray(d)
+    lab = rng.integers(0, 3, size=s.size)
+    for q in itertools.product(range(3), repeat=3):
+        want = _brute_edge_labelled(n, s, d, lab, q)
+        order = oracle.ORDER_DEGREE if (seed + q[0]) % 2 else oracle.ORDER_ID
+        assert oracle.edge_labelled(n, s, d, lab, q, order=order) == want, q
+
+
+def test_edge_labelled_closed_forms():
+    """K_n with edge {i, j} labelled (i + j) mod 2: a triangle's three labels sum to an even
+    number, so it is all-even (three vertices of one parity) or has two odd labels; one
+    label everywhere gives every triangle."""
+    from math import comb
+    n = 11
+    s = np.array([i for i in range(n) for j in range(i + 1, n)])
+    d = np.array([j for i in range(n) for j in range(i + 1, n)])
+    lab = (s + d) % 2
+    e, o = (n + 1) // 2, n // 2
+    assert oracle.edge_labelled(n, s, d, lab, (0, 0, 0)) == comb(e, 3) + comb(o, 3)
+    assert oracle.edge_labelled(n, s, d, lab, (1, 0, 1)) == comb(e, 2) * o + comb(o, 2) * e
+    assert oracle.edge_labelled(n, s, d, lab, (1, 1, 0)) == comb(e, 2) * o + comb(o, 2) * e
+    assert oracle.edge_labelled(n, s, d, lab, (1, 1, 1)) == 0
+    assert oracle.edge_labelled(n, s, d, lab, (0, 0, 1)) == 0
+    assert oracle.edge_labelled(n, s, d, np.full(s.size, 2), (2, 2, 2)) == comb(n, 3)
+    # a pair given twice with labels 0 and 3 carries 3
+    assert oracle.edge_labelled(3, [0, 1, 2, 1], [1, 2, 0, 0], [0, 0, 0, 3], (0, 0, 3)) == 1
+    assert oracle.edge_labelled(3, [0, 1, 2, 1], [1, 2, 0, 0], [0, 0, 0, 3], (0, 0, 0)) == 0
+
+
+def test_edge_labelled_multisets_partition_the_triangles():
+    """Summed over every multiset of three edge labels, the counts give the unlabelled
+    total (a triangle matches exactly the query with its own label multiset, once)."""
+    import itertools
+    s, d, n = graphgen.rmat(9, 8, 7)
+    s, d = s.numpy(), d.numpy()
+    lab = np.random.default_rng(7).integers(0, 4, size=s.size)
+    T = oracle.triangles(n, s, d)
+    parts = sum(oracle.edge_labelled(n, s, d, lab, q)
+                for q in itertools.combinations_with_replacement(range(4), 3))
+    assert parts == T > 0
