@@ -479,6 +479,51 @@ tc_status tc_count_directed(const tc_csr* dag, const uint8_t* dir, int32_t p01, 
                             void* ws, size_t* ws_bytes, void* stream);
 
 /*
+ * tc_edge_labels - the labels of an edge-labelled data graph on the DAG of its
+ * underlying undirected graph (Sec. II-A: matching with edge label
+ * information), one byte per DAG edge.
+ *
+ *   dag           oriented CSR built from the same pairs
+ *   edge_capacity upper bound on m = dag row_ptr[n]
+ *   num_pairs     pairs {src[i], dst[i]} with label labels[i] (device int32,
+ *                 int32, uint8 [num_pairs]); labels in 0..3; a pair given
+ *                 several times (either direction) gives its edge the largest
+ *                 of its labels; self-loops are ignored
+ *   edge_labels   device uint8[edge_capacity rounded up to a multiple of 4],
+ *                 4-byte aligned (written): the label of each DAG edge, aligned
+ *                 with dag->col
+ *   m_out         device int64[1] (written): m, or negative: -TC_ERR_CAPACITY
+ *                 when m > edge_capacity, -TC_ERR_ID_OUT_OF_RANGE for an id
+ *                 outside [0, n), -TC_ERR_INVALID_ARG for a label above 3 or a
+ *                 pair that is not a DAG edge
+ * No workspace.
+ */
+tc_status tc_edge_labels(const tc_csr* dag, int64_t edge_capacity, int64_t num_pairs,
+                         const int32_t* src, const int32_t* dst, const uint8_t* labels,
+                         uint8_t* edge_labels, int64_t* m_out, void* stream);
+
+/*
+ * tc_count_edge_labelled - matches of a triangle query with edge labels: the
+ * query's edges 0-1, 0-2, 1-2 carry labels q01, q02, q12 (each 0..3); a match
+ * maps the query nodes one-to-one onto a triangle so that every query edge
+ * lands on a data edge of the same label, counted as subgraphs (maps divided
+ * by the query's label-preserving automorphisms): each triangle whose three
+ * edge labels form the query's multiset counts once.
+ * The same launch as tc_count_directed, with the labels as the per-edge codes:
+ * every closed wedge adds the table entry (built on the host from the query)
+ * of the labels of (u, v), (u, w) and (v, w).
+ *
+ *   dag           oriented CSR (as written by tc_orient, either order)
+ *   edge_labels   device uint8[m] as tc_edge_labels writes it for this DAG
+ *   total         device uint64[1] (written): the number of matches
+ *   tune          launch parameters or NULL (as for tc_count)
+ *   ws, ws_bytes  workspace; as tc_count's.
+ */
+tc_status tc_count_edge_labelled(const tc_csr* dag, const uint8_t* edge_labels, int32_t q01,
+                                 int32_t q02, int32_t q12, uint64_t* total, const tc_tune* tune,
+                                 void* ws, size_t* ws_bytes, void* stream);
+
+/*
  * tc_ne_filter - the candidate filter of Alg. 1: a data vertex can stand for a
  * query node only if its neighbourhood encoding (NE = degree, Sec. III-C)
  * covers the node's; every node of the triangle query has degree 2.  Iterated:

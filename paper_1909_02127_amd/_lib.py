@@ -106,6 +106,10 @@ def _load() -> ctypes.CDLL:
     lib.tc_edge_directions.argtypes = [csr, i64, i64, p, p, p, p, p]
     lib.tc_count_directed.restype = i32
     lib.tc_count_directed.argtypes = [csr, p, i32, i32, i32, i32, p, tune, p, sz, p]
+    lib.tc_edge_labels.restype = i32
+    lib.tc_edge_labels.argtypes = [csr, i64, i64, p, p, p, p, p, p]
+    lib.tc_count_edge_labelled.restype = i32
+    lib.tc_count_edge_labelled.argtypes = [csr, p, i32, i32, i32, p, tune, p, sz, p]
     lib.tc_list_triangles.restype = i32
     lib.tc_list_triangles.argtypes = [csr, p, i64, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
@@ -455,6 +459,42 @@ def tc_count_directed(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
     csr = make_csr(n, dag_row_ptr, dag_col)
     _ws_call(LIB.tc_count_directed, ws, ctypes.byref(csr), _ptr(direction), *p,
              int(bool(induced)), _ptr(total), _tune_ref(tune), stream=stream)
+
+
+def tc_edge_labels(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                   src: torch.Tensor, dst: torch.Tensor, labels: torch.Tensor,
+                   edge_labels: torch.Tensor, m_out: torch.Tensor, *, stream=None) -> None:
+    """Labels (uint8, 0..3) of the pairs {src[i], dst[i]} on the DAG built from them:
+    edge_labels (uint8, at least dag_col.numel() rounded up to 4 entries) gets each edge's
+    largest label; m_out (int64[1]) receives m or a negative status.  The edge capacity is
+    dag_col.numel()."""
+    if src.dtype != torch.int32 or dst.dtype != torch.int32 or src.numel() != dst.numel():
+        raise ValueError("src and dst must be int32 tensors of equal length")
+    if labels.dtype != torch.uint8 or labels.numel() != src.numel():
+        raise ValueError("labels must be uint8 with one entry per pair")
+    cap = dag_col.numel()
+    if edge_labels.dtype != torch.uint8 or edge_labels.numel() < (cap + 3) // 4 * 4:
+        raise ValueError("edge_labels must be uint8 with dag_col.numel() rounded up to 4 entries")
+    if m_out.dtype != torch.int64 or m_out.numel() != 1:
+        raise ValueError("m_out must be int64[1]")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _check(LIB.tc_edge_labels(ctypes.byref(csr), cap, src.numel(), _ptr(src), _ptr(dst),
+                              _ptr(labels), _ptr(edge_labels), _ptr(m_out), _stream(stream)))
+
+
+def tc_count_edge_labelled(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
+                           edge_labels: torch.Tensor, query, total: torch.Tensor,
+                           ws: torch.Tensor, *, tune=None, stream=None) -> None:
+    """Triangles whose edges carry the query's labels (q01, q02, q12) into total (int64[1]),
+    on the DAG and the labels tc_edge_labels wrote for it.  The workspace is tc_count's."""
+    q = [int(x) for x in query]
+    if len(q) != 3:
+        raise ValueError("the query has three edges")
+    if edge_labels.dtype != torch.uint8 or edge_labels.numel() < dag_col.numel():
+        raise ValueError("edge_labels must be uint8 with one entry per dag_col entry")
+    csr = make_csr(n, dag_row_ptr, dag_col)
+    _ws_call(LIB.tc_count_edge_labelled, ws, ctypes.byref(csr), _ptr(edge_labels), *q,
+             _ptr(total), _tune_ref(tune), stream=stream)
 
 
 def tc_list_triangles_workspace(n: int) -> int:

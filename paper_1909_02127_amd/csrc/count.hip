@@ -68,7 +68,8 @@ constexpr int kKindTotal = 0;      // the total (and optionally per-graph / per-
 constexpr int kKindPerVertex = 1;  // plus t(v) for every vertex
 constexpr int kKindList = 2;       // every triangle as a (u, v, w) row
 constexpr int kKindSupport = 3;    // triangles on every oriented edge
-constexpr int kKindDirected = 4;   // matches of a directed query (weighted hits)
+constexpr int kKindDirected = 4;   // matches of a query on per-edge codes: arc directions or
+                                   // edge labels (weighted hits)
 // Kinds that count hits per LDS slot (the (u, w) pairs of a source).
 __host__ __device__ constexpr bool counted(int kind) {
   return kind == kKindPerVertex || kind == kKindSupport;
@@ -419,8 +420,8 @@ struct ListCtx {
   uint32_t* sup;
   int64_t ubeg;
   uint64_t* tv;  // per-vertex counts (kModeGlobal adds t(w) per hit)
-  const uint8_t* dir;   // directed kind: arc directions per DAG edge
-  const uint32_t* tab;  // directed kind: matches per triangle by its direction codes (LDS)
+  const uint8_t* dir;   // directed kind: a 2-bit code per DAG edge (arc directions or label)
+  const uint32_t* tab;  // directed kind: matches per triangle by its three codes (LDS)
 };
 
 // Writes the wedges u -> v -> w of the lanes set in `hits` as rows (u, v, w).
@@ -457,7 +458,7 @@ __device__ __forceinline__ int32_t find_sorted(const int32_t* __restrict__ keys,
   return lo < n && keys[lo] == w ? lo : -1;
 }
 
-// Directed kind: the direction code of the edge (u, w) when w is a key of the
+// Directed kind: the code of the edge (u, w) when w is a key of the
 // slice (stored beside the key when the table was built), else -1.
 template <int Mode, bool Wide>
 __device__ __forceinline__ int32_t probe_code(const Table& t, const Slice& sl, int32_t w,
@@ -726,7 +727,7 @@ __device__ uint64_t scan_middles(const int32_t* __restrict__ nbrs, int64_t d,
     const int64_t i = first + j * stride;
     int32_t v = 0;
     OffT vb = 0, ve = 0;
-    uint32_t cuv16 = 0;  // directed kind: 16 x the direction code of (u, v)
+    uint32_t cuv16 = 0;  // directed kind: 16 x the code of (u, v)
     if (j < mine) {
       v = nbrs[i];
       vb = row_ptr[v];
@@ -783,7 +784,7 @@ struct ListArgs {
   const int64_t* off;
   int64_t cap;
   uint32_t* sup;
-  const uint8_t* dir;   // directed kind: arc directions per DAG edge
+  const uint8_t* dir;   // directed kind: a 2-bit code per DAG edge
   const uint32_t* tab;  // directed kind: set by the kernel (its LDS copy of the table)
 };
 
@@ -1556,6 +1557,42 @@ DirCodes directed_codes(const int32_t q[3], bool induced) {
   return t;
 }
 
+// The table of a triangle query with edge labels q = (q01, q02, q12): for every
+// combination of a triangle's edge labels (codes of (u, v), (u, w), (v, w)),
+// the one-to-one maps of the query nodes onto (u, v, w) = (0, 1, 2) that give
+// every query edge the label of its image, divided by the permutations of the
+// query nodes that keep every edge's label.
+DirCodes edge_label_codes(const int32_t q[3]) {
+  // label of the edge {i, j} under the pair codes c (c[0]: 0-1, c[1]: 0-2, c[2]: 1-2)
+  auto lab = [](const int32_t c[3], int i, int j) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    return c[lo == 0 ? hi - 1 : 2];
+  };
+  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  int aut = 0;
+  for (const auto& f : perm) {
+    bool keeps = true;
+    for (int i = 0; i < 3; ++i)
+      for (int j = i + 1; j < 3; ++j)
+        if (lab(q, i, j) != lab(q, f[i], f[j])) keeps = false;
+    aut += keeps;
+  }
+  DirCodes t{};
+  for (int c = 0; c < 64; ++c) {
+    const int32_t g[3] = {c >> 4, (c >> 2) & 3, c & 3};
+    int maps = 0;
+    for (const auto& f : perm) {
+      bool ok = true;
+      for (int i = 0; i < 3; ++i)
+        for (int j = i + 1; j < 3; ++j)
+          if (lab(g, f[i], f[j]) != lab(q, i, j)) ok = false;
+      maps += ok;
+    }
+    t.v[c] = (uint8_t)(maps / aut);
+  }
+  return t;
+}
+
 // One count launch of the directed kind: every wedge u -> v -> w closed by
 // (u, w) adds the table entry of its three direction codes.
 template <typename OffT>
@@ -1723,6 +1760,33 @@ extern "C" tc_status tc_count_directed(const tc_csr* dag, const uint8_t* dir, in
   else
     st = directed_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col, dir,
                                 codes, total, t, L, s);
+  return st == TC_OK ? ok() : st;
+}
+
+extern "C" tc_status tc_count_edge_labelled(const tc_csr* dag, const uint8_t* edge_labels,
+                                            int32_t q01, int32_t q02, int32_t q12,
+                                            uint64_t* total, const tc_tune* tune, void* ws,
+                                            size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  tc_status st = check_dag(dag);
+  if (st != TC_OK) return st;
+  Tune t;
+  if ((st = read_tune(tune, &t)) != TC_OK) return st;
+  const int32_t q[3] = {q01, q02, q12};
+  for (int32_t c : q)
+    if (c < 0 || c > 3) return fail(TC_ERR_INVALID_ARG, "edge labels must be in [0, 3], got %d", c);
+  if (workspace_query(ws, ws_bytes, carve_count(nullptr, dag->n, false).bytes, &st)) return st;
+  if (!dag->row_ptr || !total || (dag->n > 0 && !edge_labels))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const CountLayout L = carve_count(ws, dag->n, false);
+  const DirCodes codes = edge_label_codes(q);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dag->offset_bytes == 4)
+    st = directed_impl<int32_t>(dag->n, static_cast<const int32_t*>(dag->row_ptr), dag->col,
+                                edge_labels, codes, total, t, L, s);
+  else
+    st = directed_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col,
+                                edge_labels, codes, total, t, L, s);
   return st == TC_OK ? ok() : st;
 }
 

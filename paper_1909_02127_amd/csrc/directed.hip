@@ -1,5 +1,6 @@
-// directed.hip - tc_edge_directions: which way each edge of the DAG points in a
-// directed data graph.
+// directed.hip - per-edge codes of the DAG from the input pairs:
+// tc_edge_directions (which way each edge points in a directed data graph) and
+// tc_edge_labels (each edge's label in an edge-labelled one).
 //
 // The build and the orientation keep the undirected edges (the method is
 // stated for undirected graphs, Sec. II-A, which also says it extends to
@@ -86,8 +87,87 @@ tc_status check_edge_dag(const tc_csr* dag, int64_t edge_capacity) {
   return TC_OK;
 }
 
+// Every labelled pair {a, b} (a != b) raises the byte of the DAG edge between
+// a and b to its label (the largest label of an edge's pairs wins), through a
+// compare-and-swap of the byte's 32-bit word; a label above kMaxEdgeLabel is
+// reported as -TC_ERR_INVALID_ARG.
+constexpr int32_t kMaxEdgeLabel = 3;
+
+template <typename OffT>
+__global__ __launch_bounds__(256) void edge_label_kernel(const OffT* __restrict__ rp, int64_t n,
+                                                         const int32_t* __restrict__ col,
+                                                         int64_t num_pairs,
+                                                         const int32_t* __restrict__ src,
+                                                         const int32_t* __restrict__ dst,
+                                                         const uint8_t* __restrict__ labels,
+                                                         uint32_t* __restrict__ words,
+                                                         int64_t* __restrict__ m_out) {
+  if (*m_out < 0) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < num_pairs; i += stride) {
+    const int32_t a = src[i], b = dst[i];
+    if (a < 0 || a >= n || b < 0 || b >= n) {
+      *m_out = -(int64_t)TC_ERR_ID_OUT_OF_RANGE;
+      continue;
+    }
+    if (a == b) continue;
+    const uint32_t lab = labels[i];
+    if (lab > (uint32_t)kMaxEdgeLabel) {
+      *m_out = -(int64_t)TC_ERR_INVALID_ARG;
+      continue;
+    }
+    int64_t pos = row_find(col, (int64_t)rp[a], (int64_t)rp[a + 1], b);
+    if (pos < 0) pos = row_find(col, (int64_t)rp[b], (int64_t)rp[b + 1], a);
+    if (pos < 0) {
+      *m_out = -(int64_t)TC_ERR_INVALID_ARG;  // not an edge of this DAG
+      continue;
+    }
+    uint32_t* w = &words[pos >> 2];
+    const int sh = (int)(pos & 3) * 8;
+    uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (((old >> sh) & 0xFFu) < lab) {
+      const uint32_t want = (old & ~(0xFFu << sh)) | (lab << sh);
+      const uint32_t seen = atomicCAS(w, old, want);
+      if (seen == old) break;
+      old = seen;
+    }
+  }
+}
+
 }  // namespace
 }  // namespace tc
+
+extern "C" tc_status tc_edge_labels(const tc_csr* dag, int64_t edge_capacity, int64_t num_pairs,
+                                    const int32_t* src, const int32_t* dst, const uint8_t* labels,
+                                    uint8_t* edge_labels, int64_t* m_out, void* stream) {
+  using namespace tc;
+  tc_status st = check_edge_dag(dag, edge_capacity);
+  if (st != TC_OK) return st;
+  if (num_pairs < 0) return fail(TC_ERR_INVALID_ARG, "negative num_pairs");
+  if (!dag->row_ptr || !m_out || (edge_capacity > 0 && !edge_labels) ||
+      (num_pairs > 0 && (!src || !dst || !labels)))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(edge_labels) % 4 != 0)
+    return fail(TC_ERR_INVALID_ARG, "edge_labels must be 4-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* words = reinterpret_cast<uint32_t*>(edge_labels);
+  const int cg = grid_for((edge_capacity + 3) / 4, 256, 8192);
+  const int ag = grid_for(num_pairs, 256, 16384);
+  if (dag->offset_bytes == 4) {
+    const int32_t* rp = static_cast<const int32_t*>(dag->row_ptr);
+    dir_clear_kernel<int32_t><<<cg, 256, 0, s>>>(rp, dag->n, edge_capacity, words, m_out);
+    if (num_pairs > 0)
+      edge_label_kernel<int32_t><<<ag, 256, 0, s>>>(rp, dag->n, dag->col, num_pairs, src, dst,
+                                                    labels, words, m_out);
+  } else {
+    const int64_t* rp = static_cast<const int64_t*>(dag->row_ptr);
+    dir_clear_kernel<int64_t><<<cg, 256, 0, s>>>(rp, dag->n, edge_capacity, words, m_out);
+    if (num_pairs > 0)
+      edge_label_kernel<int64_t><<<ag, 256, 0, s>>>(rp, dag->n, dag->col, num_pairs, src, dst,
+                                                    labels, words, m_out);
+  }
+  return check_hip(hipGetLastError(), "tc_edge_labels launch") == TC_OK ? ok() : TC_ERR_HIP;
+}
 
 extern "C" tc_status tc_edge_directions(const tc_csr* dag, int64_t edge_capacity,
                                         int64_t num_pairs, const int32_t* src,

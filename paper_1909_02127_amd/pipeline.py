@@ -60,6 +60,9 @@ class Pipeline:
         self.list_count = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_labelled = None
         self.direction = None
+        self.edge_label = None
+        self.edge_label_m = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.edge_labelled_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.direction_m = torch.zeros(1, dtype=torch.int64, device=dev)
         self.directed_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.labelled_total = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -174,6 +177,36 @@ class Pipeline:
         _lib.tc_count_directed(self.n, self.dag_ptr, self.dag_col, self.direction, pattern,
                                self.directed_total, self.ws_count, induced=induced, tune=tune,
                                stream=stream)
+
+    def edge_labels(self, src: torch.Tensor, dst: torch.Tensor, labels: torch.Tensor,
+                    stream=None) -> None:
+        """Enqueue tc_edge_labels: the labels (uint8, 0..3) of the pairs given to build
+        recorded on the current DAG's edges, for edge_labelled()."""
+        cap = self.dag_col.numel()
+        if self.edge_label is None:
+            self.edge_label = torch.zeros((cap + 3) // 4 * 4, dtype=torch.uint8,
+                                          device=self.device)
+        _lib.tc_edge_labels(self.n, self.dag_ptr, self.dag_col, src, dst, labels,
+                            self.edge_label, self.edge_label_m, stream=stream)
+
+    def edge_labelled(self, query, *, stream=None, tune=None) -> None:
+        """Enqueue tc_count_edge_labelled (edge labels recorded by edge_labels()): result in
+        self.edge_labelled_total (read with edge_labelled_count())."""
+        tune = self.tune if tune is None else tune
+        if self.edge_label is None:
+            raise RuntimeError("edge_labels() must run first")
+        _lib.tc_count_edge_labelled(self.n, self.dag_ptr, self.dag_col, self.edge_label, query,
+                                    self.edge_labelled_total, self.ws_count, tune=tune,
+                                    stream=stream)
+
+    def edge_labelled_count(self) -> int:
+        """Synchronise and read the result of edge_labelled() (raises when the labels
+        reported an error)."""
+        torch.cuda.synchronize(self.device)
+        em = int(self.edge_label_m.item())
+        if em < 0:
+            raise TcError(-em, "reported by tc_edge_labels on the device")
+        return int(self.edge_labelled_total.item()) & ((1 << 64) - 1)
 
     def directed_count(self) -> int:
         """Synchronise and read the result of directed() (raises when the directions reported
