@@ -61,7 +61,7 @@ def _load():
         lib.oracle_count_labelled.restype = ctypes.c_uint64
         lib.oracle_count_labelled.argtypes = [i64, p, p, p, i32, i32, i32]
         lib.oracle_count_edge_labelled.restype = i64
-        lib.oracle_count_edge_labelled.argtypes = [i64, p, p, i64, p, p, p, i32, i32, i32]
+        lib.oracle_count_edge_labelled.argtypes = [i64, p, p, i64, p, p, p, i32, i32, i32, i64]
         lib.oracle_count_directed.restype = i64
         lib.oracle_count_directed.argtypes = [i64, p, p, i64, p, p, i32, i32, i32, i32, i64]
         lib.oracle_kcore.restype = i64
@@ -254,9 +254,10 @@ def directed(n: int, src, dst, pattern, *, induced: bool = False,
 
 
 def count_edge_labelled(dag_ptr: np.ndarray, dag_col: np.ndarray, src, dst, labels,
-                        query) -> int:
+                        query, sources=None) -> int:
     """Triangles whose edges carry the query's edge labels (q01, q02, q12), matched as
-    subgraphs; pair i has label labels[i], an edge given several times the largest."""
+    subgraphs; pair i has label labels[i], an edge given several times the largest.  With
+    `sources`, only the triangles whose DAG source has an id below it count."""
     lib = _load()
     dag_ptr = np.ascontiguousarray(dag_ptr, dtype=np.int64)
     dag_col = _i32(dag_col)
@@ -267,7 +268,8 @@ def count_edge_labelled(dag_ptr: np.ndarray, dag_col: np.ndarray, src, dst, labe
     if len(q) != 3:
         raise ValueError("the query has three edges")
     r = int(lib.oracle_count_edge_labelled(dag_ptr.size - 1, _ptr(dag_ptr), _ptr(dag_col), s.size,
-                                           _ptr(s), _ptr(d), _ptr(lab), q[0], q[1], q[2]))
+                                           _ptr(s), _ptr(d), _ptr(lab), q[0], q[1], q[2],
+                                           _sources(dag_ptr, sources)))
     if r < 0:
         raise OracleError(f"oracle_count_edge_labelled failed ({r})")
     return r

@@ -595,7 +595,8 @@ int64_t oracle_count_directed(int64_t n, const int64_t* dag_ptr, const int32_t* 
  * carry the labels q01, q02, q12.  An embedding is a one-to-one map f of the
  * query nodes onto a triangle's vertices with label{f(i), f(j)} = q_ij for each
  * query edge; the result is the number of embeddings divided by the number of
- * permutations of the query nodes that keep every edge's label.
+ * permutations of the query nodes that keep every edge's label.  Only the
+ * triangles whose DAG source has an id below `sources` count (n: all).
  * Returns -2 if a pair holds an id outside [0, n), -1 on allocation failure.
  * Single-threaded.
  */
@@ -632,7 +633,8 @@ static int cmp_keyed(const void* a, const void* b) {
 
 int64_t oracle_count_edge_labelled(int64_t n, const int64_t* dag_ptr, const int32_t* dag_col,
                                    int64_t num_pairs, const int32_t* src, const int32_t* dst,
-                                   const int32_t* lab, int32_t q01, int32_t q02, int32_t q12) {
+                                   const int32_t* lab, int32_t q01, int32_t q02, int32_t q12,
+                                   int64_t sources) {
   static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
   for (int64_t i = 0; i < num_pairs; ++i)
     if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return -2;
@@ -674,7 +676,7 @@ int64_t oracle_count_edge_labelled(int64_t n, const int64_t* dag_ptr, const int3
     aut += same;
   }
   int64_t embeddings = 0;
-  for (int64_t u = 0; u < n; ++u) {
+  for (int64_t u = 0; u < sources; ++u) {
     for (int64_t e = dag_ptr[u]; e < dag_ptr[u + 1]; ++e) {
       int64_t v = dag_col[e];
       int64_t i = dag_ptr[u], iend = dag_ptr[u + 1];

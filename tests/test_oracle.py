@@ -884,3 +884,20 @@ def test_edge_labelled_multisets_partition_the_triangles():
     parts = sum(oracle.edge_labelled(n, s, d, lab, q)
                 for q in itertools.combinations_with_replacement(range(4), 3))
     assert parts == T > 0
+
+
+def test_edge_labelled_sources_sample():
+    """The benchmark's bounded sample: all sources give the whole count, none give 0, and
+    the sample grows with the bound."""
+    s, d, n = graphgen.rmat(8, 8, 4)
+    s, d = s.numpy(), d.numpy()
+    lab = np.random.default_rng(4).integers(0, 2, size=s.size)
+    rp, col = oracle.clean(n, s, d)
+    dp, dc = oracle.orient(rp, col)
+    full = oracle.count_edge_labelled(dp, dc, s, d, lab, (0, 1, 1))
+    assert full > 0
+    assert oracle.count_edge_labelled(dp, dc, s, d, lab, (0, 1, 1), sources=n) == full
+    assert oracle.count_edge_labelled(dp, dc, s, d, lab, (0, 1, 1), sources=0) == 0
+    parts = [oracle.count_edge_labelled(dp, dc, s, d, lab, (0, 1, 1), sources=k)
+             for k in range(0, n + 1, max(1, n // 8))]
+    assert parts == sorted(parts)
