@@ -504,24 +504,35 @@ tc_status tc_edge_labels(const tc_csr* dag, int64_t edge_capacity, int64_t num_p
 
 /*
  * tc_count_edge_labelled - matches of a triangle query with edge labels: the
- * query's edges 0-1, 0-2, 1-2 carry labels q01, q02, q12 (each 0..3); a match
- * maps the query nodes one-to-one onto a triangle so that every query edge
- * lands on a data edge of the same label, counted as subgraphs (maps divided
- * by the query's label-preserving automorphisms): each triangle whose three
- * edge labels form the query's multiset counts once.
- * The same launch as tc_count_directed, with the labels as the per-edge codes:
- * every closed wedge adds the table entry (built on the host from the query)
- * of the labels of (u, v), (u, w) and (v, w).
+ * query's edges 0-1, 0-2, 1-2 carry labels q01, q02, q12 (each 0..3, in any
+ * order: the nodes' permutations permute a triangle's edges); a match maps the
+ * query nodes one-to-one onto a triangle so that every query edge lands on a
+ * data edge of the same label, counted as subgraphs (maps divided by the
+ * query's label-preserving automorphisms): each triangle whose three edge
+ * labels form the query's multiset counts once.
+ * Alg. 1's candidate filtering with edge labels: the DAG edges whose label is
+ * one of the query's are compacted (with their labels) into a DAG on the same
+ * vertices; then the count kernel's coded launch (as tc_count_directed's, the
+ * labels as the per-edge codes) adds, per closed wedge, the entry of a table
+ * built on the host from the query for the labels of (u, v), (u, w), (v, w).
  *
  *   dag           oriented CSR (as written by tc_orient, either order)
+ *   edge_capacity upper bound on m = dag row_ptr[n]; sizes the workspace; at
+ *                 most INT32_MAX with 4-byte offsets
  *   edge_labels   device uint8[m] as tc_edge_labels writes it for this DAG
- *   total         device uint64[1] (written): the number of matches
- *   tune          launch parameters or NULL (as for tc_count)
- *   ws, ws_bytes  workspace; as tc_count's.
+ *   total         device uint64[1] (written): the number of matches, 0 on a
+ *                 capacity error
+ *   kept_out      device int64[1] or NULL (written): the DAG edges whose label
+ *                 is in the query, or -TC_ERR_CAPACITY when m > edge_capacity
+ *   tune          launch parameters of the count, or NULL (as for tc_count)
+ *   ws, ws_bytes  workspace: the filtered DAG and its labels (offsets and 6
+ *                 bytes per edge of capacity), 24 bytes per vertex, and
+ *                 tc_count's workspace.
  */
-tc_status tc_count_edge_labelled(const tc_csr* dag, const uint8_t* edge_labels, int32_t q01,
-                                 int32_t q02, int32_t q12, uint64_t* total, const tc_tune* tune,
-                                 void* ws, size_t* ws_bytes, void* stream);
+tc_status tc_count_edge_labelled(const tc_csr* dag, int64_t edge_capacity,
+                                 const uint8_t* edge_labels, int32_t q01, int32_t q02,
+                                 int32_t q12, uint64_t* total, int64_t* kept_out,
+                                 const tc_tune* tune, void* ws, size_t* ws_bytes, void* stream);
 
 /*
  * tc_ne_filter - the candidate filter of Alg. 1: a data vertex can stand for a

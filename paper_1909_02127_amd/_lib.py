@@ -109,7 +109,7 @@ def _load() -> ctypes.CDLL:
     lib.tc_edge_labels.restype = i32
     lib.tc_edge_labels.argtypes = [csr, i64, i64, p, p, p, p, p, p]
     lib.tc_count_edge_labelled.restype = i32
-    lib.tc_count_edge_labelled.argtypes = [csr, p, i32, i32, i32, p, tune, p, sz, p]
+    lib.tc_count_edge_labelled.argtypes = [csr, i64, p, i32, i32, i32, p, p, tune, p, sz, p]
     lib.tc_list_triangles.restype = i32
     lib.tc_list_triangles.argtypes = [csr, p, i64, p, tune, p, sz, p]
     lib.tc_status_string.restype = ctypes.c_char_p
@@ -482,19 +482,30 @@ def tc_edge_labels(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
                               _ptr(labels), _ptr(edge_labels), _ptr(m_out), _stream(stream)))
 
 
+def tc_count_edge_labelled_workspace(n: int, edge_capacity: int, offset_bytes: int = 4) -> int:
+    csr = tc_csr(n, offset_bytes, None, None)
+    return _ws_query(LIB.tc_count_edge_labelled, ctypes.byref(csr), edge_capacity, None, 0, 0, 0,
+                     None, None, None)
+
+
 def tc_count_edge_labelled(n: int, dag_row_ptr: torch.Tensor, dag_col: torch.Tensor,
                            edge_labels: torch.Tensor, query, total: torch.Tensor,
-                           ws: torch.Tensor, *, tune=None, stream=None) -> None:
+                           ws: torch.Tensor, *, kept_out: torch.Tensor | None = None, tune=None,
+                           stream=None) -> None:
     """Triangles whose edges carry the query's labels (q01, q02, q12) into total (int64[1]),
-    on the DAG and the labels tc_edge_labels wrote for it.  The workspace is tc_count's."""
+    on the DAG and the labels tc_edge_labels wrote for it; kept_out (int64[1]) receives the
+    DAG edges whose label is in the query, or -TC_ERR_CAPACITY.  The edge capacity is
+    dag_col.numel()."""
     q = [int(x) for x in query]
     if len(q) != 3:
         raise ValueError("the query has three edges")
     if edge_labels.dtype != torch.uint8 or edge_labels.numel() < dag_col.numel():
         raise ValueError("edge_labels must be uint8 with one entry per dag_col entry")
+    if kept_out is not None and (kept_out.dtype != torch.int64 or kept_out.numel() != 1):
+        raise ValueError("kept_out must be int64[1]")
     csr = make_csr(n, dag_row_ptr, dag_col)
-    _ws_call(LIB.tc_count_edge_labelled, ws, ctypes.byref(csr), _ptr(edge_labels), *q,
-             _ptr(total), _tune_ref(tune), stream=stream)
+    _ws_call(LIB.tc_count_edge_labelled, ws, ctypes.byref(csr), dag_col.numel(), _ptr(edge_labels),
+             *q, _ptr(total), _ptr(kept_out), _tune_ref(tune), stream=stream)
 
 
 def tc_list_triangles_workspace(n: int) -> int:

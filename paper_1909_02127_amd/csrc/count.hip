@@ -1763,18 +1763,20 @@ extern "C" tc_status tc_count_directed(const tc_csr* dag, const uint8_t* dir, in
   return st == TC_OK ? ok() : st;
 }
 
-extern "C" tc_status tc_count_edge_labelled(const tc_csr* dag, const uint8_t* edge_labels,
-                                            int32_t q01, int32_t q02, int32_t q12,
-                                            uint64_t* total, const tc_tune* tune, void* ws,
-                                            size_t* ws_bytes, void* stream) {
-  using namespace tc;
+// The coded count of an edge-labelled query, for tc_count_edge_labelled (which
+// first filters the DAG to the edges whose label is in the query).
+namespace tc {
+
+tc_status count_coded_edge_labels(const tc_csr* dag, const uint8_t* edge_labels, const int32_t q[3],
+                                  uint64_t* total, const tc_tune* tune, void* ws,
+                                  size_t* ws_bytes, void* stream) {
   tc_status st = check_dag(dag);
   if (st != TC_OK) return st;
   Tune t;
   if ((st = read_tune(tune, &t)) != TC_OK) return st;
-  const int32_t q[3] = {q01, q02, q12};
-  for (int32_t c : q)
-    if (c < 0 || c > 3) return fail(TC_ERR_INVALID_ARG, "edge labels must be in [0, 3], got %d", c);
+  for (int i = 0; i < 3; ++i)
+    if (q[i] < 0 || q[i] > 3)
+      return fail(TC_ERR_INVALID_ARG, "edge labels must be in [0, 3], got %d", q[i]);
   if (workspace_query(ws, ws_bytes, carve_count(nullptr, dag->n, false).bytes, &st)) return st;
   if (!dag->row_ptr || !total || (dag->n > 0 && !edge_labels))
     return fail(TC_ERR_INVALID_ARG, "null device pointer");
@@ -1787,8 +1789,10 @@ extern "C" tc_status tc_count_edge_labelled(const tc_csr* dag, const uint8_t* ed
   else
     st = directed_impl<int64_t>(dag->n, static_cast<const int64_t*>(dag->row_ptr), dag->col,
                                 edge_labels, codes, total, t, L, s);
-  return st == TC_OK ? ok() : st;
+  return st;
 }
+
+}  // namespace tc
 
 extern "C" tc_status tc_count_diamonds(const tc_csr* dag, int64_t edge_capacity, uint64_t* total,
                                        int64_t* m_out, const tc_tune* tune, void* ws,

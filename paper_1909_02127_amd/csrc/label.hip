@@ -111,14 +111,16 @@ __global__ void label_status_kernel(const OffT* __restrict__ rp, int64_t n, int6
   totals[1] = 0;
 }
 
-// Pass 1: kept out-degree of every source, and the keep flag of each edge of
-// the sources whose label is in the query (the rows of the others are not
-// read and keep nothing).
-template <typename OffT>
+// Pass 1: kept out-degree of every source, and the keep flag of each edge it
+// reads.  Node labels (Edge false): the edges of the sources whose label is in
+// the query (the rows of the others are not read and keep nothing), kept when
+// the pair of labels fits the query.  Edge labels (Edge true): every edge,
+// kept when its own label is one of the query's.
+template <typename OffT, bool Edge>
 __global__ __launch_bounds__(256) void label_degree_kernel(
     int64_t n, const OffT* __restrict__ rp, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ labels, Query q, const int64_t* __restrict__ status,
-    uint8_t* __restrict__ keep, int64_t* __restrict__ deg) {
+    const int32_t* __restrict__ labels, const uint8_t* __restrict__ elab, Query q,
+    const int64_t* __restrict__ status, uint8_t* __restrict__ keep, int64_t* __restrict__ deg) {
   __shared__ WalkLds lds_all[256 / kWave];
   WalkLds& L = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
@@ -132,8 +134,8 @@ __global__ __launch_bounds__(256) void label_degree_kernel(
     const int64_t x = r0 + lane < n ? r0 + lane : n;
     const int64_t bnd = lane <= kRows ? (int64_t)rp[x] : 0;
     const bool row_ok = lane < kRows && r0 + lane < n;
-    const int32_t lab = row_ok ? labels[r0 + lane] : 0;
-    const uint64_t cand = ballot(row_ok && !bad && label_in(q, lab));
+    const int32_t lab = !Edge && row_ok ? labels[r0 + lane] : 0;
+    const uint64_t cand = ballot(row_ok && !bad && (Edge || label_in(q, lab)));
     // cross-lane reads are made by every lane, outside any condition (a lane
     // reading from one that skipped the instruction would get no value)
     const int64_t bnd_next = __shfl_down(bnd, 1, kWave);
@@ -150,15 +152,16 @@ __global__ __launch_bounds__(256) void label_degree_kernel(
       for (int k = 0; k < kSteps; ++k) {
         const int64_t e = e0 + k * kWave + lane;
         act[k] = e < e_end && ((cand >> row[k]) & 1);
-        v[k] = act[k] ? col[e] : 0;
+        // edge labels: the edge's own label; node labels: the column, then its label
+        v[k] = act[k] ? (Edge ? (int32_t)elab[e] : col[e]) : 0;
       }
 #pragma unroll
-      for (int k = 0; k < kSteps; ++k) lv[k] = act[k] ? labels[v[k]] : 0;
+      for (int k = 0; k < kSteps; ++k) lv[k] = !Edge && act[k] ? labels[v[k]] : 0;
 #pragma unroll
       for (int k = 0; k < kSteps; ++k) {
         const int64_t e = e0 + k * kWave + lane;
         const int32_t lu = __shfl(lab, row[k], kWave);
-        const bool kp = act[k] && pair_fits(q, lu, lv[k]);
+        const bool kp = act[k] && (Edge ? label_in(q, v[k]) : pair_fits(q, lu, lv[k]));
         if (act[k]) keep[e] = (uint8_t)kp;
         const uint64_t b = ballot(kp);
         // the last lane of each row's part of the step adds the part's kept edges
@@ -188,12 +191,13 @@ struct OffStore {
 // keep flags were written by pass 1).  When the capacity check failed, or the
 // kept edges exceed the capacity, every row is written empty (the count then
 // sees a graph with no edges).
-template <typename OffT>
+template <typename OffT, bool Edge>
 __global__ __launch_bounds__(256) void label_compact_kernel(
     int64_t n, const OffT* __restrict__ rp, const int32_t* __restrict__ col,
     const uint8_t* __restrict__ keep, const int64_t* __restrict__ off,
     const int64_t* __restrict__ partial, int64_t tiles, int64_t cap,
-    const int64_t* __restrict__ status, OffT* __restrict__ frp, int32_t* __restrict__ fcol) {
+    const int64_t* __restrict__ status, OffT* __restrict__ frp, int32_t* __restrict__ fcol,
+    const uint8_t* __restrict__ elab, uint8_t* __restrict__ flab) {
   __shared__ WalkLds lds_all[256 / kWave];
   WalkLds& L = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
@@ -240,8 +244,11 @@ __global__ __launch_bounds__(256) void label_compact_kernel(
         const int64_t e = e0 + k * kWave + lane;
         const uint64_t b = ballot(kp[k]);
         // rank in the row: the row's kept edges of earlier steps, then this part's
-        if (kp[k])
-          fcol[L.at[row[k]] + L.count[row[k]] + popc(b & lane_range(seg0[k], lane))] = v[k];
+        if (kp[k]) {
+          const int64_t pos = L.at[row[k]] + L.count[row[k]] + popc(b & lane_range(seg0[k], lane));
+          fcol[pos] = v[k];
+          if (Edge) flab[pos] = elab[e];  // the kept edge's label moves with it
+        }
         const bool in = e < e_end;
         const int32_t row_next = __shfl_down(row[k], 1, kWave);
         const bool next_same = lane + 1 < kWave && e + 1 < e_end && row_next == row[k];
@@ -276,12 +283,14 @@ struct LabelLayout {
   int64_t* partial2;
   void* frp;         // filtered DAG row offsets (the input's offset type)
   int32_t* fcol;     // filtered DAG columns
+  uint8_t* flab;     // edge labels: the kept edges' labels, aligned with fcol
   void* cws;         // tc_count workspace
   size_t cws_bytes;
   size_t bytes;
 };
 
-LabelLayout carve_label(void* ws, int64_t n, int64_t cap, int offset_bytes, size_t count_bytes) {
+LabelLayout carve_label(void* ws, int64_t n, int64_t cap, int offset_bytes, size_t count_bytes,
+                        bool edge = false) {
   Carver c(ws);
   LabelLayout L;
   L.status = c.take<int64_t>(1);
@@ -293,19 +302,19 @@ LabelLayout carve_label(void* ws, int64_t n, int64_t cap, int offset_bytes, size
   L.partial2 = c.take<int64_t>(scan_partial_len(n));
   L.frp = c.take<char>((n + 1) * offset_bytes);
   L.fcol = c.take<int32_t>(cap);
+  L.flab = edge ? c.take<uint8_t>(cap) : nullptr;
   L.cws = c.take<char>((int64_t)count_bytes);
   L.cws_bytes = count_bytes;
   L.bytes = c.used();
   return L;
 }
 
-// One filter of the DAG by the query's label pairs, then one count of the
-// filtered DAG into *t.  `partial` receives the scan partials (its last entry
-// is the number of kept edges).
-template <typename OffT>
-tc_status filter_and_count(const tc_csr* dag, const int32_t* labels, const Query& q, int64_t cap,
-                           const LabelLayout& L, int64_t* partial, uint64_t* t,
-                           const tc_tune* tune, hipStream_t s) {
+// One filter of the DAG into the compacted DAG (frp, fcol, and with edge labels
+// flab).  `partial` receives the scan partials (its last entry is the number of
+// kept edges).
+template <typename OffT, bool Edge>
+tc_status run_filter(const tc_csr* dag, const int32_t* labels, const uint8_t* elab, const Query& q,
+                     int64_t cap, const LabelLayout& L, int64_t* partial, hipStream_t s) {
   const int64_t n = dag->n;
   const OffT* rp = static_cast<const OffT*>(dag->row_ptr);
   OffT* frp = static_cast<OffT*>(L.frp);
@@ -314,28 +323,31 @@ tc_status filter_and_count(const tc_csr* dag, const int32_t* labels, const Query
   const int waves_per_block = 256 / kWave;
   const int grid = grid_for((n + kRows - 1) / kRows, waves_per_block, 8 * device_cu_count());
   if (n > 0)
-    label_degree_kernel<OffT><<<grid, 256, 0, s>>>(n, rp, dag->col, labels, q, L.status, L.keep,
-                                                   L.deg);
+    label_degree_kernel<OffT, Edge><<<grid, 256, 0, s>>>(n, rp, dag->col, labels, elab, q,
+                                                         L.status, L.keep, L.deg);
   hipError_t e = scan_exclusive<OpSum>(n, DegLoad{L.deg}, OffStore{L.off}, partial, s);
   if (e != hipSuccess) return check_hip(e, "label filter scan");
   const int64_t tiles = scan_num_tiles(n);
-  label_compact_kernel<OffT><<<n > 0 ? grid : 1, 256, 0, s>>>(n, rp, dag->col, L.keep, L.off,
-                                                             partial, tiles, cap, L.status, frp,
-                                                             L.fcol);
-  if ((e = hipGetLastError()) != hipSuccess) return check_hip(e, "label filter launch");
-  tc_csr f{n, dag->offset_bytes, L.frp, L.fcol};
+  label_compact_kernel<OffT, Edge><<<n > 0 ? grid : 1, 256, 0, s>>>(
+      n, rp, dag->col, L.keep, L.off, partial, tiles, cap, L.status, frp, L.fcol, elab, L.flab);
+  return check_hip(hipGetLastError(), "label filter launch");
+}
+
+// One filter of the DAG by the query's label pairs, then one count of the
+// filtered DAG into *t.
+template <typename OffT>
+tc_status filter_and_count(const tc_csr* dag, const int32_t* labels, const Query& q, int64_t cap,
+                           const LabelLayout& L, int64_t* partial, uint64_t* t,
+                           const tc_tune* tune, hipStream_t s) {
+  tc_status st = run_filter<OffT, false>(dag, labels, nullptr, q, cap, L, partial, s);
+  if (st != TC_OK) return st;
+  tc_csr f{dag->n, dag->offset_bytes, L.frp, L.fcol};
   size_t bytes = L.cws_bytes;
   return tc_count(&f, t, tune, L.cws, &bytes, s);
 }
 
-}  // namespace
-}  // namespace tc
-
-extern "C" tc_status tc_count_labelled(const tc_csr* dag, int64_t edge_capacity,
-                                       const int32_t* labels, int32_t a, int32_t b, int32_t c,
-                                       uint64_t* total, int64_t* kept_out, const tc_tune* tune,
-                                       void* ws, size_t* ws_bytes, void* stream) {
-  using namespace tc;
+// Shared checks of the two labelled entry points.
+tc_status check_labelled(const tc_csr* dag, int64_t edge_capacity) {
   if (!dag) return fail(TC_ERR_INVALID_ARG, "dag is NULL");
   const int64_t n = dag->n;
   if (n < 0) return fail(TC_ERR_INVALID_ARG, "negative n");
@@ -348,10 +360,24 @@ extern "C" tc_status tc_count_labelled(const tc_csr* dag, int64_t edge_capacity,
   if (dag->offset_bytes == 4 && edge_capacity > INT32_MAX)
     return fail(TC_ERR_INVALID_ARG, "edge_capacity=%lld does not fit 4-byte offsets",
                 (long long)edge_capacity);
+  return TC_OK;
+}
+
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_count_labelled(const tc_csr* dag, int64_t edge_capacity,
+                                       const int32_t* labels, int32_t a, int32_t b, int32_t c,
+                                       uint64_t* total, int64_t* kept_out, const tc_tune* tune,
+                                       void* ws, size_t* ws_bytes, void* stream) {
+  using namespace tc;
+  tc_status st = check_labelled(dag, edge_capacity);
+  if (st != TC_OK) return st;
+  const int64_t n = dag->n;
   // the count's workspace (also validates the tune)
   size_t count_bytes = 0;
   tc_csr probe{n, dag->offset_bytes, nullptr, nullptr};
-  tc_status st = tc_count(&probe, nullptr, tune, nullptr, &count_bytes, nullptr);
+  st = tc_count(&probe, nullptr, tune, nullptr, &count_bytes, nullptr);
   if (st != TC_OK) return st;
   const LabelLayout need = carve_label(nullptr, n, edge_capacity, dag->offset_bytes, count_bytes);
   if (workspace_query(ws, ws_bytes, need.bytes, &st)) return st;
@@ -385,4 +411,50 @@ extern "C" tc_status tc_count_labelled(const tc_csr* dag, int64_t edge_capacity,
   label_finish_kernel<<<1, 1, 0, s>>>(L.t, L.status, L.partial, scan_num_tiles(n), edge_capacity,
                                       total, kept_out);
   return check_hip(hipGetLastError(), "tc_count_labelled launch") == TC_OK ? ok() : TC_ERR_HIP;
+}
+
+extern "C" tc_status tc_count_edge_labelled(const tc_csr* dag, int64_t edge_capacity,
+                                            const uint8_t* edge_labels, int32_t q01, int32_t q02,
+                                            int32_t q12, uint64_t* total, int64_t* kept_out,
+                                            const tc_tune* tune, void* ws, size_t* ws_bytes,
+                                            void* stream) {
+  using namespace tc;
+  tc_status st = check_labelled(dag, edge_capacity);
+  if (st != TC_OK) return st;
+  const int64_t n = dag->n;
+  int32_t x[3] = {q01, q02, q12};
+  // a triangle's three edges are permuted by the permutations of its nodes, so the
+  // query is its multiset of edge labels
+  std::sort(x, x + 3);
+  // the coded count's workspace (also validates the labels and the tune)
+  size_t count_bytes = 0;
+  tc_csr probe{n, dag->offset_bytes, nullptr, nullptr};
+  st = count_coded_edge_labels(&probe, nullptr, x, nullptr, tune, nullptr, &count_bytes, nullptr);
+  if (st != TC_OK) return st;
+  const LabelLayout need =
+      carve_label(nullptr, n, edge_capacity, dag->offset_bytes, count_bytes, true);
+  if (workspace_query(ws, ws_bytes, need.bytes, &st)) return st;
+  if (!dag->row_ptr || !total || (edge_capacity > 0 && !edge_labels))
+    return fail(TC_ERR_INVALID_ARG, "null device pointer");
+  const LabelLayout L = carve_label(ws, n, edge_capacity, dag->offset_bytes, count_bytes, true);
+  const Query q{x[0], x[1], x[2]};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool w4 = dag->offset_bytes == 4;
+  if (w4)
+    label_status_kernel<int32_t><<<1, 1, 0, s>>>(static_cast<const int32_t*>(dag->row_ptr), n,
+                                                 edge_capacity, L.status, L.t);
+  else
+    label_status_kernel<int64_t><<<1, 1, 0, s>>>(static_cast<const int64_t*>(dag->row_ptr), n,
+                                                 edge_capacity, L.status, L.t);
+  // the edges whose label is one of the query's, then the coded count of those
+  st = w4 ? run_filter<int32_t, true>(dag, nullptr, edge_labels, q, edge_capacity, L, L.partial, s)
+          : run_filter<int64_t, true>(dag, nullptr, edge_labels, q, edge_capacity, L, L.partial, s);
+  if (st != TC_OK) return st;
+  tc_csr f{n, dag->offset_bytes, L.frp, L.fcol};
+  size_t bytes = L.cws_bytes;
+  st = count_coded_edge_labels(&f, L.flab, x, &L.t[0], tune, L.cws, &bytes, s);
+  if (st != TC_OK) return st;
+  label_finish_kernel<<<1, 1, 0, s>>>(L.t, L.status, L.partial, scan_num_tiles(n), edge_capacity,
+                                      total, kept_out);
+  return check_hip(hipGetLastError(), "tc_count_edge_labelled launch") == TC_OK ? ok() : TC_ERR_HIP;
 }

@@ -44,6 +44,13 @@ class Carver {
 // Returns true when the caller only asked for the size (already written).
 bool workspace_query(void* ws, size_t* ws_bytes, size_t need, tc_status* status);
 
+// The count kernel's coded launch for a triangle query with edge labels q (each
+// 0..3): every closed wedge adds the query's matches on its triangle, by the
+// labels of its three edges (count.hip); workspace protocol as tc_count's.
+tc_status count_coded_edge_labels(const tc_csr* dag, const uint8_t* edge_labels, const int32_t q[3],
+                                  uint64_t* total, const tc_tune* tune, void* ws,
+                                  size_t* ws_bytes, void* stream);
+
 inline int grid_for(int64_t work, int block, int cap) {
   int64_t g = (work + block - 1) / block;
   if (g < 1) g = 1;

@@ -63,6 +63,8 @@ class Pipeline:
         self.edge_label = None
         self.edge_label_m = torch.zeros(1, dtype=torch.int64, device=dev)
         self.edge_labelled_total = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.edge_labelled_kept = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws_edge_labelled = None
         self.direction_m = torch.zeros(1, dtype=torch.int64, device=dev)
         self.directed_total = torch.zeros(1, dtype=torch.int64, device=dev)
         self.labelled_total = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -195,9 +197,12 @@ class Pipeline:
         tune = self.tune if tune is None else tune
         if self.edge_label is None:
             raise RuntimeError("edge_labels() must run first")
+        if self.ws_edge_labelled is None:
+            self.ws_edge_labelled = _bytes(_lib.tc_count_edge_labelled_workspace(
+                self.n, self.dag_col.numel(), self.dag_ptr.element_size()), self.device)
         _lib.tc_count_edge_labelled(self.n, self.dag_ptr, self.dag_col, self.edge_label, query,
-                                    self.edge_labelled_total, self.ws_count, tune=tune,
-                                    stream=stream)
+                                    self.edge_labelled_total, self.ws_edge_labelled,
+                                    kept_out=self.edge_labelled_kept, tune=tune, stream=stream)
 
     def edge_labelled_count(self) -> int:
         """Synchronise and read the result of edge_labelled() (raises when the labels
@@ -206,6 +211,9 @@ class Pipeline:
         em = int(self.edge_label_m.item())
         if em < 0:
             raise TcError(-em, "reported by tc_edge_labels on the device")
+        kept = int(self.edge_labelled_kept.item())
+        if kept < 0:
+            raise TcError(-kept, "reported by tc_count_edge_labelled on the device")
         return int(self.edge_labelled_total.item()) & ((1 << 64) - 1)
 
     def directed_count(self) -> int:

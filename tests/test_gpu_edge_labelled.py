@@ -1,7 +1,7 @@
 """GPU parity of the triangle query with edge labels (tc_edge_labels records each DAG edge's
-label from the labelled input pairs; tc_count_edge_labelled counts the triangles whose edge
-labels match the query's, in the count kernel with the labels as per-edge codes) against
-the oracle.
+label from the labelled input pairs; tc_count_edge_labelled keeps the edges whose label is in
+the query and counts the triangles whose edge labels match the query's, in the count kernel
+with the labels as per-edge codes) against the oracle.
 
 Counts are integers, so the bar is equality.  The per-edge labels are compared with their
 definition (the largest label of an edge's pairs), written out here from the pairs.  At scale
@@ -71,15 +71,17 @@ def _check(tc, n, s, d, lab, queries, *, order=0, offset_bytes=4, labels=True, t
     p = _pipe(tc, n, s, d, lab, order=order, offset_bytes=offset_bytes)
     rp, col = oracle.clean(n, np.asarray(s), np.asarray(d))
     dp, dc = oracle.orient(rp, col, order)
+    want_lab = _want_labels(dp, dc, s, d, lab)
     if labels:
         torch.cuda.synchronize()
         assert int(p.edge_label_m.item()) == dc.size
-        np.testing.assert_array_equal(p.edge_label[: dc.size].cpu().numpy(),
-                                      _want_labels(dp, dc, s, d, lab))
+        np.testing.assert_array_equal(p.edge_label[: dc.size].cpu().numpy(), want_lab)
     for q in queries:
         p.edge_labelled(q, tune=tune)
         assert p.edge_labelled_count() == oracle.count_edge_labelled(dp, dc, s, d, lab, q), \
             (q, order, offset_bytes)
+        # the filter keeps the edges whose label is one of the query's
+        assert int(p.edge_labelled_kept.item()) == int(np.isin(want_lab, q).sum()), q
     return p
 
 
