@@ -168,3 +168,25 @@ def test_edge_labelled_rmat_scale20_full(tc):
     assert p.edge_labelled_count() == T
     p.edge_labelled((2, 2, 1))
     assert p.edge_labelled_count() == 0
+
+
+def test_edge_labelled_degenerate(tc):
+    from paper_1909_02127_amd import _lib
+    for n, s, d in [(0, [], []), (1, [], []), (3, [0, 0], [0, 0]), (4, [0, 1], [1, 2]),
+                    (3, [0, 1, 0], [1, 2, 2])]:
+        lab = np.arange(len(s)) % 4
+        _check(tc, n, np.array(s, np.int32), np.array(d, np.int32), lab,
+               [(0, 0, 0), (0, 1, 2), (3, 3, 3)])
+    # a column capacity below m is reported on the device, and nothing is counted
+    n, s, d = pins.complete(6)  # 15 edges
+    p = _pipe(tc, n, s, d, np.zeros(len(s), np.int64))
+    ws = torch.empty(_lib.tc_count_edge_labelled_workspace(n, 14), dtype=torch.uint8,
+                     device="cuda")
+    total = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    kept = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _lib.tc_count_edge_labelled(n, p.dag_ptr, p.dag_col[:14], p.edge_label, (0, 0, 0), total, ws,
+                                kept_out=kept)
+    torch.cuda.synchronize()
+    assert int(kept.item()) == -_lib.TC_ERR_CAPACITY and int(total.item()) == 0
+    p.edge_labelled((0, 0, 0))
+    assert p.edge_labelled_count() == comb(6, 3)
