@@ -494,9 +494,11 @@ __device__ __forceinline__ int32_t probe_code(const Table& t, const Slice& sl, i
 
 // The matches of a directed query on the triangle u -> v -> w: the table entry
 // of its three direction codes, 16 c(u, v) + 4 c(u, w) + c(v, w); 0 on a miss.
+// The code of (v, w) is loaded beside w itself (the same position of the column
+// array), so no hit waits for a load after its probe.
 __device__ __forceinline__ uint32_t directed_hits(const ListCtx& lc, uint32_t cuv16, int32_t cuw,
-                                                  int64_t vw_edge) {
-  return cuw >= 0 ? lc.tab[cuv16 + 4u * (uint32_t)cuw + lc.dir[vw_edge]] : 0u;
+                                                  uint32_t cvw) {
+  return cuw >= 0 ? lc.tab[cuv16 + 4u * (uint32_t)cuw + cvw] : 0u;
 }
 
 // The wave's hits among the wedges u -> v -> w[lane], with the per-hit work of
@@ -531,13 +533,16 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
   for (; base + kUnroll * kWave <= len; base += kUnroll * kWave) {
     const int32_t* p = lst + base + lane;
     int32_t w[kUnroll];
+    uint32_t cw[kUnroll];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) w[k] = p[k * kWave];
+    for (int k = 0; k < kUnroll; ++k) {
+      w[k] = p[k * kWave];
+      cw[k] = K == kKindDirected ? (uint32_t)lc.dir[jb + base + k * kWave + lane] : 0u;
+    }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       if (K == kKindDirected) {
-        hv += directed_hits(lc, cuv16, probe_code<Mode, Wide>(t, sl, w[k], lc),
-                            jb + base + k * kWave + lane);
+        hv += directed_hits(lc, cuv16, probe_code<Mode, Wide>(t, sl, w[k], lc), cw[k]);
         continue;
       }
       const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
@@ -550,18 +555,19 @@ __device__ __forceinline__ uint32_t scan_list(const int32_t* __restrict__ lst, i
   if (base < len) {
     const uint32_t last = (uint32_t)(len - 1);
     int32_t w[kUnroll];
+    uint32_t cw[kUnroll];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const uint32_t i = (uint32_t)(base + k * kWave + lane);
       const int32_t x = list_at(lst, i < last ? i : last);
       w[k] = i <= last ? x : kNoKey;
+      cw[k] = K == kKindDirected ? (uint32_t)lc.dir[jb + (i < last ? i : last)] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       if (base + k * kWave < len) {
         if (K == kKindDirected) {
-          hv += directed_hits(lc, cuv16, probe_code<Mode, Wide>(t, sl, w[k], lc),
-                              jb + base + k * kWave + lane);
+          hv += directed_hits(lc, cuv16, probe_code<Mode, Wide>(t, sl, w[k], lc), cw[k]);
           continue;
         }
         const uint64_t b = probe_mask<K, Mode, Wide>(t, sl, w[k], lc);
@@ -656,7 +662,7 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
     wave_sync();
     if (marks) ws.mark[start - base] = -1;
     int32_t w[kWin], mid[kWin];
-    uint32_t c16[kWin];
+    uint32_t c16[kWin], cvw[kWin];
     OffT at[kWin];  // column index; int32 offsets keep the address arithmetic 32-bit
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
@@ -671,13 +677,13 @@ __device__ __forceinline__ uint32_t scan_short(int32_t v, OffT vb, int32_t len,
         w[k] = pos < total ? list_at(col, (uint32_t)at[k]) : kNoKey;
       else
         w[k] = pos < total ? col[at[k]] : kNoKey;
+      cvw[k] = K == kKindDirected && pos < total ? (uint32_t)lc.dir[at[k]] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       if (base + k * kWave < total) {
         if (K == kKindDirected) {
-          hv += directed_hits(lc, c16[k], probe_code<Mode, Wide>(t, sl, w[k], lc),
-                              (int64_t)at[k]);
+          hv += directed_hits(lc, c16[k], probe_code<Mode, Wide>(t, sl, w[k], lc), cvw[k]);
           continue;
         }
         // a hit adds to its segment's counter inside the probe (counted kinds)
