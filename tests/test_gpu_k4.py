@@ -98,6 +98,25 @@ def test_k4_long_out_lists(tc):
         _check(tc, n, s, d, order)
 
 
+def test_k4_split_sources(tc):
+    """The kernel splits a source whose wedge work (the sum of d+(v) over its middles with
+    d+(v) >= 2) passes 16384 over several workgroups, as tasks of one part of its middles
+    each, in an array of n / 4 + 4096 entries; sources whose tasks do not fit stay whole.
+    K_800 and K_1000 in degree order split several hundred sources into more tasks than
+    that array holds (5447 against 4296 for K_800), so split and whole heavy sources share
+    a launch, with N+(u) hashed (d+ <= 816) or sorted (K_1000's first sources).  R-MAT
+    scale 15 in id order splits 869 sources into 2654 tasks, all of which fit."""
+    from math import comb
+    for n in (800, 1000):
+        _, s, d = pins.complete(n)
+        _say("k4 split K", n)
+        for order, ob in ((0, 4), (1, 8)):
+            assert _gpu_k4(tc, n, s, d, order, ob) == comb(n, 4), (n, order)
+    s, d, n = graphgen.rmat(15, 16, 3)
+    _say("k4 split rmat 15")
+    _check(tc, n, s.numpy(), d.numpy(), 1, 8)
+
+
 def test_k4_empty_and_small(tc):
     for n, s, d in [(0, [], []), (1, [], []), (3, [0, 1, 2], [1, 2, 0]), (4, [0, 0, 0, 1, 1, 2],
                                                                          [1, 2, 3, 2, 3, 3])]:
