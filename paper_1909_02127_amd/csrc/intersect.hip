@@ -271,7 +271,8 @@ tc_status intersect_impl(int64_t n, const OffT* rp, const int32_t* col, int64_t 
   if (e != hipSuccess) return check_hip(e, "segmented intersection scan");
   intersect_finish_scan_kernel<<<1, 1, 0, s>>>(L.partial, scan_num_tiles(cap), cap, L.P);
   if (sup) clear_u32_kernel<<<grid_for(cap, 256, 8192), 256, 0, s>>>(sup, m_out);
-  // 4 workgroups per CU (the launch bound), the most the LDS staging allows
+  // 4 workgroups per CU (the launch bound): about 105 VGPRs per lane; bounds of 5 and 6
+  // fit the LDS staging too but spill registers and were slower
   const int grid = 4 * device_cu_count();
   const bool narrow = cap < (int64_t(1) << 30);
   if (sup && narrow)
