@@ -591,9 +591,9 @@ tc_status tc_count_bfs(const tc_csr* dag, const uint8_t* keep, int64_t frontier_
  *
  *   dag      oriented CSR (as written by tc_orient, either order)
  *   total    device uint64[1] (written)
- *   ws, ws_bytes  workspace: about 3 n + 33 KB bytes (a byte per vertex marking
+ *   ws, ws_bytes  workspace: about 5 n + 33 KB bytes (a byte per vertex marking
  *            the sources whose middles are split over several workgroups, and
- *            8-byte entries listing their parts, n / 4 + 4096 of them).
+ *            8-byte entries listing their parts, n / 2 + 4096 of them).
  */
 tc_status tc_count_k4(const tc_csr* dag, uint64_t* total, void* ws, size_t* ws_bytes,
                       void* stream);

@@ -35,7 +35,7 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLdsKeys = 2048;           // N+(u) ids held in LDS
 constexpr int kListCap = 1024;           // kept w per chunk in the in-memory path
-constexpr int kGrab = 8;                 // sources per claim from the global cursor
+constexpr int kGrab = 4;                 // sources per claim from the global cursor
 constexpr int32_t kWalkMax = 1 << 24;    // longest N+(w) walked in a concatenation of 64
 constexpr int kHashKeys = 816;           // d+(u) up to which N+(u) goes into an LDS cuckoo table
 constexpr int kMaxKicks = 48;
@@ -50,7 +50,7 @@ __host__ __device__ constexpr int k4_side_log2(int keys) {
 }
 static_assert(2 * (1 << k4_side_log2(kHashKeys)) <= kLdsKeys, "the table fits the key array");
 
-constexpr int64_t kPartWork = 16384;     // wedges sum_v d+(v) per part of a split source
+constexpr int64_t kPartWork = 8192;      // wedges sum_v d+(v) per part of a split source
 constexpr int kMaxParts = 64;
 static_assert(kMaxParts <= kWave && kMaxParts < 65536, "one lane writes each part's task");
 
@@ -69,7 +69,7 @@ struct K4Task {
 };
 
 // Task entries of the workspace for n sources.
-__host__ __device__ constexpr int64_t k4_task_cap(int64_t n) { return n / 4 + 4096; }
+__host__ __device__ constexpr int64_t k4_task_cap(int64_t n) { return n / 2 + 4096; }
 
 __global__ void k4_init_kernel(K4State* st, uint64_t* total) {
   st->cursor = 0;
@@ -80,9 +80,12 @@ __global__ void k4_init_kernel(K4State* st, uint64_t* total) {
 
 // One wave per source: w = sum of d+(v) over N+(u) with d+(v) >= 2 (the N+(v)
 // that the 4-clique walk streams); a source with d+(u) >= 3 and w > kPartWork
-// reserves ceil(w / kPartWork) tasks (at most kMaxParts, at most one per group
-// of four middles) and is marked in split[] so the run cursor skips it.  A
-// reservation that does not fit the task array leaves the source unsplit.
+// gets ceil(w / kPartWork) tasks (at most kMaxParts, at most one per group of
+// four middles) and is marked in split[] so the run cursor skips it.  A wave
+// holds up to 64 such sources (lane j the j-th) and reserves their tasks with
+// one atomic add, in lane order: one counter shared by every heavy source
+// would serialise its atomics.  A source whose tasks do not fit the array
+// stays whole and blanks the entries of its reservation below the capacity.
 template <typename OffT>
 __global__ __launch_bounds__(256) void k4_split_kernel(int64_t n, const OffT* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
@@ -92,35 +95,58 @@ __global__ __launch_bounds__(256) void k4_split_kernel(int64_t n, const OffT* __
   const int lane = lane_id();
   const int64_t per_block = blockDim.x / kWave;
   const int64_t waves = (int64_t)gridDim.x * per_block;
-  for (int64_t u = (int64_t)blockIdx.x * per_block + threadIdx.x / kWave; u < n; u += waves) {
-    const int64_t ub = row_ptr[u];
-    const int64_t du = (int64_t)row_ptr[u + 1] - ub;
-    int64_t w = 0;
-    if (du >= 3) {
-      for (int64_t j = lane; j < du; j += kWave) {
-        const int32_t v = col[ub + j];
-        const int64_t dv = (int64_t)row_ptr[v + 1] - (int64_t)row_ptr[v];
-        w += dv >= 2 ? dv : 0;
+  int64_t held_u = 0;  // lane j < held: the j-th held source and its parts
+  int32_t held_p = 0;
+  int held = 0;        // uniform
+  for (int64_t u = (int64_t)blockIdx.x * per_block + threadIdx.x / kWave;; u += waves) {
+    const bool more = u < n;
+    if (more) {
+      const int64_t ub = row_ptr[u];
+      const int64_t du = (int64_t)row_ptr[u + 1] - ub;
+      int64_t w = 0;
+      if (du >= 3) {
+        for (int64_t j = lane; j < du; j += kWave) {
+          const int32_t v = col[ub + j];
+          const int64_t dv = (int64_t)row_ptr[v + 1] - (int64_t)row_ptr[v];
+          w += dv >= 2 ? dv : 0;
+        }
+      }
+      w = wave_sum(w);
+      int64_t parts = (w + kPartWork - 1) / kPartWork;
+      const int64_t groups = (du + kWavesPerBlock - 1) / kWavesPerBlock;
+      parts = parts < kMaxParts ? parts : kMaxParts;
+      parts = parts < groups ? parts : groups;
+      if (du >= 3 && parts > 1) {
+        if (lane == held) {
+          held_u = u;
+          held_p = (int32_t)parts;
+        }
+        ++held;
+      } else if (lane == 0) {
+        split[u] = 0;
       }
     }
-    w = wave_sum(w);
-    int64_t parts = (w + kPartWork - 1) / kPartWork;
-    const int64_t groups = (du + kWavesPerBlock - 1) / kWavesPerBlock;
-    parts = parts < kMaxParts ? parts : kMaxParts;
-    parts = parts < groups ? parts : groups;
-    uint8_t mark = 0;
-    if (du >= 3 && parts > 1) {
-      uint64_t at = 0;
-      if (lane == 0) at = atomicAdd((unsigned long long*)&st->tasks, (unsigned long long)parts);
-      at = (uint64_t)read_lane64((int64_t)at, 0);
-      if (at + (uint64_t)parts <= (uint64_t)cap) {
-        if (lane < parts) tasks[at + lane] = K4Task{(int32_t)u, (uint16_t)lane, (uint16_t)parts};
-        mark = 1;
-      } else if (at + lane < (uint64_t)cap && lane < parts) {
-        tasks[at + lane].u = -1;
+    if (held == kWave || (!more && held > 0)) {
+      const int32_t incl = wave_inclusive_sum32(held_p);
+      const int32_t sum = read_lane(incl, kWave - 1);
+      uint64_t base = 0;
+      if (lane == 0) base = atomicAdd((unsigned long long*)&st->tasks, (unsigned long long)sum);
+      base = (uint64_t)read_lane64((int64_t)base, 0);
+      if (lane < held) {
+        const uint64_t at = base + (uint64_t)(incl - held_p);
+        const bool fits = at + (uint64_t)held_p <= (uint64_t)cap;
+        for (int32_t k = 0; k < held_p; ++k) {
+          if (fits)
+            tasks[at + k] = K4Task{(int32_t)held_u, (uint16_t)k, (uint16_t)held_p};
+          else if (at + k < (uint64_t)cap)
+            tasks[at + k].u = -1;
+        }
+        split[held_u] = fits ? 1 : 0;
       }
+      held = 0;
+      held_p = 0;
     }
-    if (lane == 0) split[u] = mark;
+    if (!more) break;
   }
 }
 

@@ -100,12 +100,12 @@ def test_k4_long_out_lists(tc):
 
 def test_k4_split_sources(tc):
     """The kernel splits a source whose wedge work (the sum of d+(v) over its middles with
-    d+(v) >= 2) passes 16384 over several workgroups, as tasks of one part of its middles
-    each, in an array of n / 4 + 4096 entries; sources whose tasks do not fit stay whole.
+    d+(v) >= 2) passes 8192 over several workgroups, as tasks of one part of its middles
+    each, in an array of n / 2 + 4096 entries; sources whose tasks do not fit stay whole.
     K_800 and K_1000 in degree order split several hundred sources into more tasks than
-    that array holds (5447 against 4296 for K_800), so split and whole heavy sources share
+    that array holds (10674 against 4496 for K_800), so split and whole heavy sources share
     a launch, with N+(u) hashed (d+ <= 816) or sorted (K_1000's first sources).  R-MAT
-    scale 15 in id order splits 869 sources into 2654 tasks, all of which fit."""
+    scale 15 in id order splits 1805 sources into 6642 tasks, all of which fit."""
     from math import comb
     for n in (800, 1000):
         _, s, d = pins.complete(n)

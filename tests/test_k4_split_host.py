@@ -1,11 +1,12 @@
 """CPU emulation of how the 4-clique kernel (clique4.hip, tc_count_k4) splits heavy sources.
 
 A pre-pass gives each source u with d+(u) >= 3 its wedge work w(u), the sum of d+(v) over its
-middles with d+(v) >= 2, and, when w(u) > 16384, ceil(w / 16384) parts (at most 64, and at most
-one per group of four middles).  The source reserves that many entries of a task array of
-n / 4 + 4096 with one atomic add; if they all fit it writes one task (u, part, parts) per entry
-and is marked as split, otherwise it blanks the entries of its reservation that lie below the
-capacity and stays whole.  Workgroups take the first min(reserved, capacity) entries, skipping
+middles with d+(v) >= 2, and, when w(u) > 8192, ceil(w / 8192) parts (at most 64, and at most
+one per group of four middles).  Each source gets a contiguous range of a task array of
+n / 2 + 4096 entries (a wave reserves the ranges of up to 64 such sources with one atomic add,
+in lane order, which is one of the orders emulated here); if the range fits the source writes one
+task (u, part, parts) per entry and is marked as split, otherwise it blanks the entries of its
+range that lie below the capacity and stays whole.  Workgroups take the first min(reserved, capacity) entries, skipping
 blanks, then every unmarked source whole; part k of P takes the middles iv whose group iv // 4
 is k mod P (four waves, one middle each per group).
 
@@ -17,7 +18,7 @@ that the part counts follow the rule.
 import numpy as np
 import pytest
 
-PART_WORK = 16384
+PART_WORK = 8192
 MAX_PARTS = 64
 WAVES = 4
 
@@ -85,7 +86,7 @@ def test_k4_split_covers_every_middle_once(seed):
     dplus, rp, col = random_lists(rng, n)
     for cap_name in ("fits", "overflows"):
         order = rng.permutation(n)
-        full = n // 4 + 4096
+        full = n // 2 + 4096
         parts_all = None
         for cap in ((full,) if cap_name == "fits" else (5, 97, 300)):
             parts, split, taken, reserved = emulate(dplus, rp, col, cap, order)
