@@ -13,15 +13,16 @@
 // up to kMaxParts parts (part k takes every parts-th group of four middles),
 // listed as tasks and taken one per claim before the other sources: a heavy
 // source's middles then run on several workgroups instead of setting the
-// launch's tail on one.  For
-// each (u, v) a wave streams N+(v), finds each w in N+(u) and keeps it in a
-// per-wave list (S = the kept w); then it walks the N+(w) of 64 kept w at a time
-// as one concatenation (one round trip for their row bounds) and counts the x
-// that are in S.  With the table, S is also a per-wave bit beside each slot, so
-// x is tested by its table probe and that bit; with the sorted copy, by binary
-// search in S.  Longer sources keep N+(u) in memory: w and
-// x are then tested by binary search in the sorted rows of u and v, and the
-// kept w go through a bounded list in chunks.
+// launch's tail on one.
+//
+// For each (u, v) a wave streams N+(v), finds each w in N+(u) and keeps it in
+// a per-wave list (S = the kept w); then it walks the N+(w) of 64 kept w at a
+// time as one concatenation (one round trip for their row bounds) and counts
+// the x that are in S.  With the table, S is also a per-wave bit beside each
+// slot, so x is tested by its table probe and that bit; with the sorted copy,
+// by binary search in S.  Longer sources keep N+(u) in memory: w and x are
+// then tested by binary search in the sorted rows of u and v, and the kept w
+// go through a bounded list in chunks.
 #include "tc_device.h"
 #include "tc_hash.h"
 #include "tc_host.h"
@@ -52,7 +53,7 @@ static_assert(2 * (1 << k4_side_log2(kHashKeys)) <= kLdsKeys, "the table fits th
 
 constexpr int64_t kPartWork = 8192;      // wedges sum_v d+(v) per part of a split source
 constexpr int kMaxParts = 64;
-static_assert(kMaxParts <= kWave && kMaxParts < 65536, "one lane writes each part's task");
+static_assert(kMaxParts < 65536, "part numbers fit the 16-bit task fields");
 
 struct K4State {
   int32_t cursor;        // runs of kGrab sources (the unsplit ones)
