@@ -60,11 +60,15 @@ __global__ __launch_bounds__(256) void dir_arcs_kernel(const OffT* __restrict__ 
       continue;
     }
     if (a == b) continue;
-    int64_t pos = row_find(col, (int64_t)rp[a], (int64_t)rp[a + 1], b);
-    uint32_t bit = 1u;
+    // the shorter row first: degree orders put an edge in its lower-degree end's row
+    const int64_t ab = (int64_t)rp[a], ae = (int64_t)rp[a + 1];
+    const int64_t bb = (int64_t)rp[b], be = (int64_t)rp[b + 1];
+    const bool a_first = ae - ab <= be - bb;
+    int64_t pos = a_first ? row_find(col, ab, ae, b) : row_find(col, bb, be, a);
+    uint32_t bit = a_first ? 1u : 2u;
     if (pos < 0) {
-      pos = row_find(col, (int64_t)rp[b], (int64_t)rp[b + 1], a);
-      bit = 2u;
+      pos = a_first ? row_find(col, bb, be, a) : row_find(col, ab, ae, b);
+      bit ^= 3u;
     }
     if (pos < 0) {
       *m_out = -(int64_t)TC_ERR_INVALID_ARG;  // not an edge of this DAG
@@ -116,8 +120,12 @@ __global__ __launch_bounds__(256) void edge_label_kernel(const OffT* __restrict_
       *m_out = -(int64_t)TC_ERR_INVALID_ARG;
       continue;
     }
-    int64_t pos = row_find(col, (int64_t)rp[a], (int64_t)rp[a + 1], b);
-    if (pos < 0) pos = row_find(col, (int64_t)rp[b], (int64_t)rp[b + 1], a);
+    // the shorter row first: degree orders put an edge in its lower-degree end's row
+    const int64_t ab = (int64_t)rp[a], ae = (int64_t)rp[a + 1];
+    const int64_t bb = (int64_t)rp[b], be = (int64_t)rp[b + 1];
+    const bool a_first = ae - ab <= be - bb;
+    int64_t pos = a_first ? row_find(col, ab, ae, b) : row_find(col, bb, be, a);
+    if (pos < 0) pos = a_first ? row_find(col, bb, be, a) : row_find(col, ab, ae, b);
     if (pos < 0) {
       *m_out = -(int64_t)TC_ERR_INVALID_ARG;  // not an edge of this DAG
       continue;
